@@ -1,0 +1,83 @@
+"""Closed-form spectra of the synthetic pencils.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+The pencils are Kronecker sums / tensor products of 1D three-point operators,
+so every eigenpair is a sum (or product) of 1D eigenpairs with sine modes.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def dirichlet_1d(N: int) -> np.ndarray:
+    """Eigenvalues of tridiag(-1, 2, -1), N x N: 4 sin^2(i pi / (2(N+1))), i = 1..N."""
+    i = np.arange(1, N + 1)
+    return 4.0 * np.sin(i * np.pi / (2.0 * (N + 1))) ** 2
+
+
+def periodic_1d(N: int) -> np.ndarray:
+    """Eigenvalues of the periodic three-point Laplacian: 4 sin^2(pi i / N), i = 0..N-1."""
+    i = np.arange(N)
+    return 4.0 * np.sin(np.pi * i / N) ** 2
+
+
+def sine_mode(N: int, i: int) -> np.ndarray:
+    """Unit-norm eigenvector sin(i j pi/(N+1)), j = 1..N, of the 1D Dirichlet operator."""
+    j = np.arange(1, N + 1)
+    v = np.sin(i * j * np.pi / (N + 1))
+    return v / np.linalg.norm(v)
+
+
+def laplacian_2d_dirichlet(N: int) -> np.ndarray:
+    s = dirichlet_1d(N)
+    return np.sort((s[:, None] + s[None, :]).ravel())
+
+
+def laplacian_3d_dirichlet(N: int) -> np.ndarray:
+    s = dirichlet_1d(N)
+    return np.sort((s[:, None, None] + s[None, :, None] + s[None, None, :]).ravel())
+
+
+def laplacian_3d_periodic(N: int) -> np.ndarray:
+    s = periodic_1d(N)
+    return np.sort((s[:, None, None] + s[None, :, None] + s[None, None, :]).ravel())
+
+
+def fem_1d(N: int) -> np.ndarray:
+    """Eigenvalues of the 1D pencil K1 = tridiag(-1,2,-1)/h, M1 = h tridiag(1,4,1)/6.
+
+    mu_i = 6 (1 - cos t_i) / (h^2 (2 + cos t_i)), t_i = i pi / (N+1), h = 1/(N+1).
+    """
+    h = 1.0 / (N + 1)
+    t = np.arange(1, N + 1) * np.pi / (N + 1)
+    return 6.0 * (1.0 - np.cos(t)) / (h * h * (2.0 + np.cos(t)))
+
+
+def fem_q1_3d(N: int) -> np.ndarray:
+    """Eigenvalues of the tensor-product Q1 pencil: mu_a + mu_b + mu_c."""
+    m = fem_1d(N)
+    return np.sort((m[:, None, None] + m[None, :, None] + m[None, None, :]).ravel())
+
+
+def smallest(values: np.ndarray, count: int) -> np.ndarray:
+    """The `count` smallest values (full sort; for grids up to 96^3 this is cheap)."""
+    return np.sort(values)[:count]
+
+
+def cluster_boundary(values: np.ndarray, k: int, rel_gap: float = 1e-9) -> int:
+    """Largest c <= k such that lambda_c and lambda_{c+1} are distinct clusters."""
+    v = np.sort(values)
+    c = k
+    while c > 0 and abs(v[c] - v[c - 1]) <= rel_gap * max(abs(v[c]), 1.0):
+        c -= 1
+    return c
+
+
+def norm2_laplacian_2d(N: int) -> float:
+    return float(2.0 * dirichlet_1d(N)[-1])
+
+
+def norm2_laplacian_3d(N: int) -> float:
+    return float(3.0 * dirichlet_1d(N)[-1])

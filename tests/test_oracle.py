@@ -1,0 +1,404 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the values
+the paper prints for its worked example, closed-form spectra, a hand-written
+Jacobi eigensolver, invariants the paper states, or brute force.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from oracle import brute, closed_forms as cf
+from oracle import lobpcg as L
+from paper_1704_07458_amd import problems as P
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *nums = line.split()
+            vals[key] = np.array([float(x) for x in nums])
+    return vals
+
+
+# ---------------------------------------------------------------- brute force
+def test_jacobi_eigensolver_matches_closed_form_1d():
+    N = 40
+    T = P.tridiag_1d(N, -1.0, 2.0, -1.0).to_scipy().toarray()
+    w, V = brute.jacobi_eigh(T)
+    assert np.allclose(w, cf.dirichlet_1d(N), rtol=0, atol=1e-13)
+    assert np.allclose(V.T @ V, np.eye(N), atol=1e-13)
+    assert np.allclose(T @ V, V * w, atol=1e-12)
+    # eigenvector of the smallest eigenvalue is the first sine mode (up to sign)
+    assert abs(abs(V[:, 0] @ cf.sine_mode(N, 1)) - 1.0) < 1e-12
+
+
+def test_closed_forms_against_brute_force():
+    # 2D Dirichlet 6x6, 3D Dirichlet 4^3, periodic 3D 4^3 and the Q1 FEM pencil 4^3.
+    A = P.laplacian_2d_dirichlet(6).to_scipy().toarray()
+    assert np.allclose(brute.jacobi_eigh(A)[0], cf.laplacian_2d_dirichlet(6), atol=1e-12)
+    A = P.laplacian_3d(4).to_scipy().toarray()
+    assert np.allclose(brute.jacobi_eigh(A)[0], cf.laplacian_3d_dirichlet(4), atol=1e-12)
+    A = P.laplacian_3d(4, periodic=True).to_scipy().toarray()
+    assert np.allclose(brute.jacobi_eigh(A)[0], cf.laplacian_3d_periodic(4), atol=1e-12)
+    K, M = P.fem_q1_pencil(4)
+    w, _ = brute.jacobi_eigh_pencil(K.to_scipy().toarray(), M.to_scipy().toarray())
+    assert np.allclose(w, cf.fem_q1_3d(4), rtol=1e-12)
+
+
+def test_generators_structure():
+    A = P.laplacian_3d(64)
+    assert A.n == 262144 and A.nnz == 1810432
+    A = P.laplacian_2d_dirichlet(32)
+    assert A.n == 1024 and A.nnz == 4992
+    K, M = P.fem_q1_pencil(6)
+    assert K.nnz == (3 * 6 - 2) ** 3 and M.nnz == K.nnz
+    for C in (A, K, M):
+        S = C.to_scipy()
+        assert abs(S - S.T).max() == 0
+        for r in range(C.n):
+            cols = C.colind[C.rowptr[r]:C.rowptr[r + 1]]
+            assert np.all(np.diff(cols) > 0)
+    assert P.block_size(100) == 110 and P.block_size(10) == 11 and P.block_size(1000) == 1100
+
+
+# ---------------------------------------------------------- Algorithm 2 (RR)
+def test_rayleigh_ritz_against_brute_force():
+    rng = np.random.default_rng(3)
+    n, m = 60, 9
+    A = P.random_sparse_spd(5, n, 0.1).to_scipy().toarray()
+    Bm = P.random_sparse_spd(6, n, 0.1).to_scipy().toarray()
+    S = rng.standard_normal((n, m))
+    GA, GB = S.T @ A @ S, S.T @ Bm @ S
+    C, theta = L.rayleigh_ritz(GA, GB)
+    assert np.allclose(C.T @ GB @ C, np.eye(m), atol=1e-11)
+    assert np.allclose(C.T @ GA @ C, np.diag(theta), atol=1e-10 * np.abs(theta).max())
+    w, _ = brute.jacobi_eigh_pencil(GA, GB)
+    assert np.allclose(theta, w, rtol=1e-11)
+
+
+# --------------------------------------------------- Algorithms 4 and 6 (SVQB)
+def test_svqb_contracts():
+    rng = np.random.default_rng(0)
+    n, m = 80, 7
+    Bm = P.random_sparse_spd(1, n, 0.05)
+    Mop = L.Operator(Bm.to_scipy())
+    U = rng.standard_normal((n, m)) @ np.diag(10.0 ** np.arange(m))
+    Uo = L.svqb(Mop, U, 1e-14)
+    assert Uo.shape == (n, m)
+    assert np.allclose(Uo.T @ Mop(Uo), np.eye(m), atol=1e-10)
+    # span(U_out) contains span(U_in): projecting U_in on span(U_out) leaves nothing
+    Q = sla.orth(Uo)
+    assert np.linalg.norm(U - Q @ (Q.T @ U)) <= 1e-10 * np.linalg.norm(U)
+
+
+def test_svqb_drop_truncates_rank_deficient_basis():
+    rng = np.random.default_rng(1)
+    n = 50
+    base = rng.standard_normal((n, 4))
+    U = np.hstack([base, base @ rng.standard_normal((4, 3))])  # rank 4, 7 columns
+    Mop = L.Operator(None)
+    tol = L.Tolerances()
+    Uo = L.svqb_drop(Mop, U, tol.tau_drop(U.shape[1]))
+    assert Uo.shape[1] == 4
+    assert np.allclose(Uo.T @ Uo, np.eye(4), atol=1e-12)
+    Q = sla.orth(Uo)
+    assert np.linalg.norm(U - Q @ (Q.T @ U)) <= 1e-11 * np.linalg.norm(U)
+
+
+def test_ortho_drop_against_external_basis():
+    rng = np.random.default_rng(2)
+    n = 100
+    Bm = P.random_sparse_spd(2, n, 0.05).to_scipy()
+    Mop = L.Operator(Bm)
+    V = L.svqb(Mop, rng.standard_normal((n, 6)), 1e-15)
+    MV = Mop(V)
+    # candidate with components inside span(V) and two columns that depend on
+    # the other five once span(V) is removed
+    U = rng.standard_normal((n, 5)) + V @ rng.standard_normal((6, 5))
+    U = np.hstack([U, U @ rng.standard_normal((5, 2)) + V[:, :2] @ rng.standard_normal((2, 2))])
+    Uo = L.ortho_drop(Mop, U, V, MV, L.Tolerances())
+    # Algorithm 5's output contract: n_out <= n_in, M-orthonormal, M-orthogonal to V.
+    # (Its first inner pass is svqb with flooring, which turns the two dependent
+    # directions into rounding noise that later passes may keep as new directions.)
+    m = Uo.shape[1]
+    assert 5 <= m <= 7
+    assert np.allclose(Uo.T @ Mop(Uo), np.eye(m), atol=1e-11)
+    assert np.linalg.norm(V.T @ Mop(Uo)) < 1e-11
+    # span([U_out, V]) contains span([U_in, V])
+    Q = sla.orth(np.hstack([Uo, V]))
+    assert np.linalg.norm(U - Q @ (Q.T @ U)) <= 1e-9 * np.linalg.norm(U)
+
+
+# ------------------------------------------------- section 4.1 worked example
+def _e1_setup(n=8):
+    A = P.tridiag_1d(n, 1.0, 3.0, 1.0).to_scipy()
+    X0 = np.zeros((n, 2))
+    X0[0] = [1.0, 1.0]
+    X0[1] = [-1.0, 1.0]
+    return A, X0 / np.sqrt(2.0)
+
+
+def test_e1_values_printed_in_paper():
+    g = _read_golden("e1_spurious_ritz.txt")
+    A, X0 = _e1_setup()
+    theta0 = np.diag(X0.T @ (A @ X0))
+    assert np.allclose(theta0, g["theta0"], atol=1e-15)
+    assert abs((X0.T @ (A @ X0))[0, 1]) < 1e-15
+    W0 = A @ X0 - X0 * theta0
+    assert np.allclose(W0[:3, 0], g["w0_col1"], atol=1e-15)
+    assert np.allclose(W0[:3, 1], g["w0_col2"], atol=1e-15)
+    assert np.all(W0[3:] == 0)
+
+
+def test_e1_ortho_drop_removes_spurious_ritz_value():
+    g = _read_golden("e1_spurious_ritz.txt")
+    A, X0 = _e1_setup()
+    Mop = L.Operator(None)
+    theta0 = np.diag(X0.T @ (A @ X0))
+    W0 = A @ X0 - X0 * theta0
+    W = L.ortho_drop(Mop, W0, X0, X0, L.Tolerances())
+    assert W.shape[1] == 1  # one column survives, +-e3
+    assert abs(abs(W[2, 0]) - 1.0) < 1e-14
+    S = np.hstack([X0, W])
+    GA, GB = S.T @ (A @ S), S.T @ S
+    rr = L.rayleigh_ritz_modified(GA, GB, 2, 0, True, L.Tolerances())
+    assert np.allclose(rr.theta_all, g["rr_values"], atol=1e-14)
+    assert rr.theta_all.min() > 1.0  # A is SPD with smallest eigenvalue > 1
+
+
+def test_e1_svqb_without_dropping_shows_spurious_value():
+    """Negative control: the straightforward svqb keeps both columns."""
+    g = _read_golden("e1_spurious_ritz.txt")
+    A, X0 = _e1_setup()
+    Mop = L.Operator(None)
+    theta0 = np.diag(X0.T @ (A @ X0))
+    W0 = A @ X0 - X0 * theta0
+    U = L.svqb(Mop, W0 - X0 @ (X0.T @ W0), L.Tolerances().tau_replace(2))
+    assert U.shape[1] == 2
+    S = np.hstack([X0, U])  # four columns spanning a 3D space
+    theta = np.linalg.eigvalsh(S.T @ (A @ S))  # assumes S^T S = I
+    assert abs(theta[0] - g["spurious_theta1"][0]) < 1e-8
+
+
+# ------------------------------------------------- Algorithm 7 / section 4.2
+def test_lq_identity_of_section_4_2():
+    """[0;Z2] - Zx Zx^T [0;Z2] = Zperp Z2perp^T Z2 = -Zperp Z1perp^T Z1."""
+    rng = np.random.default_rng(7)
+    n_s, k = 12, 4
+    Z, _ = np.linalg.qr(rng.standard_normal((n_s, n_s)))
+    Z1, Z2 = Z[:k, :k], Z[k:, :k]
+    Z1p, Z2p = Z[:k, k:], Z[k:, k:]
+    Zx, Zp = Z[:, :k], Z[:, k:]
+    E = np.vstack([np.zeros((k, k)), Z2])
+    lhs = E - Zx @ (Zx.T @ E)
+    assert np.allclose(lhs, Zp @ (Z2p.T @ Z2), atol=1e-14)
+    assert np.allclose(lhs, -Zp @ (Z1p.T @ Z1), atol=1e-14)
+
+
+def _random_projected_pencil(seed, n, n_s, B=None):
+    rng = np.random.default_rng(seed)
+    A = P.random_sparse_spd(seed, n, 0.05).to_scipy()
+    S = rng.standard_normal((n, n_s))
+    GA = S.T @ (A @ S)
+    GB = S.T @ (S if B is None else B @ S)
+    return 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+
+
+@pytest.mark.parametrize("n_c", [0, 2, 5])
+def test_rr_modified_contracts_and_hl_span(n_c):
+    n_x, n_s = 8, 22
+    Bm = P.random_sparse_spd(11, 120, 0.05).to_scipy()
+    GA, GB = _random_projected_pencil(4, 120, n_s, Bm)
+    tol = L.Tolerances(skip_factor=0.0)  # never flip here
+    rr = L.rayleigh_ritz_modified(GA, GB, n_x, n_c, False, tol)
+    C = np.hstack([rr.Cx, rr.Cp])
+    assert rr.Cp.shape[1] == n_x - n_c
+    # Algorithm 7 output contract: C^T G_B C = I and C^T G_A C = blockdiag(Theta_x, Theta_p)
+    assert np.allclose(C.T @ GB @ C, np.eye(C.shape[1]), atol=1e-9)
+    T = np.zeros((C.shape[1],) * 2)
+    T[:n_x, :n_x] = np.diag(rr.theta_x)
+    T[n_x:, n_x:] = rr.theta_p
+    assert np.allclose(C.T @ GA @ C, T, atol=1e-9 * np.abs(rr.theta_all).max())
+    # Ritz values against brute force on the pencil
+    w, _ = brute.jacobi_eigh_pencil(GA, GB)
+    assert np.allclose(rr.theta_all, w, rtol=1e-10)
+    # span(C_p) equals HL's construction (eq. 6) restricted to the active
+    # columns, written without coordinates: take the new X columns n_c:n_x,
+    # remove their G_B-projection onto the old X (the first n_x columns of S)
+    # and then onto the new X.
+    Cx = rr.Cx
+    Eold = np.zeros((n_s, n_x))
+    Eold[:n_x, :n_x] = np.eye(n_x)
+    Y = Cx[:, n_c:]
+    Y = Y - Eold @ np.linalg.solve(Eold.T @ GB @ Eold, Eold.T @ GB @ Y)
+    hl = Y - Cx @ (Cx.T @ GB @ Y)
+    Gc = sla.cholesky(GB)
+
+    def proj(Yb):
+        Q = sla.orth(Gc @ Yb)
+        return Q @ Q.T
+
+    assert np.linalg.norm(proj(hl) - proj(rr.Cp)) < 1e-8
+
+
+def test_rr_modified_literal_lq_same_span_when_nothing_converged():
+    n_x, n_s = 6, 18
+    GA, GB = _random_projected_pencil(9, 100, n_s)
+    tol = L.Tolerances(skip_factor=0.0)
+    a = L.rayleigh_ritz_modified(GA, GB, n_x, 0, False, tol)
+    b = L.rayleigh_ritz_modified(GA, GB, n_x, 0, False, tol, literal_lq=True)
+    Gc = sla.cholesky(GB)
+    Qa, Qb = sla.orth(Gc @ a.Cp), sla.orth(Gc @ b.Cp)
+    assert np.linalg.norm(Qa @ Qa.T - Qb @ Qb.T) < 1e-9
+
+
+def test_rr_modified_flips_on_ill_conditioned_basis():
+    rng = np.random.default_rng(5)
+    n = 80
+    S = rng.standard_normal((n, 6))
+    S = np.hstack([S, S[:, :2] + 1e-9 * rng.standard_normal((n, 2))])
+    A = P.random_sparse_spd(3, n, 0.1).to_scipy()
+    rr = L.rayleigh_ritz_modified(S.T @ (A @ S), S.T @ S, 3, 0, False, L.Tolerances())
+    assert rr.flipped and rr.use_ortho and rr.cond_R > 1e5
+
+
+# ---------------------------------------------------- section 4.3 criterion
+def test_sketch_is_a_lower_bound_of_the_2_norm():
+    A = P.laplacian_3d(12).to_scipy()
+    X0 = P.initial_block(0, A.shape[0], 22)
+    est = L.sketch_norm(L.Operator(A), X0)
+    assert est <= cf.norm2_laplacian_3d(12)
+    assert est >= 0.3 * cf.norm2_laplacian_3d(12)
+
+
+def test_criterion9_scale_invariance_and_criterion8_not():
+    """Scaling B -> sB leaves (9) unchanged and multiplies (8) by sqrt(s)."""
+    K, M = P.fem_q1_pencil(5)
+    A, Bm = K.to_scipy().toarray(), M.to_scipy().toarray()
+    lam, V = sla.eigh(A, Bm)
+    rng = np.random.default_rng(0)
+    x = V[:, :3] + 1e-6 * rng.standard_normal((A.shape[0], 3))
+    th = np.diag(x.T @ A @ x) / np.diag(x.T @ Bm @ x)
+    nA, nB = np.linalg.norm(A, 2), np.linalg.norm(Bm, 2)
+    for s in (1e-10, 1e3):
+        xs = x / np.sqrt(s)
+        ths = th / s
+        R = A @ x - Bm @ x * th
+        Rs = A @ xs - (s * Bm) @ xs * ths
+        c9 = L.criterion9(R, x, th, nA, nB)
+        c9s = L.criterion9(Rs, xs, ths, nA, s * nB)
+        assert np.allclose(c9, c9s, rtol=1e-9)
+        c8 = L.criterion8(R, x, Bm @ x, th)
+        c8s = L.criterion8(Rs, xs, (s * Bm) @ xs, ths)
+        assert np.allclose(c8s, np.sqrt(s) * c8, rtol=1e-9)
+
+
+# ------------------------------------------------------ Algorithm 8, end to end
+def _solve(w, **kw):
+    A = w.A.to_scipy()
+    B = None if w.B is None else w.B.to_scipy()
+    pre = L.jacobi_precond(A) if w.precond == "jacobi" else None
+    return L.lobpcg(A, w.X0, w.k, w.tol, B=B, precond=pre, **kw)
+
+
+def test_cfg0_closed_form_and_backward_error():
+    w = P.workload(0)
+    res = _solve(w)
+    assert res.converged
+    ex = cf.smallest(cf.laplacian_2d_dirichlet(32), w.k)
+    assert np.max(np.abs(res.theta[: w.k] - ex) / ex) < 1e-10
+    # criterion (9) also holds with the exact ||A||_2 (the sketch is a lower bound)
+    X, th = res.X[:, : w.k], res.theta[: w.k]
+    A = w.A.to_scipy()
+    rho = L.criterion9(A @ X - X * th, X, th, cf.norm2_laplacian_2d(32), 1.0)
+    assert np.all(rho <= w.tol)
+    assert np.allclose(X.T @ X, np.eye(w.k), atol=1e-10)
+
+
+@pytest.mark.parametrize("idx", [1, 2, 4])
+def test_small_workloads_against_dense(idx):
+    w = P.workload(idx, small=True)
+    res = _solve(w)
+    assert res.converged
+    A = w.A.to_scipy().toarray()
+    if w.B is None:
+        ex = np.linalg.eigvalsh(A)[: w.k]
+    else:
+        ex = sla.eigh(A, w.B.to_scipy().toarray(), eigvals_only=True)[: w.k]
+    assert np.max(np.abs(res.theta[: w.k] - ex) / np.abs(ex)) < 1e-10
+
+
+def test_small_fem_pencil_closed_form_and_B_orthonormality():
+    w = P.workload(2, small=True)
+    res = _solve(w)
+    ex = cf.smallest(cf.fem_q1_3d(10), w.k)
+    assert np.max(np.abs(res.theta[: w.k] - ex) / ex) < 1e-10
+    X = res.X[:, : w.k]
+    Bm = w.B.to_scipy()
+    assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
+
+
+def test_brute_force_jacobi_on_random_pencil():
+    n = 150
+    A = P.add_diagonal(P.laplacian_2d_dirichlet(10), np.zeros(100))
+    # random sparse SPD pencil of size n <= 200
+    Am = P.random_sparse_spd(21, n, 0.05, shift=-0.5).to_scipy()
+    Bm = P.random_sparse_spd(22, n, 0.03, shift=2.0).to_scipy()
+    X0 = P.initial_block(3, n, 8)
+    res = L.lobpcg(Am, X0, 6, 1e-10, B=Bm)
+    assert res.converged
+    w, _ = brute.jacobi_eigh_pencil(Am.toarray(), Bm.toarray())
+    assert np.max(np.abs(res.theta[:6] - w[:6]) / np.abs(w[:6])) < 1e-9
+    del A
+
+
+def test_gram_identities_12_to_14_hold_after_an_iteration():
+    """X^T A X = Theta, X^T B X = I, X^T A P = 0, X^T B P = 0, P^T B P = I."""
+    w = P.workload(2, small=True)
+    A, Bm = w.A.to_scipy(), w.B.to_scipy()
+    res = L.lobpcg(A, w.X0, w.k, w.tol, B=Bm, maxit=3)
+    X = res.X
+    th = res.theta
+    assert np.allclose(X.T @ (Bm @ X), np.eye(w.n_x), atol=1e-10)
+    G = X.T @ (A @ X)
+    assert np.allclose(G, np.diag(th), atol=1e-9 * np.abs(th).max())
+
+
+def test_forced_ortho_switch_still_converges():
+    """tau_skip large enough that the Cholesky path is rejected at once."""
+    w = P.workload(1, small=True)
+    tol = L.Tolerances(skip_factor=1e12)  # cond(R)^3 > 1/(1e12 eps) = 4.5e3
+    res = _solve(w, tols=tol)
+    assert res.ortho_switch_iter >= 1
+    assert res.converged
+    ex = cf.smallest(cf.laplacian_3d_dirichlet(12), w.k)
+    assert np.max(np.abs(res.theta[: w.k] - ex) / ex) < 1e-10
+    assert res.ortho_stats.svqb_calls > 0
+
+
+def test_maxit_returns_not_converged():
+    w = P.workload(0)
+    res = _solve(w, maxit=3)
+    assert not res.converged and res.iterations == 3
+
+
+def test_jacobi_diagonal_shift_makes_indefinite_diagonal_positive():
+    L3 = P.laplacian_3d(6, periodic=True)
+    V = P.potential(0, L3.n, -8.0, 8.0)
+    A = P.add_diagonal(L3, V).to_scipy()
+    d = L.jacobi_diagonal(A)
+    assert np.all(d > 0)
+    # no shift when the diagonal is already positive
+    A1 = P.laplacian_3d(6).to_scipy()
+    assert np.all(L.jacobi_diagonal(A1) == 6.0)
