@@ -1,0 +1,209 @@
+"""Benchmark: time to k eigenpairs at criterion (9) <= 1e-8 on one MI355X.
+
+Workload: 3D 7-point Dirichlet Laplacian on a 64^3 grid (n = 262,144), B = I,
+k = 100 (block n_x = 110), Jacobi preconditioner, seeded N(0,1) initial block,
+tol 1e-8.  A step is one full solve (every step of the robust LOBPCG
+iteration, repeated until the k smallest pairs converge) with the matrix and
+X0 already resident in HBM; it is timed for the FP64 path (the headline value)
+and for the FP32-split path.
+
+Prints one JSON line.  Options: --steps K --warmup W (default 3 / 1),
+--gpus N (only 1 is supported), --no-cpu (skip the oracle baseline),
+--cpu-iters M (oracle iterations in the CPU sample, default 5).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-k-eigenpairs at rel. residual 1e-8; SpMM GB/s; FP64 vs FP32-split"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_solves(torch, solver, X0, tol, steps, warmup, label):
+    for i in range(warmup):
+        info = solver.solve(tol, X0)
+        _log(f"[bench] {label} warmup {i}: {info['status']} iters {info['iterations']} "
+             f"{info['seconds_total']:.3f}s")
+    torch.cuda.synchronize()
+    solver.kernel_stats(True)
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        infos.append(solver.solve(tol, X0))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = solver.kernel_stats(False)
+    for i, info in enumerate(infos):
+        _log(f"[bench] {label} step {i}: {info['status']} iters {info['iterations']} "
+             f"{info['seconds_total']:.3f}s")
+    return (t1 - t0) / steps, infos, stats
+
+
+def check_solution(w, lam, X, normA, exact):
+    from scipy.sparse import csr_matrix
+
+    A = csr_matrix((w.A.values, w.A.colind, w.A.rowptr), shape=(w.A.n, w.A.n))
+    R = A @ X - X * lam
+    rho = np.linalg.norm(R, axis=0) / ((normA + np.abs(lam)) * np.linalg.norm(X, axis=0))
+    err = float(np.max(np.abs(lam - exact) / exact))
+    return float(rho.max()), err
+
+
+def cpu_baseline(w, iters, gpu_iters):
+    """The oracle, untuned, on the host: `iters` iterations of the same solve."""
+    from oracle import lobpcg as L
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = len(os.sched_getaffinity(0))
+    A = w.A.to_scipy()
+    pre = L.jacobi_precond(A)
+    t0 = time.perf_counter()
+    res = L.lobpcg(A, w.X0, w.k, w.tol, precond=pre, maxit=iters)
+    dt = time.perf_counter() - t0
+    per_it = dt / res.iterations
+    return {
+        "value": per_it * gpu_iters,
+        "unit": "s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": (f"{res.iterations} oracle iterations (incl. set-up) of the same 64^3 solve "
+                   f"from the same X0 took {dt:.1f} s = {per_it:.2f} s/iteration; value is that "
+                   f"rate times the GPU FP64 iteration count ({gpu_iters}): an estimate of the "
+                   "oracle's time to k eigenpairs"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--no-split", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the row-partitioned design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from oracle import closed_forms as cf
+    from paper_1704_07458_amd import binding as B
+    from paper_1704_07458_amd import problems as P
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    B.load()
+    w = P.workload(1)
+    exact = cf.smallest(cf.laplacian_3d_dirichlet(64), w.k)
+    X0 = torch.from_numpy(w.X0).cuda()  # resident in HBM before timing
+
+    s64 = B.Solver(w.A, w.k, precond="jacobi")
+    t64, infos64, st64 = timed_solves(torch, s64, X0, w.tol, args.steps, args.warmup, "fp64")
+    lam64, X64, _ = s64.eigpairs(w.k)
+    lam64_h, X64_h = lam64.cpu().numpy(), X64.cpu().numpy()
+    rho64, err64 = check_solution(w, lam64_h, X64_h, infos64[-1]["norm_A_est"], exact)
+    iters64 = infos64[-1]["iterations"]
+
+    split = None
+    if not args.no_split:
+        s32 = B.Solver(w.A, w.k, precond="jacobi", precision="split")
+        t32, infos32, st32 = timed_solves(torch, s32, X0, w.tol, args.steps, args.warmup, "split")
+        lam32, X32, _ = s32.eigpairs(w.k)
+        lam32_h = lam32.cpu().numpy()
+        rho32, err32 = check_solution(w, lam32_h, X32.cpu().numpy(), infos32[-1]["norm_A_est"],
+                                      exact)
+        split = {
+            "seconds": t32,
+            "iterations_fp32": infos32[-1]["fp32_iterations"],
+            "iterations_fp64": infos32[-1]["fp64_iterations"],
+            "speedup_vs_fp64": t64 / t32,
+            "max_rho": rho32,
+            "eig_rel_err_vs_closed_form": err32,
+            "eig_rel_err_vs_fp64": float(np.max(np.abs(lam32_h - lam64_h) / lam64_h)),
+            "kernels": st32,
+        }
+
+    # Roofline of the dominant HIP kernel class (by time inside the timed region).
+    classes = {"spmm": ("hbm", "GB/s", HBM_PEAK_GBS, 1e-9),
+               "gram": ("mfma", "TFLOP/s", PEAK_TFLOPS["f64"], 1e-12),
+               "update": ("mfma", "TFLOP/s", PEAK_TFLOPS["f64"], 1e-12),
+               "residual": ("hbm", "GB/s", HBM_PEAK_GBS, 1e-9)}
+    per_kernel = {}
+    for name, (bound, unit, peak, scale) in classes.items():
+        st = st64[name]
+        if st["seconds"] > 0:
+            ach = st["work"] / st["seconds"] * scale
+            per_kernel[name] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit,
+                                "frac": ach / peak, "seconds": st["seconds"],
+                                "launches": st["launches"],
+                                "avg_launch_us": 1e6 * st["seconds"] / st["launches"]}
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["seconds"])
+    roof = dict(per_kernel[dom])
+    roof["kernel"] = dom
+    roof["traffic"] = None
+    total_kernel_s = sum(v["seconds"] for v in st64.values())
+    cpu = None
+    if not args.no_cpu:
+        _log(f"[bench] oracle CPU baseline: {args.cpu_iters} iterations")
+        cpu = cpu_baseline(w, args.cpu_iters, iters64)
+
+    spmm = per_kernel.get("spmm", {})
+    out = {
+        "metric": METRIC,
+        "value": t64,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t64,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3D 7-point Dirichlet Laplacian 64^3 (n=262144, nnz=1810432), B=I, "
+                        "k=100, n_x=110, Jacobi, seeded N(0,1) X0, criterion (9) tol 1e-8",
+            "n": w.A.n, "k": w.k, "n_x": w.n_x, "tol": w.tol, "precond": "jacobi",
+        },
+        "iterations": iters64,
+        "iters_per_s": iters64 / t64,
+        "max_rho": rho64,
+        "eig_rel_err_vs_closed_form": err64,
+        "spmm_GB_s": spmm.get("achieved"),
+        "spmm_frac_hbm": spmm.get("frac"),
+        "fp32_split": split,
+        "roofline": roof,
+        "kernels": per_kernel,
+        "rayleigh_ritz_seconds": st64["rayleigh_ritz"]["seconds"],
+        "kernel_time_share": {k: v["seconds"] / (t64 * args.steps) for k, v in st64.items()},
+        "cpu_baseline": cpu,
+    }
+    del total_kernel_s
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

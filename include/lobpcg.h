@@ -1,0 +1,202 @@
+/*
+ * lobpcg.h -- C ABI of the MI355X (gfx950) robust LOBPCG library.
+ *
+ * Computes the k algebraically smallest eigenpairs of a symmetric-definite
+ * pencil (A, B), A X = B X Lambda, A symmetric and B symmetric positive
+ * definite (B = I when omitted), as defined in section 2 of Duersch, Shao,
+ * Yang and Gu, "A Robust and Efficient Implementation of LOBPCG"
+ * (arXiv 1704.07458): X minimises trace(X^T A X) subject to X^T B X = I
+ * (eq. 1).  The iteration is the paper's Algorithm 8 (robust LOBPCG) with the
+ * basis selection of Algorithms 5-7 and the backward-stable convergence test of
+ * eq. (9); every step runs on the GPU in this library's HIP kernels (sparse
+ * products, Gram blocks, basis updates, residuals) and in FP64 dense routines
+ * on the device (Rayleigh-Ritz).
+ *
+ * Conventions shared by every entry point:
+ *   - Dense blocks are ROW-MAJOR: element (i, j) of an n x m block with leading
+ *     dimension ld lives at p[i * ld + j], ld >= m.  (Column-major only where
+ *     stated.)
+ *   - Sparse matrices are CSR with full symmetric storage, int64 row pointers
+ *     (n + 1 entries, rowptr[0] = 0, rowptr[n] = nnz), int32 column indices
+ *     sorted and unique within each row, FP64 values.
+ *   - All work is enqueued on the HIP stream given in lobpcg_options.stream
+ *     (NULL = the default stream); calls that return host data synchronise it.
+ *   - Return value: 0 success, > 0 warning, < 0 error (codes below).  Nothing
+ *     throws across this boundary.  lobpcg_last_error() gives a message for the
+ *     last failing call on the calling thread.
+ *   - A handle is not thread safe; distinct handles are independent.
+ */
+#ifndef LOBPCG_MI355X_H
+#define LOBPCG_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define LOBPCG_OK 0
+#define LOBPCG_NOT_CONVERGED 1  /* maxit reached; the n_converged leading pairs are valid */
+#define LOBPCG_ERR_ARG (-1)     /* invalid argument or CSR structure */
+#define LOBPCG_ERR_ALLOC (-2)   /* device allocation failed */
+#define LOBPCG_ERR_HIP (-3)     /* a HIP runtime or ROCm library call failed */
+#define LOBPCG_ERR_BREAKDOWN (-4) /* the search space collapsed (all of W and P dropped,
+                                     or Cholesky of the initial block failed) */
+#define LOBPCG_ERR_NONFINITE (-5) /* NaN or Inf appeared in a Ritz value or residual */
+#define LOBPCG_ERR_CALLBACK (-6)  /* the preconditioner callback returned nonzero */
+#define LOBPCG_ERR_STATE (-7)     /* call out of order (e.g. eigpairs before solve) */
+
+/* Opaque solver handle; owns every device allocation it makes. */
+typedef struct lobpcg_ctx* lobpcg_t;
+
+/* Square sparse matrix in CSR form (see conventions).  on_device = 0: the three
+ * arrays are host memory; 1: device memory.  lobpcg_create copies them. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const double* values;
+  int32_t on_device;
+} lobpcg_csr;
+
+/* Preconditioner callback: W = K^-1 R for the ncols columns of R (section 2:
+ * W = K^-1 (A X - B X Theta) for any preconditioner K; Algorithm 8 applies it to
+ * the unconverged residual columns).  R and W are DEVICE pointers to row-major
+ * n x ncols blocks with leading dimensions ldr and ldw; dtype 0 = double,
+ * 1 = float (FP32 phase of the precision-split mode).  The callback must enqueue
+ * its work on `stream` (a hipStream_t) and return 0, or nonzero to abort the
+ * solve with LOBPCG_ERR_CALLBACK.  W and R do not alias. */
+typedef int (*lobpcg_precond_fn)(void* user, int64_t n, int32_t ncols, int32_t dtype,
+                                 const void* R, int64_t ldr, void* W, int64_t ldw, void* stream);
+
+/* Solver options.  Fill with lobpcg_default_options(), then override. */
+typedef struct {
+  int32_t block_size;        /* n_x >= k; 0 = k + ceil(k/10) (ten percent padding, section 6) */
+  int32_t maxit;             /* iteration limit; 0 = 2000 (section 6) */
+  int32_t precision;         /* 0 = FP64 throughout; 1 = precision split: FP32 sparse
+                                products, Gram blocks and updates until the FP32 phase
+                                converges at fp32_tol, then FP64 iterations to tol */
+  int32_t precond;           /* 0 = none (K = I); 1 = Jacobi (diagonal of A, shifted to be
+                                positive when it is not); 2 = the solve's callback */
+  int32_t implicit_products; /* -1 = automatic cost model; 0 = recompute A X (and B X) with the
+                                sparse product; 1 = implicit updates A X = (A S) C_x
+                                (section 5.2, B = I only) */
+  int32_t lq_literal;        /* 0 = P built from the LQ of Z_1(:, n_c:n_x)^T Z_1perp; 1 = the first
+                                n_x - n_c rows of the LQ of Z_1perp (Algorithm 7, line 14) */
+  double tau_ortho;          /* relative orthogonality tolerance of Algorithm 5; <= 0: 1e-12
+                                (FP64), 1e-5 in the FP32 phase */
+  double drop_factor;        /* tau_drop = drop_factor * n_u * eps (section 4.1); <= 0: 10 */
+  double replace_factor;     /* tau_replace = replace_factor * n_u * eps (Algorithm 4); <= 0: 10 */
+  double skip_factor;        /* tau_skip = skip_factor * eps; Cholesky of S^T B S is rejected when
+                                cond_1(R)^3 * tau_skip > 1 (section 5.3); <= 0: 10 */
+  double fp32_tol;           /* criterion (9) threshold ending the FP32 phase; <= 0: 1e-5 */
+  uint64_t seed;             /* seed of the Gaussian initial block when X0 is NULL */
+  void* stream;              /* hipStream_t for all work; NULL = default stream */
+} lobpcg_options;
+
+/* Per-solve statistics. seconds_phase: 0 sparse products, 1 preconditioner,
+ * 2 orthoDrop, 3 Gram blocks, 4 Rayleigh-Ritz, 5 basis update, 6 residual and
+ * convergence test, 7 other (host-timed with stream synchronisation only when
+ * profile_phases is set by lobpcg_set_profiling). */
+typedef struct {
+  int32_t iterations;         /* Algorithm 8 iterations (both phases in split mode) */
+  int32_t n_converged;        /* leading pairs meeting criterion (9) at exit */
+  int32_t ortho_switch_iter;  /* iteration at which useOrtho became true; -1 if never */
+  int32_t fp32_iterations;    /* iterations of the FP32 phase (split mode) */
+  int32_t fp64_iterations;    /* FP64 iterations */
+  int32_t svqb_calls;         /* svqb + svqbDrop calls inside orthoDrop */
+  int32_t ortho_calls;        /* orthoDrop calls */
+  int32_t flips;              /* Cholesky rejections (0 or 1 per phase) */
+  double norm_A_est;          /* ||A||_2 lower bound from the Gaussian sketch (section 4.3) */
+  double norm_B_est;          /* same for B (1 when B = I) */
+  double seconds_total;       /* wall time of lobpcg_solve */
+  double seconds_phase[8];
+} lobpcg_info;
+
+/* Fill *opt with the defaults documented above. */
+void lobpcg_default_options(lobpcg_options* opt);
+
+/* Create a solver for the k smallest eigenpairs of (A, B).
+ * A: CSR, square, sorted unique columns (checked).  B: CSR of the same size or
+ * NULL for B = I.  Symmetry is the caller's responsibility.  k >= 1 and
+ * 3 * n_x <= n (the basis [X, P, W] must fit, section 4.2).  opt may be NULL.
+ * Copies A and B to device memory owned by the handle.
+ * Errors: LOBPCG_ERR_ARG, LOBPCG_ERR_ALLOC, LOBPCG_ERR_HIP. */
+int lobpcg_create(lobpcg_t* out, const lobpcg_csr* A, const lobpcg_csr* B, int32_t k,
+                  const lobpcg_options* opt);
+
+/* Run Algorithm 8 to criterion (9) with threshold tol.
+ * X0: row-major n x n_x initial block (ld = n_x), host memory when
+ * x0_on_device = 0, device memory when 1; NULL = Gaussian N(0,1) block from
+ * opt.seed.  X0 is copied.  The sketch Omega of section 4.3 is X0^T.
+ * K: preconditioner callback (used when opt.precond = 2), K_user its argument.
+ * info: may be NULL.
+ * Returns LOBPCG_OK, LOBPCG_NOT_CONVERGED (maxit reached), or an error. */
+int lobpcg_solve(lobpcg_t h, double tol, const double* X0, int32_t x0_on_device,
+                 lobpcg_precond_fn K, void* K_user, lobpcg_info* info);
+
+/* Copy out the leading `count` Ritz pairs (count <= n_x) of the last solve:
+ * lambda (count values, ascending), X (row-major n x count, leading dimension
+ * ldx >= count, B-orthonormal columns) and rel_resid (criterion (9) per pair);
+ * any output pointer may be NULL.  on_device = 0: host buffers; 1: device.
+ * Errors: LOBPCG_ERR_STATE before a solve, LOBPCG_ERR_ARG. */
+int lobpcg_eigpairs(lobpcg_t h, int32_t count, double* lambda, double* X, int64_t ldx,
+                    double* rel_resid, int32_t on_device);
+
+/* Gradient of a loss L(lambda_1..k, x_1..k) with respect to the stored values
+ * of A, from the first `count` eigenpairs of the last solve (B = I only).
+ * First-order perturbation: d lambda_i = x_i^T dA x_i; eigenvector adjoints
+ * y_i = -sum_{j != i} x_j (x_j^T xbar_i) / (lambda_j - lambda_i), split into the
+ * part inside the computed block and a projected conjugate-gradient solve of
+ * (I - X X^T)(A - lambda_i I)(I - X X^T) z = -(I - X X^T) xbar_i for the rest.
+ * grad[p] for stored entry p = (r, c):
+ *   sum_i lambda_bar_i x_i(r) x_i(c) + 1/2 sum_i (y_i(r) x_i(c) + x_i(r) y_i(c)).
+ * lambda_bar: count values (host, may be NULL = 0); X_bar: row-major n x count
+ * DEVICE block with leading dimension ld_xbar (may be NULL = 0); grad: nnz(A)
+ * DEVICE values.  cg_tol: relative residual of the projected solve (<= 0: 1e-12);
+ * cg_maxit <= 0: 10000.  cg_iters (host, may be NULL) receives the largest CG
+ * iteration count.  Errors: LOBPCG_ERR_STATE, LOBPCG_ERR_ARG (B != I). */
+int lobpcg_adjoint(lobpcg_t h, int32_t count, const double* lambda_bar, const double* X_bar,
+                   int64_t ld_xbar, double* grad, double cg_tol, int32_t cg_maxit,
+                   int32_t* cg_iters);
+
+/* Problem dimensions of a handle (any pointer may be NULL). */
+int lobpcg_dims(lobpcg_t h, int64_t* n, int32_t* k, int32_t* n_x);
+
+/* Free every device allocation of the handle.  NULL is ignored. */
+void lobpcg_destroy(lobpcg_t h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lobpcg_last_error(void);
+
+/* Per-kernel-class statistics of the solves run while collection is enabled,
+ * for roofline accounting.  Each launch of a class is bracketed by HIP events
+ * on the solver's stream; `work` sums the algorithmic work of the launches:
+ *   kind 0 sparse products      work = bytes: nnz*(s_v+4) + 8*(n+1) + 2*n*ncols*s_v
+ *   kind 1 Gram blocks          work = flops: 2*n*m*p
+ *   kind 2 basis updates        work = flops: 2*n*K*N
+ *   kind 3 residual + test      work = bytes: (3 or 4)*n*n_x*s_v + 8*n
+ *   kind 4 Rayleigh-Ritz        work = 0 (dense FP64 on the projected pencil)
+ * (s_v = 8 for FP64, 4 for FP32 blocks.)  kinds 5-7 are reserved (zero). */
+typedef struct {
+  int64_t launches;
+  double seconds;
+  double work;
+} lobpcg_kernel_stat;
+
+/* enable = 1: reset and start collecting; 0: stop.  out (may be NULL) receives
+ * 8 entries indexed by kind, accumulated since the last reset. */
+int lobpcg_kernel_stats(lobpcg_t h, int32_t enable, lobpcg_kernel_stat* out);
+
+/* 1 = time the phases in lobpcg_info.seconds_phase (adds a stream
+ * synchronisation per phase); 0 = off (default). */
+int lobpcg_set_profiling(lobpcg_t h, int32_t on);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOBPCG_MI355X_H */

@@ -1,0 +1,193 @@
+// FP64 projected-problem routines on the device (Algorithms 2, 4, 6, 7).
+#include "dense.hpp"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "kernels.hpp"
+
+namespace lobpcg {
+
+#define LOBPCG_ROCBLAS(call)                                                               \
+  do {                                                                                     \
+    rocblas_status st_ = (call);                                                           \
+    if (st_ != rocblas_status_success)                                                     \
+      throw ::lobpcg::Error(LOBPCG_ERR_HIP, std::string(#call) + ": " +                    \
+                                                rocblas_status_to_string(st_));            \
+  } while (0)
+
+Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax), s_(s) {
+  LOBPCG_ROCBLAS(rocblas_create_handle(&h_));
+  LOBPCG_ROCBLAS(rocblas_set_stream(h_, s_));
+  const size_t sq = sizeof(double) * (size_t)nsmax * nsmax;
+  H_.alloc(sq);
+  R_.alloc(sq);
+  Ri_.alloc(sq);
+  T1_.alloc(sq);
+  Mt_.alloc(sq);
+  ZQ_.alloc(sq);
+  Qs_.alloc(sq);
+  d_.alloc(sizeof(double) * nsmax);
+  E_.alloc(sizeof(double) * nsmax);
+  tau_.alloc(sizeof(double) * nsmax);
+  th2_.alloc(sizeof(double) * nsmax);
+  scale_.alloc(sizeof(double) * nsmax);
+  info_.alloc(sizeof(int32_t) * 8);
+  cond_.alloc(sizeof(double) * 2);
+  sinfo_.alloc(sizeof(int32_t) * 2);
+  LOBPCG_HIP(hipHostMalloc((void**)&hinfo_, sizeof(int32_t) * 8, hipHostMallocDefault));
+  LOBPCG_HIP(hipHostMalloc((void**)&hcond_, sizeof(double) * 2, hipHostMallocDefault));
+}
+
+Dense::~Dense() {
+  if (h_) rocblas_destroy_handle(h_);
+  if (hinfo_) (void)hipHostFree(hinfo_);
+  if (hcond_) (void)hipHostFree(hcond_);
+}
+
+void Dense::gemm(rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 double* C, int64_t ldc) {
+  if (m == 0 || n == 0) return;
+  LOBPCG_ROCBLAS(rocblas_dgemm(h_, ta, tb, m, n, k, &alpha, A, (rocblas_int)lda, B,
+                               (rocblas_int)ldb, &beta, C, (rocblas_int)ldc));
+}
+
+void Dense::syev(int n, double* A, int64_t lda, double* w) {
+  int32_t* dinfo = info_.as<int32_t>() + 2;
+  if (eig_ == 1) {
+    LOBPCG_ROCBLAS(rocsolver_dsyevdj(h_, rocblas_evect_original, rocblas_fill_upper, n, A,
+                                     (rocblas_int)lda, w, dinfo));
+  } else {
+    LOBPCG_ROCBLAS(rocsolver_dsyevd(h_, rocblas_evect_original, rocblas_fill_upper, n, A,
+                                    (rocblas_int)lda, w, E_.as<double>(), dinfo));
+  }
+}
+
+static void copy_cm(int m, int n, const double* src, int64_t lds, double* dst, int64_t ldd,
+                    hipStream_t s) {
+  if (m == 0 || n == 0) return;
+  LOBPCG_HIP(hipMemcpy2DAsync(dst, sizeof(double) * ldd, src, sizeof(double) * lds,
+                              sizeof(double) * m, n, hipMemcpyDeviceToDevice, s));
+}
+
+RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int ns, int nx,
+                            int nc, bool use_ortho, bool literal_lq, double tau_skip, double* C,
+                            int64_t ldc, double* theta, double* theta_p, int64_t ldtp) {
+  LOBPCG_CHECK(ns <= nsmax_ && nx <= ns && nc <= nx, LOBPCG_ERR_ARG, "rr_modified: bad sizes");
+  RROutput out;
+  const int64_t ld = nsmax_;
+  double* H = H_.as<double>();
+  double* T = Ri_.as<double>();  // R^-1, then T = D R^-1 (or I)
+  double* d = d_.as<double>();
+  int32_t* dinfo = info_.as<int32_t>();
+  if (!use_ortho) {
+    double* R = R_.as<double>();
+    // Algorithm 7 lines 7-8: D = diag(S^T B S)^-1/2, R^T R = D S^T B S D.
+    launch_diag_scale(ns, GB, ldg, d, R, ld, true, s_);
+    launch_diag_scale(ns, GA, ldg, d, H, ld, false, s_);
+    LOBPCG_ROCBLAS(rocsolver_dpotrf(h_, rocblas_fill_upper, ns, R, (rocblas_int)ld, dinfo));
+    launch_zero_lower(ns, R, ld, s_);
+    copy_cm(ns, ns, R, ld, T, ld, s_);
+    LOBPCG_ROCBLAS(
+        rocsolver_dtrtri(h_, rocblas_fill_upper, rocblas_diagonal_non_unit, ns, T, (rocblas_int)ld,
+                         dinfo + 1));
+    launch_zero_lower(ns, T, ld, s_);
+    launch_cond1_upper(ns, R, T, ld, cond_.as<double>(), s_);
+    LOBPCG_HIP(hipMemcpyAsync(hinfo_, dinfo, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
+    LOBPCG_HIP(hipMemcpyAsync(hcond_, cond_.get(), sizeof(double), hipMemcpyDeviceToHost, s_));
+    LOBPCG_HIP(hipStreamSynchronize(s_));
+    out.cond = hcond_[0];
+    out.potrf_info = hinfo_[0];
+    out.trtri_info = hinfo_[1];
+    // Line 9 (section 5.3 reading): reject when cond(R)^3 tau_skip > 1.
+    const bool bad_factor = hinfo_[0] != 0 || hinfo_[1] != 0 || !std::isfinite(out.cond);
+    const bool ill = tau_skip > 0.0 && out.cond * out.cond * out.cond * tau_skip > 1.0;
+    if (bad_factor || ill) {
+      out.flipped = true;
+      return out;
+    }
+    // Line 10: (R^-T D GA D R^-1) Z = Z Theta.
+    double* T1 = T1_.as<double>();
+    gemm(rocblas_operation_none, rocblas_operation_none, ns, ns, ns, 1.0, H, ld, T, ld, 0.0, T1,
+         ld);
+    gemm(rocblas_operation_transpose, rocblas_operation_none, ns, ns, ns, 1.0, T, ld, T1, ld, 0.0,
+         H, ld);
+    launch_symmetrize(ns, H, ld, s_);
+    syev(ns, H, ld, theta);
+    // T = D R^-1 (line 12).
+    launch_row_scale(ns, ns, d, T, ld, s_);
+  } else {
+    // Line 3: S is B-orthonormal, solve (S^T A S) Z = Z Theta directly.
+    copy_cm(ns, ns, GA, ldg, H, ld, s_);
+    launch_symmetrize(ns, H, ld, s_);
+    syev(ns, H, ld, theta);
+    launch_set_identity(ns, ns, T, ld, s_);
+  }
+  const double* Z = H;
+  // C_x = T [Z_1; Z_2].
+  gemm(rocblas_operation_none, rocblas_operation_none, ns, nx, ns, 1.0, T, ld, Z, ld, 0.0, C, ldc);
+  const int m = ns - nx;
+  const int na = nx - nc;
+  const int np = std::min(na, m);
+  out.np = np;
+  if (np > 0) {
+    double* Mt = Mt_.as<double>();
+    const int64_t ldm = ld;
+    if (literal_lq) {
+      // Q_1perp rows from the LQ of Z_1perp; the first n_x - n_c of them span
+      // the first n_x - n_c rows of Z_1perp: factor those rows only.
+      const double one = 1.0, zero = 0.0;
+      LOBPCG_ROCBLAS(rocblas_dgeam(h_, rocblas_operation_transpose, rocblas_operation_none, m, na,
+                                   &one, Z + nx * ld, (rocblas_int)ld, &zero, Mt, (rocblas_int)ldm,
+                                   Mt, (rocblas_int)ldm));
+    } else {
+      // Mt = (Z_1(:, nc:nx)^T Z_1perp)^T = Z_1perp^T Z_1(:, nc:nx)   (m x na)
+      gemm(rocblas_operation_transpose, rocblas_operation_none, m, na, nx, 1.0, Z + nx * ld, ld,
+           Z + nc * ld, ld, 0.0, Mt, ldm);
+    }
+    // LQ of Mt^T == QR of Mt (Householder): Q (m x np) orthonormal columns.
+    LOBPCG_ROCBLAS(rocsolver_dgeqrf(h_, m, na, Mt, (rocblas_int)ldm, tau_.as<double>()));
+    LOBPCG_ROCBLAS(rocsolver_dorgqr(h_, m, np, np, Mt, (rocblas_int)ldm, tau_.as<double>()));
+    // C_p = T Z_perp Q.
+    double* ZQ = ZQ_.as<double>();
+    gemm(rocblas_operation_none, rocblas_operation_none, ns, np, m, 1.0, Z + nx * ld, ld, Mt, ldm,
+         0.0, ZQ, ld);
+    gemm(rocblas_operation_none, rocblas_operation_none, ns, np, ns, 1.0, T, ld, ZQ, ld, 0.0,
+         C + nx * ldc, ldc);
+    // Line 14: Theta_p = Q^T Theta_perp Q.
+    double* Qs = Qs_.as<double>();
+    copy_cm(m, np, Mt, ldm, Qs, ld, s_);
+    launch_row_scale(m, np, theta + nx, Qs, ld, s_);
+    gemm(rocblas_operation_transpose, rocblas_operation_none, np, np, m, 1.0, Mt, ldm, Qs, ld, 0.0,
+         theta_p, ldtp);
+    launch_symmetrize(np, theta_p, ldtp, s_);
+  }
+  return out;
+}
+
+int Dense::svqb_transform(double* G, int64_t ldg, int nu, double tau, bool drop, double* Tu) {
+  if (nu == 0) return 0;
+  double* d = d_.as<double>();
+  double* th = th2_.as<double>();
+  double* sc = scale_.as<double>();
+  int32_t* si = sinfo_.as<int32_t>();
+  // D = diag(U^T M U)^-1/2; eig(D U^T M U D) = Z Theta.
+  launch_diag_scale(nu, G, ldg, d, G, ldg, true, s_);
+  syev(nu, G, ldg, th);
+  launch_svqb_theta(nu, th, tau, drop ? 1 : 0, sc, si, s_);
+  LOBPCG_HIP(hipMemcpyAsync(hinfo_ + 4, si, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
+  LOBPCG_HIP(hipStreamSynchronize(s_));
+  const int first = hinfo_[4], keep = hinfo_[5];
+  if (keep <= 0) return 0;
+  // Tu = D Z(:, J) Theta(J)^-1/2
+  launch_col_scale(nu, keep, G + (int64_t)first * ldg, ldg, sc + first, 0, Tu, nu, s_);
+  launch_row_scale(nu, keep, d, Tu, nu, s_);
+  return keep;
+}
+
+}  // namespace lobpcg

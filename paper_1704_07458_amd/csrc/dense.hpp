@@ -1,0 +1,69 @@
+// FP64 dense routines on the device for the projected problems of the
+// robust LOBPCG: Rayleigh-Ritz with improved basis selection (Algorithm 7,
+// also used for Algorithm 2 on the initial block) and the small eigenproblems
+// of SVQB (Algorithms 4 and 6).  Built on rocSOLVER / rocBLAS (column-major)
+// plus the small kernels of kernels.hip.
+#pragma once
+
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace lobpcg {
+
+struct RROutput {
+  int np = 0;           // columns of C_p
+  bool flipped = false; // Cholesky rejected (section 5.3): no coefficients
+  double cond = 0.0;    // cond_1 of the scaled Cholesky factor (0 when unused)
+  int potrf_info = 0, trtri_info = 0;
+};
+
+class Dense {
+ public:
+  // nsmax: largest projected dimension; nxmax: largest n_x.
+  Dense(int nsmax, int nxmax, hipStream_t s);
+  ~Dense();
+  Dense(const Dense&) = delete;
+  Dense& operator=(const Dense&) = delete;
+
+  // Algorithm 7 on (GA, GB) (column-major, ldg).  Writes C = [C_x, C_p]
+  // (ns x (nx + np), column-major, ldc), theta (ns, ascending) and theta_p
+  // (np x np, column-major, ld ldtp).  GB is unused when use_ortho.  tau_skip <= 0
+  // disables the conditioning test (Algorithm 2).  Synchronises the stream once
+  // (to read the Cholesky status and cond) unless use_ortho.
+  RROutput rr_modified(const double* GA, const double* GB, int64_t ldg, int ns, int nx, int nc,
+                       bool use_ortho, bool literal_lq, double tau_skip, double* C, int64_t ldc,
+                       double* theta, double* theta_p, int64_t ldtp);
+
+  // SVQB transform of Algorithms 4 / 6 from the Gram matrix G = U^T M U (nu x nu,
+  // column-major, ldg; overwritten): Tu = D Z(:, J) Theta(J)^-1/2 written to Tu
+  // (nu x nkeep, column-major, ld nu).  drop = false floors theta at tau*max|theta|
+  // (keeps all); drop = true keeps theta_j > tau*max|theta|.  Returns nkeep
+  // (synchronises the stream).
+  int svqb_transform(double* G, int64_t ldg, int nu, double tau, bool drop, double* Tu);
+
+  rocblas_handle handle() const { return h_; }
+  hipStream_t stream() const { return s_; }
+
+  // Eigen-solver selection for the projected problem (0 = syevd, 1 = syevdj).
+  void set_eigensolver(int which) { eig_ = which; }
+
+ private:
+  void gemm(rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double alpha,
+            const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+            int64_t ldc);
+  void syev(int n, double* A, int64_t lda, double* w);
+
+  int nsmax_, nxmax_;
+  hipStream_t s_;
+  rocblas_handle h_ = nullptr;
+  int eig_ = 0;
+  // scratch (column-major, leading dimension nsmax_)
+  DevBuf H_, R_, Ri_, T1_, Mt_, ZQ_, Qs_, d_, E_, tau_, info_, cond_, th2_, scale_, sinfo_;
+  int32_t* hinfo_ = nullptr;  // pinned host status words
+  double* hcond_ = nullptr;
+};
+
+}  // namespace lobpcg

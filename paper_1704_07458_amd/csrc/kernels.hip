@@ -1,0 +1,1043 @@
+// HIP kernels of the robust LOBPCG path for gfx950 (CDNA4, wave64).
+//
+//  spmm      CSR sparse x row-major block (HBM-bound): one wave per row, lanes
+//            across columns, XCD-contiguous row ranges.
+//  gram      tall-skinny L^T R on MFMA (v_mfma_f64_16x16x4f64 / f32_16x16x4f32),
+//            split-K over rows, deterministic FP64 second-stage sum.
+//  update    row-tiled S C on MFMA (section 5.1 basis update).
+//  residual  R = AX - BX Theta fused with the Jacobi preconditioner, the
+//            reversed W store and FP64 column norms for criterion (9).
+//  small     FP64 helpers for the projected (n_s x n_s) problem.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace lobpcg {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kXcds = 8;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Workgroups are handed to the 8 XCDs round-robin.  Map the dispatch index so
+// that each XCD works on one contiguous range of logical blocks: neighbouring
+// rows then share that XCD's L2.  The map is a bijection on [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int x = b % kXcds, i = b / kXcds;
+  const int q = nb / kXcds, r = nb % kXcds;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------------ SpMM
+// Grid: x = row blocks of kRowsPerBlock rows, y = column panels of 64*NC.
+constexpr int kSpmmRowsPerBlock = 32;
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void spmm_kernel(int64_t n, const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ colind,
+                                                   const T* __restrict__ vals,
+                                                   const T* __restrict__ X, int64_t ldx,
+                                                   T* __restrict__ Y, int64_t ldy, int ncols) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int wave = uniform(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int col0 = blockIdx.y * (kWave * NC) + lane;
+  const int64_t rbeg = (int64_t)lb * kSpmmRowsPerBlock;
+  const int64_t rend = rbeg + kSpmmRowsPerBlock < n ? rbeg + kSpmmRowsPerBlock : n;
+  bool cok[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) cok[j] = col0 + kWave * j < ncols;
+
+  for (int64_t r = rbeg + wave; r < rend; r += 4) {
+    T acc[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[j] = T(0);
+    int64_t p = rowptr[r];
+    const int64_t pe = rowptr[r + 1];
+    // Four nonzeros per step: their column indices and values are wave-uniform
+    // (scalar loads); the X-row loads are independent and issued together.
+    for (; p + 4 <= pe; p += 4) {
+      const int64_t c0 = colind[p], c1 = colind[p + 1], c2 = colind[p + 2], c3 = colind[p + 3];
+      const T a0 = vals[p], a1 = vals[p + 1], a2 = vals[p + 2], a3 = vals[p + 3];
+      T x0[NC], x1[NC], x2[NC], x3[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int c = col0 + kWave * j;
+        x0[j] = cok[j] ? X[c0 * ldx + c] : T(0);
+        x1[j] = cok[j] ? X[c1 * ldx + c] : T(0);
+        x2[j] = cok[j] ? X[c2 * ldx + c] : T(0);
+        x3[j] = cok[j] ? X[c3 * ldx + c] : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        acc[j] = fma(a0, x0[j], acc[j]);
+        acc[j] = fma(a1, x1[j], acc[j]);
+        acc[j] = fma(a2, x2[j], acc[j]);
+        acc[j] = fma(a3, x3[j], acc[j]);
+      }
+    }
+    for (; p < pe; ++p) {
+      const int64_t c0 = colind[p];
+      const T a0 = vals[p];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int c = col0 + kWave * j;
+        if (cok[j]) acc[j] = fma(a0, X[c0 * ldx + c], acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+      if (cok[j]) Y[r * ldy + col0 + kWave * j] = acc[j];
+  }
+}
+
+// ------------------------------------------------------------------ MFMA
+template <typename T>
+struct Mfma;
+// 16x16x4 MFMA lane layout (wave64), used by both kernels below:
+//   A (16 x 4):  lane l holds A[l % 16][l / 16]
+//   B (4 x 16):  lane l holds B[l / 16][l % 16]
+//   D (16 x 16): lane l, accumulator element q holds D[row(l / 16, q)][l % 16] with
+//                row = 4 * (l / 16) + q for f32 and row = l / 16 + 4 * q for f64
+//                (the FP64 instruction interleaves the rows across lane groups).
+template <>
+struct Mfma<double> {
+  using acc_t = v4d;
+  __device__ static __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int lk, int q) { return lk + 4 * q; }
+};
+template <>
+struct Mfma<float> {
+  using acc_t = v4f;
+  __device__ static __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int lk, int q) { return 4 * lk + q; }
+};
+
+// ------------------------------------------------------------------ Gram
+// Workgroup tile 64 (m) x 64 (p): 2 x 2 waves, each wave 32 x 32 = 2 x 2 MFMA
+// blocks.  Grid: x = nsplit * tiles (tile index fastest).  Each workgroup sums
+// its row range [k0, k1) and writes a partial tile to part[split][i][j].
+constexpr int kGramTM = 64, kGramTP = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_kernel(
+    int64_t n, int m, int p, int p1, const T* __restrict__ L, int64_t ldl,
+    const T* __restrict__ R1, int64_t ldr1, const T* __restrict__ R2, int64_t ldr2,
+    double* __restrict__ part, int tiles_m, int tiles_p, int64_t rows_per_split) {
+  using acc_t = typename Mfma<T>::acc_t;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntiles = tiles_m * tiles_p;
+  const int split = lb / ntiles;
+  const int tile = lb % ntiles;
+  const int tm = tile / tiles_p, tp = tile % tiles_p;
+  const int wave = uniform(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int wm = wave >> 1, wp = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  const int64_t k0 = (int64_t)split * rows_per_split;
+  const int64_t k1 = k0 + rows_per_split < n ? k0 + rows_per_split : n;
+
+  // Column of L (A operand) and of R (B operand) this lane reads, per block.
+  int colA[2], colB[2];
+  bool okA[2], okB[2];
+  const T* baseB[2];
+  int64_t ldB[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    colA[f] = tm * kGramTM + wm * 32 + f * 16 + li;
+    okA[f] = colA[f] < m;
+    const int cb = tp * kGramTP + wp * 32 + f * 16 + li;
+    okB[f] = cb < p;
+    if (cb < p1) {
+      baseB[f] = R1 + cb;
+      ldB[f] = ldr1;
+    } else {
+      baseB[f] = R2 + (cb - p1);
+      ldB[f] = ldr2;
+    }
+    colB[f] = cb;
+  }
+
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  // Main loop: 4 rows per MFMA step, two steps per iteration so that the loads
+  // of the second step are in flight while the first step's MFMAs issue.
+  int64_t k = k0;
+  for (; k + 8 <= k1; k += 8) {
+    T a[2][2], b[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int64_t row = k + 4 * s + lk;
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        a[s][f] = okA[f] ? L[row * ldl + colA[f]] : T(0);
+        b[s][f] = okB[f] ? baseB[f][row * ldB[f]] : T(0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int fa = 0; fa < 2; ++fa)
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb) acc[fa][fb] = Mfma<T>::mma(a[s][fa], b[s][fb], acc[fa][fb]);
+  }
+  for (; k < k1; k += 4) {
+    const int64_t row = k + lk;
+    const bool rok = row < k1;
+    T a[2], b[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      a[f] = (rok && okA[f]) ? L[row * ldl + colA[f]] : T(0);
+      b[f] = (rok && okB[f]) ? baseB[f][row * ldB[f]] : T(0);
+    }
+#pragma unroll
+    for (int fa = 0; fa < 2; ++fa)
+#pragma unroll
+      for (int fb = 0; fb < 2; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
+  }
+
+  // Store the partial tile (FP64).
+  double* out = part + (int64_t)split * m * p;
+#pragma unroll
+  for (int fa = 0; fa < 2; ++fa)
+#pragma unroll
+    for (int fb = 0; fb < 2; ++fb) {
+      const int j = colB[fb];
+      if (j >= p) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = tm * kGramTM + wm * 32 + fa * 16 + Mfma<T>::row(lk, q);
+        if (i < m) out[(int64_t)i * p + j] = (double)acc[fa][fb][q];
+      }
+    }
+}
+
+// Second stage: G(i, j) = sum over splits in fixed order (column-major output).
+// Column j < p1 goes to column c1 + j of G1, the rest to column c2 + j - p1 of G2.
+// Rows i < mirror_rows are also written transposed (symmetric completion).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int p1, int nsplit,
+                                                          const double* __restrict__ part,
+                                                          double* __restrict__ G1, int c1,
+                                                          double* __restrict__ G2, int c2,
+                                                          int64_t ldg, int mirror_rows) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mp = (int64_t)m * p;
+  if (idx >= mp) return;
+  const int i = (int)(idx / p), j = (int)(idx % p);
+  double s = 0.0;
+  for (int t = 0; t < nsplit; ++t) s += part[(int64_t)t * mp + idx];
+  double* G = j < p1 ? G1 : G2;
+  const int c = j < p1 ? c1 + j : c2 + (j - p1);
+  G[i + (int64_t)c * ldg] = s;
+  if (i < mirror_rows) G[c + (int64_t)i * ldg] = s;
+}
+
+struct GramPlan {
+  int tiles_m, tiles_p, nsplit;
+  int64_t rows_per_split;
+};
+
+GramPlan gram_plan(int64_t n, int m, int p) {
+  GramPlan g;
+  g.tiles_m = (m + kGramTM - 1) / kGramTM;
+  g.tiles_p = (p + kGramTP - 1) / kGramTP;
+  const int ntiles = g.tiles_m * g.tiles_p;
+  // Aim for about 2048 workgroups (8 per CU) with at least 256 rows each.
+  int64_t target = std::max<int64_t>(1, 2048 / std::max(ntiles, 1));
+  int64_t max_by_rows = std::max<int64_t>(1, n / 256);
+  int64_t ns = std::min(target, max_by_rows);
+  ns = std::min<int64_t>(ns, 1024);
+  int64_t rps = (n + ns - 1) / ns;
+  rps = round_up(std::max<int64_t>(rps, 8), 8);
+  g.nsplit = (int)((n + rps - 1) / rps);
+  if (g.nsplit < 1) g.nsplit = 1;
+  g.rows_per_split = rps;
+  return g;
+}
+
+// ------------------------------------------------------------------ update
+// Y tile 64 rows x 64 cols per workgroup: 2 x 2 waves, each 32 x 32.
+// Grid: x = row tiles * col tiles (col tile fastest).
+constexpr int kUpdTM = 64, kUpdTN = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void update_kernel(int64_t n, int K, int N,
+                                                     const T* __restrict__ S, int64_t lds,
+                                                     const double* __restrict__ C, int64_t ldc,
+                                                     T alpha, int beta1, T* __restrict__ Y,
+                                                     int64_t ldy, int tiles_n) {
+  using acc_t = typename Mfma<T>::acc_t;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t tr = lb / tiles_n;
+  const int tc = lb % tiles_n;
+  const int wave = uniform(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  int64_t rowA[2];
+  bool okA[2];
+  int colB[2];
+  bool okB[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    rowA[f] = tr * kUpdTM + wr * 32 + f * 16 + li;
+    okA[f] = rowA[f] < n;
+    colB[f] = tc * kUpdTN + wc * 32 + f * 16 + li;
+    okB[f] = colB[f] < N;
+  }
+  const T* srow[2] = {S + (okA[0] ? rowA[0] : 0) * lds, S + (okA[1] ? rowA[1] : 0) * lds};
+  const double* ccol[2] = {C + (int64_t)(okB[0] ? colB[0] : 0) * ldc,
+                           C + (int64_t)(okB[1] ? colB[1] : 0) * ldc};
+
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  int k = 0;
+  for (; k + 8 <= K; k += 8) {
+    T a[2][2], b[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int kk = k + 4 * s + lk;
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        a[s][f] = okA[f] ? srow[f][kk] : T(0);
+        b[s][f] = okB[f] ? (T)ccol[f][kk] : T(0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int fa = 0; fa < 2; ++fa)
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb) acc[fa][fb] = Mfma<T>::mma(a[s][fa], b[s][fb], acc[fa][fb]);
+  }
+  for (; k < K; k += 4) {
+    const int kk = k + lk;
+    const bool kok = kk < K;
+    T a[2], b[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      a[f] = (kok && okA[f]) ? srow[f][kk] : T(0);
+      b[f] = (kok && okB[f]) ? (T)ccol[f][kk] : T(0);
+    }
+#pragma unroll
+    for (int fa = 0; fa < 2; ++fa)
+#pragma unroll
+      for (int fb = 0; fb < 2; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
+  }
+
+#pragma unroll
+  for (int fa = 0; fa < 2; ++fa)
+#pragma unroll
+    for (int fb = 0; fb < 2; ++fb) {
+      const int j = colB[fb];
+      if (!okB[fb]) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = tr * kUpdTM + wr * 32 + fa * 16 + Mfma<T>::row(lk, q);
+        if (r < n) {
+          T v = alpha * acc[fa][fb][q];
+          if (beta1) v += Y[r * ldy + j];
+          Y[r * ldy + j] = v;
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------------ residual
+// Grid: x = row blocks (kResRows rows each), y = column chunks of 64.
+// Each thread owns one column; 4 waves stride over the block's rows.
+constexpr int kResRows = 256;
+
+template <typename T>
+__global__ __launch_bounds__(256) void residual_kernel(
+    int64_t n, int nx, const T* __restrict__ AX, int64_t ldax, const T* __restrict__ BX,
+    int64_t ldbx, const T* __restrict__ X, int64_t ldx, const double* __restrict__ theta,
+    const double* __restrict__ dinv, T* __restrict__ W, int64_t ldw, double* __restrict__ part_r,
+    double* __restrict__ part_x) {
+  __shared__ double sr[4][kWave], sx[4][kWave];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int wave = uniform(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int j = blockIdx.y * kWave + lane;
+  const bool ok = j < nx;
+  const double th = ok ? theta[j] : 0.0;
+  const int64_t r0 = (int64_t)lb * kResRows;
+  const int64_t r1 = r0 + kResRows < n ? r0 + kResRows : n;
+  double accr = 0.0, accx = 0.0;
+  if (ok) {
+    for (int64_t r = r0 + wave; r < r1; r += 4) {
+      const double x = (double)X[r * ldx + j];
+      const double bx = BX ? (double)BX[r * ldbx + j] : x;
+      const double res = (double)AX[r * ldax + j] - bx * th;
+      accr = fma(res, res, accr);
+      accx = fma(x, x, accx);
+      if (W) W[r * ldw + (nx - 1 - j)] = (T)(dinv ? res * dinv[r] : res);
+    }
+  }
+  sr[wave][lane] = accr;
+  sx[wave][lane] = accx;
+  __syncthreads();
+  if (wave == 0 && ok) {
+    const double a = ((sr[0][lane] + sr[1][lane]) + sr[2][lane]) + sr[3][lane];
+    const double b = ((sx[0][lane] + sx[1][lane]) + sx[2][lane]) + sx[3][lane];
+    part_r[(int64_t)lb * nx + j] = a;
+    part_x[(int64_t)lb * nx + j] = b;
+  }
+}
+
+// One workgroup: rho_j, the leading run n_c[0] and a non-finite flag n_c[1].
+__global__ __launch_bounds__(256) void residual_finish_kernel(
+    int nx, int nblocks, const double* __restrict__ part_r, const double* __restrict__ part_x,
+    const double* __restrict__ theta, double normA, double normB, double tol,
+    double* __restrict__ rho, int32_t* __restrict__ n_c) {
+  __shared__ int smin[256];
+  __shared__ int sbad[256];
+  int first_bad = nx, nonfinite = 0;
+  for (int j = threadIdx.x; j < nx; j += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < nblocks; ++t) {
+      a += part_r[(int64_t)t * nx + j];
+      b += part_x[(int64_t)t * nx + j];
+    }
+    const double r = sqrt(a) / ((normA + fabs(theta[j]) * normB) * sqrt(b));
+    rho[j] = r;
+    if (!(r <= tol) && j < first_bad) first_bad = j;
+    if (!isfinite(r) || !isfinite(theta[j])) nonfinite = 1;
+  }
+  smin[threadIdx.x] = first_bad;
+  sbad[threadIdx.x] = nonfinite;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + s]);
+      sbad[threadIdx.x] = max(sbad[threadIdx.x], sbad[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && n_c) {
+    n_c[0] = smin[0];
+    n_c[1] = sbad[0];
+  }
+}
+
+// ------------------------------------------------------------------ colsq
+template <typename T>
+__global__ __launch_bounds__(256) void colsq_kernel(int64_t n, int ncols, const T* __restrict__ Y,
+                                                    int64_t ldy, double* __restrict__ part) {
+  __shared__ double sq[4][kWave];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int wave = uniform(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int j = blockIdx.y * kWave + lane;
+  const int64_t r0 = (int64_t)lb * kResRows;
+  const int64_t r1 = r0 + kResRows < n ? r0 + kResRows : n;
+  double acc = 0.0;
+  if (j < ncols)
+    for (int64_t r = r0 + wave; r < r1; r += 4) {
+      const double y = (double)Y[r * ldy + j];
+      acc = fma(y, y, acc);
+    }
+  sq[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && j < ncols)
+    part[(int64_t)lb * ncols + j] = ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane];
+}
+
+__global__ void colsq_finish_kernel(int ncols, int nblocks, const double* __restrict__ part,
+                                    double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncols) return;
+  double a = 0.0;
+  for (int t = 0; t < nblocks; ++t) a += part[(int64_t)t * ncols + j];
+  out[j] = a;
+}
+
+// ------------------------------------------------------------------ Jacobi
+// Per row: diagonal, sum of |off-diagonal|, sum of all |a_ij|.
+__global__ void jacobi_rows_kernel(int64_t n, const int64_t* __restrict__ rowptr,
+                                   const int32_t* __restrict__ colind,
+                                   const double* __restrict__ vals, double* __restrict__ diag,
+                                   double* __restrict__ margin, double* __restrict__ absrow) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double d = 0.0, off = 0.0, tot = 0.0;
+  for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+    const double a = vals[p];
+    tot += fabs(a);
+    if (colind[p] == r) d += a;
+    else off += fabs(a);
+  }
+  diag[r] = d;
+  margin[r] = d - off;
+  absrow[r] = tot;
+}
+
+// One workgroup: min of diag, min of margin, max of absrow.
+__global__ __launch_bounds__(256) void jacobi_reduce_kernel(int64_t n, const double* diag,
+                                                            const double* margin,
+                                                            const double* absrow, double* out3) {
+  __shared__ double s0[256], s1[256], s2[256];
+  double mn = INFINITY, mg = INFINITY, mx = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    mn = fmin(mn, diag[r]);
+    mg = fmin(mg, margin[r]);
+    mx = fmax(mx, absrow[r]);
+  }
+  s0[threadIdx.x] = mn;
+  s1[threadIdx.x] = mg;
+  s2[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      s0[threadIdx.x] = fmin(s0[threadIdx.x], s0[threadIdx.x + s]);
+      s1[threadIdx.x] = fmin(s1[threadIdx.x], s1[threadIdx.x + s]);
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out3[0] = s0[0];
+    out3[1] = s1[0];
+    out3[2] = s2[0];
+  }
+}
+
+__global__ void jacobi_finish_kernel(int64_t n, const double* diag, const double* stats,
+                                     double* dinv) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double sigma = stats[0] > 0.0 ? 0.0 : stats[1] - 1e-3 * stats[2];
+  dinv[r] = 1.0 / (diag[r] - sigma);
+}
+
+// ------------------------------------------------------------------ copies
+template <typename Tin, typename Tout>
+__global__ void copy2d_kernel(int64_t n, int ncols, const Tin* __restrict__ src, int64_t lds,
+                              Tout* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * ncols) return;
+  const int64_t r = idx / ncols;
+  const int c = (int)(idx % ncols);
+  dst[r * ldd + c] = (Tout)src[r * lds + c];
+}
+
+template <typename T>
+__global__ void copy2d_reverse_kernel(int64_t n, int ncols, const T* __restrict__ src,
+                                      int64_t lds, T* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * ncols) return;
+  const int64_t r = idx / ncols;
+  const int c = (int)(idx % ncols);
+  dst[r * ldd + (ncols - 1 - c)] = src[r * lds + c];
+}
+
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) counter-based generator.
+__device__ __forceinline__ void philox_round(uint32_t c[4], const uint32_t k[2]) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k[0], n2 = hi0 ^ c[3] ^ k[1];
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+__global__ void gaussian_kernel(int64_t n, int ncols, double* __restrict__ dst, int64_t ldd,
+                                uint64_t seed) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = n * ncols;
+  if (2 * idx >= total) return;
+  uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), 0u, 0u};
+  uint32_t k[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k);
+    k[0] += 0x9E3779B9u;
+    k[1] += 0xBB67AE85u;
+  }
+  // Two uniforms in (0, 1] from 64-bit words, then Box-Muller.
+  const double u1 = ((double)(((uint64_t)c[0] << 32 | c[1]) >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(((uint64_t)c[2] << 32 | c[3]) >> 11) * 0x1.0p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 6.283185307179586 * u2;
+  const int64_t e0 = 2 * idx, e1 = 2 * idx + 1;
+  dst[(e0 / ncols) * ldd + e0 % ncols] = rad * cos(ang);
+  if (e1 < total) dst[(e1 / ncols) * ldd + e1 % ncols] = rad * sin(ang);
+}
+
+// ------------------------------------------------------------------ small dense
+__global__ void fill_implicit_kernel(int nx, int np, const double* __restrict__ theta,
+                                     const double* __restrict__ theta_p, int64_t ldtp,
+                                     double* __restrict__ GA, double* __restrict__ GB,
+                                     int64_t ldg) {
+  const int m = nx + np;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m) return;
+  const int i = (int)(idx % m), j = (int)(idx / m);
+  double a = 0.0, b = (i == j) ? 1.0 : 0.0;
+  if (i < nx && j < nx) a = (i == j) ? theta[i] : 0.0;
+  else if (i >= nx && j >= nx) a = theta_p[(i - nx) + (int64_t)(j - nx) * ldtp];
+  GA[i + (int64_t)j * ldg] = a;
+  if (GB) GB[i + (int64_t)j * ldg] = b;
+}
+
+__global__ void diag_d_kernel(int n, const double* __restrict__ G, int64_t ldg,
+                              double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double g = G[i + (int64_t)i * ldg];
+  d[i] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
+}
+
+__global__ void diag_scale_kernel(int n, const double* __restrict__ G, int64_t ldg,
+                                  const double* __restrict__ d, double* __restrict__ Gout,
+                                  int64_t ldo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx % n), j = (int)(idx / n);
+  Gout[i + (int64_t)j * ldo] = d[i] * G[i + (int64_t)j * ldg] * d[j];
+}
+
+__global__ __launch_bounds__(256) void cond1_upper_kernel(int n, const double* __restrict__ R,
+                                                          const double* __restrict__ Ri,
+                                                          int64_t ld, double* __restrict__ cond) {
+  __shared__ double s0[256], s1[256];
+  double m0 = 0.0, m1 = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i <= j; ++i) {
+      a += fabs(R[i + (int64_t)j * ld]);
+      b += fabs(Ri[i + (int64_t)j * ld]);
+    }
+    // NaN-propagating maximum: a NaN column makes the condition number NaN.
+    m0 = (a > m0 || a != a) ? a : m0;
+    m1 = (b > m1 || b != b) ? b : m1;
+  }
+  s0[threadIdx.x] = m0;
+  s1[threadIdx.x] = m1;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const double a = s0[threadIdx.x + s], b = s1[threadIdx.x + s];
+      if (a > s0[threadIdx.x] || a != a) s0[threadIdx.x] = a;
+      if (b > s1[threadIdx.x] || b != b) s1[threadIdx.x] = b;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *cond = s0[0] * s1[0];
+}
+
+__global__ void zero_lower_kernel(int n, double* A, int64_t ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx % n), j = (int)(idx / n);
+  if (i > j) A[i + (int64_t)j * ld] = 0.0;
+}
+
+__global__ void row_scale_kernel(int m, int n, const double* __restrict__ d, double* A,
+                                 int64_t lda) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * n) return;
+  const int i = (int)(idx % m), j = (int)(idx / m);
+  A[i + (int64_t)j * lda] *= d[i];
+}
+
+__global__ void col_scale_kernel(int m, int n, const double* __restrict__ A, int64_t lda,
+                                 const double* __restrict__ theta, int mode,
+                                 double* __restrict__ B, int64_t ldb) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * n) return;
+  const int i = (int)(idx % m), j = (int)(idx / m);
+  const double f = mode == 0 ? theta[j] : 1.0 / sqrt(theta[j]);
+  B[i + (int64_t)j * ldb] = A[i + (int64_t)j * lda] * f;
+}
+
+__global__ void symmetrize_kernel(int n, double* A, int64_t lda) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx % n), j = (int)(idx / n);
+  if (i < j) {
+    const double v = 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]);
+    A[i + (int64_t)j * lda] = v;
+    A[j + (int64_t)i * lda] = v;
+  }
+}
+
+__global__ void set_identity_kernel(int m, int n, double* A, int64_t lda) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * n) return;
+  const int i = (int)(idx % m), j = (int)(idx / m);
+  A[i + (int64_t)j * lda] = (i == j) ? 1.0 : 0.0;
+}
+
+// theta ascending.  The eigenvalues above the threshold form a trailing run.
+__global__ __launch_bounds__(256) void svqb_theta_kernel(int n, double* theta, double tau, int drop,
+                                                         double* scale, int32_t* info) {
+  __shared__ double smax[256];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) mx = fmax(mx, fabs(theta[j]));
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double thr = tau * smax[0];
+  __syncthreads();
+  __shared__ int sfirst[256];
+  int first = n;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double t = theta[j];
+    if (drop) {
+      if (t > thr) {
+        first = min(first, j);
+        scale[j] = 1.0 / sqrt(t);
+      } else {
+        scale[j] = 0.0;
+      }
+    } else {
+      if (t < thr) t = thr;
+      theta[j] = t;
+      scale[j] = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+      first = 0;
+    }
+  }
+  sfirst[threadIdx.x] = first;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sfirst[threadIdx.x] = min(sfirst[threadIdx.x], sfirst[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int f = drop ? sfirst[0] : 0;
+    info[0] = f;
+    info[1] = n - f;
+  }
+}
+
+__global__ __launch_bounds__(256) void fro_kernel(int m, int n, const double* __restrict__ A,
+                                                  int64_t lda, int minus_identity, double* out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  const int64_t total = (int64_t)m * n;
+  for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int i = (int)(idx % m), j = (int)(idx / m);
+    double v = A[i + (int64_t)j * lda];
+    if (minus_identity && i == j) v -= 1.0;
+    acc = fma(v, v, acc);
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(s[0]);
+}
+
+__global__ __launch_bounds__(256) void sqrt_sum_kernel(int n, const double* __restrict__ v,
+                                                       double* out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) acc += v[j];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(s[0]);
+}
+
+inline unsigned blocks_for(int64_t total, int threads = 256) {
+  return (unsigned)((total + threads - 1) / threads);
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+template <typename T>
+void launch_spmm(int64_t n, const int64_t* rowptr, const int32_t* colind, const T* vals,
+                 const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, hipStream_t s) {
+  if (n == 0 || ncols == 0) return;
+  const unsigned gx = (unsigned)((n + kSpmmRowsPerBlock - 1) / kSpmmRowsPerBlock);
+  if (ncols <= 64) {
+    hipLaunchKernelGGL((spmm_kernel<T, 1>), dim3(gx, 1), dim3(256), 0, s, n, rowptr, colind, vals,
+                       X, ldx, Y, ldy, ncols);
+  } else if (ncols <= 128) {
+    hipLaunchKernelGGL((spmm_kernel<T, 2>), dim3(gx, 1), dim3(256), 0, s, n, rowptr, colind, vals,
+                       X, ldx, Y, ldy, ncols);
+  } else {
+    const unsigned gy = (unsigned)((ncols + 255) / 256);
+    hipLaunchKernelGGL((spmm_kernel<T, 4>), dim3(gx, gy), dim3(256), 0, s, n, rowptr, colind,
+                       vals, X, ldx, Y, ldy, ncols);
+  }
+  LOBPCG_HIP(hipGetLastError());
+}
+
+int64_t gram_workspace_bytes(int64_t n, int m, int p) {
+  if (n == 0 || m == 0 || p == 0) return 0;
+  const GramPlan g = gram_plan(n, m, p);
+  return (int64_t)g.nsplit * m * p * (int64_t)sizeof(double);
+}
+
+template <typename T>
+void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const T* R1,
+                 int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,
+                 int64_t ldg, int mirror_rows, void* work, hipStream_t s) {
+  if (m == 0 || p == 0) return;
+  const GramPlan g = gram_plan(n, m, p);
+  const int nsplit = n > 0 ? g.nsplit : 0;
+  double* part = static_cast<double*>(work);
+  if (nsplit > 0) {
+    const unsigned grid = (unsigned)(nsplit * g.tiles_m * g.tiles_p);
+    hipLaunchKernelGGL((gram_partial_kernel<T>), dim3(grid), dim3(256), 0, s, n, m, p, p1, L,
+                       ldl, R1, ldr1, R2 ? R2 : R1, R2 ? ldr2 : ldr1, part, g.tiles_m, g.tiles_p,
+                       g.rows_per_split);
+    LOBPCG_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for((int64_t)m * p)), dim3(256), 0, s, m, p,
+                     p1, nsplit, part, G1, c1, G2 ? G2 : G1, c2, ldg, mirror_rows);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+int64_t gram_workspace_bound(int64_t n, int m, int p) {
+  (void)n;
+  // nsplit <= max(1, 2048 / tiles) and m * p <= tiles * 64 * 64.
+  return 8 * std::max<int64_t>(2048LL * kGramTM * kGramTP, (int64_t)m * p);
+}
+
+template <typename T>
+void launch_update(int64_t n, int K, int N, const T* S, int64_t lds, const double* C, int64_t ldc,
+                   double alpha, double beta, T* Y, int64_t ldy, hipStream_t s) {
+  if (n == 0 || N == 0) return;
+  const int tiles_n = (N + kUpdTN - 1) / kUpdTN;
+  const int64_t tiles_r = (n + kUpdTM - 1) / kUpdTM;
+  const int64_t grid = tiles_r * tiles_n;
+  LOBPCG_CHECK(grid < (int64_t)1 << 31, LOBPCG_ERR_ARG, "update grid too large");
+  hipLaunchKernelGGL((update_kernel<T>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N, S, lds, C,
+                     ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+int64_t residual_workspace_bytes(int64_t n, int nx) {
+  const int64_t nb = std::max<int64_t>(1, (n + kResRows - 1) / kResRows);
+  return 2 * nb * (int64_t)std::max(nx, 1) * (int64_t)sizeof(double);
+}
+
+template <typename T>
+void launch_residual(int64_t n, int nx, const T* AX, int64_t ldax, const T* BX, int64_t ldbx,
+                     const T* X, int64_t ldx, const double* theta, const double* dinv, T* W,
+                     int64_t ldw, double normA, double normB, double tol, double* rho,
+                     int32_t* n_c, void* work, hipStream_t s) {
+  if (nx == 0) return;
+  const int64_t nb = std::max<int64_t>(1, (n + kResRows - 1) / kResRows);
+  double* part_r = static_cast<double*>(work);
+  double* part_x = part_r + nb * nx;
+  hipLaunchKernelGGL((residual_kernel<T>), dim3((unsigned)nb, (unsigned)((nx + 63) / 64)),
+                     dim3(256), 0, s, n, nx, AX, ldax, BX, ldbx, X, ldx, theta, dinv, W, ldw,
+                     part_r, part_x);
+  LOBPCG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(residual_finish_kernel, dim3(1), dim3(256), 0, s, nx, (int)nb, part_r, part_x,
+                     theta, normA, normB, tol, rho, n_c);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+int64_t colsq_workspace_bytes(int64_t n, int ncols) {
+  const int64_t nb = std::max<int64_t>(1, (n + kResRows - 1) / kResRows);
+  return nb * (int64_t)std::max(ncols, 1) * (int64_t)sizeof(double);
+}
+
+template <typename T>
+void launch_colsq(int64_t n, int ncols, const T* Y, int64_t ldy, double* out, void* work,
+                  hipStream_t s) {
+  if (ncols == 0) return;
+  const int64_t nb = std::max<int64_t>(1, (n + kResRows - 1) / kResRows);
+  double* part = static_cast<double*>(work);
+  hipLaunchKernelGGL((colsq_kernel<T>), dim3((unsigned)nb, (unsigned)((ncols + 63) / 64)),
+                     dim3(256), 0, s, n, ncols, Y, ldy, part);
+  LOBPCG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(colsq_finish_kernel, dim3(blocks_for(ncols)), dim3(256), 0, s, ncols, (int)nb,
+                     part, out);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+int64_t jacobi_workspace_bytes(int64_t n) { return (3 * n + 4) * (int64_t)sizeof(double); }
+
+void launch_jacobi_setup(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                         const double* vals, double* dinv, void* work, hipStream_t s) {
+  if (n == 0) return;
+  double* diag = static_cast<double*>(work);
+  double* margin = diag + n;
+  double* absrow = margin + n;
+  double* stats = absrow + n;
+  hipLaunchKernelGGL(jacobi_rows_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, rowptr, colind,
+                     vals, diag, margin, absrow);
+  hipLaunchKernelGGL(jacobi_reduce_kernel, dim3(1), dim3(256), 0, s, n, diag, margin, absrow,
+                     stats);
+  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, diag, stats,
+                     dinv);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+template <typename Tin, typename Tout>
+void launch_copy2d(int64_t n, int ncols, const Tin* src, int64_t lds, Tout* dst, int64_t ldd,
+                   hipStream_t s) {
+  if (n == 0 || ncols == 0) return;
+  hipLaunchKernelGGL((copy2d_kernel<Tin, Tout>), dim3(blocks_for(n * ncols)), dim3(256), 0, s, n,
+                     ncols, src, lds, dst, ldd);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_copy2d_reverse(int64_t n, int ncols, const T* src, int64_t lds, T* dst, int64_t ldd,
+                           hipStream_t s) {
+  if (n == 0 || ncols == 0) return;
+  hipLaunchKernelGGL((copy2d_reverse_kernel<T>), dim3(blocks_for(n * ncols)), dim3(256), 0, s, n,
+                     ncols, src, lds, dst, ldd);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_gaussian(int64_t n, int ncols, double* dst, int64_t ldd, uint64_t seed, hipStream_t s) {
+  const int64_t pairs = (n * ncols + 1) / 2;
+  if (pairs == 0) return;
+  hipLaunchKernelGGL(gaussian_kernel, dim3(blocks_for(pairs)), dim3(256), 0, s, n, ncols, dst, ldd,
+                     seed);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_fill_implicit(int nx, int np, const double* theta, const double* theta_p,
+                          int64_t ldtp, double* GA, double* GB, int64_t ldg, hipStream_t s) {
+  const int m = nx + np;
+  if (m == 0) return;
+  hipLaunchKernelGGL(fill_implicit_kernel, dim3(blocks_for((int64_t)m * m)), dim3(256), 0, s, nx,
+                     np, theta, theta_p, ldtp, GA, GB, ldg);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_diag_scale(int n, const double* G, int64_t ldg, double* d, double* Gout, int64_t ldo,
+                       bool compute_d, hipStream_t s) {
+  if (n == 0) return;
+  if (compute_d)
+    hipLaunchKernelGGL(diag_d_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, G, ldg, d);
+  hipLaunchKernelGGL(diag_scale_kernel, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, s, n, G,
+                     ldg, d, Gout, ldo);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_cond1_upper(int n, const double* R, const double* Rinv, int64_t ld, double* cond,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(cond1_upper_kernel, dim3(1), dim3(256), 0, s, n, R, Rinv, ld, cond);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_zero_lower(int n, double* A, int64_t ld, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(zero_lower_kernel, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, s, n, A,
+                     ld);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_row_scale(int m, int n, const double* d, double* A, int64_t lda, hipStream_t s) {
+  if (m == 0 || n == 0) return;
+  hipLaunchKernelGGL(row_scale_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, s, m, n, d,
+                     A, lda);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_col_scale(int m, int n, const double* A, int64_t lda, const double* theta, int mode,
+                      double* B, int64_t ldb, hipStream_t s) {
+  if (m == 0 || n == 0) return;
+  hipLaunchKernelGGL(col_scale_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, s, m, n, A,
+                     lda, theta, mode, B, ldb);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_symmetrize(int n, double* A, int64_t lda, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, s, n, A,
+                     lda);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_set_identity(int m, int n, double* A, int64_t lda, hipStream_t s) {
+  if (m == 0 || n == 0) return;
+  hipLaunchKernelGGL(set_identity_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, s, m, n,
+                     A, lda);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_svqb_theta(int n, double* theta, double tau, int drop, double* scale, int32_t* info,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(svqb_theta_kernel, dim3(1), dim3(256), 0, s, n, theta, tau, drop, scale, info);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_fro_minus_identity(int n, const double* A, int64_t lda, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, n, n, A, lda, 1, out);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_fro(int m, int n, const double* A, int64_t lda, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, m, n, A, lda, 0, out);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_sqrt_sum(int n, const double* v, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sqrt_sum_kernel, dim3(1), dim3(256), 0, s, n, v, out);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+// ---- explicit instantiations
+#define LOBPCG_INST(T)                                                                          \
+  template void launch_spmm<T>(int64_t, const int64_t*, const int32_t*, const T*, const T*,    \
+                               int64_t, T*, int64_t, int, hipStream_t);                         \
+  template void launch_gram<T>(int64_t, int, int, int, const T*, int64_t, const T*, int64_t,   \
+                               const T*, int64_t, double*, int, double*, int, int64_t, int,     \
+                               void*, hipStream_t);                                             \
+  template void launch_update<T>(int64_t, int, int, const T*, int64_t, const double*, int64_t, \
+                                 double, double, T*, int64_t, hipStream_t);                     \
+  template void launch_residual<T>(int64_t, int, const T*, int64_t, const T*, int64_t,         \
+                                   const T*, int64_t, const double*, const double*, T*,         \
+                                   int64_t, double, double, double, double*, int32_t*, void*,   \
+                                   hipStream_t);                                                \
+  template void launch_colsq<T>(int64_t, int, const T*, int64_t, double*, void*, hipStream_t); \
+  template void launch_copy2d_reverse<T>(int64_t, int, const T*, int64_t, T*, int64_t,         \
+                                         hipStream_t);
+LOBPCG_INST(double)
+LOBPCG_INST(float)
+template void launch_copy2d<double, double>(int64_t, int, const double*, int64_t, double*, int64_t,
+                                            hipStream_t);
+template void launch_copy2d<double, float>(int64_t, int, const double*, int64_t, float*, int64_t,
+                                           hipStream_t);
+template void launch_copy2d<float, double>(int64_t, int, const float*, int64_t, double*, int64_t,
+                                           hipStream_t);
+template void launch_copy2d<float, float>(int64_t, int, const float*, int64_t, float*, int64_t,
+                                          hipStream_t);
+
+}  // namespace lobpcg

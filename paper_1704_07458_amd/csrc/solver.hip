@@ -1,0 +1,616 @@
+// Algorithm 8 of arXiv 1704.07458 (robust and efficient LOBPCG) on one GPU.
+//
+// Storage (row-major, device):
+//   S[cur] = [X | P | W]  n x ldS, ping-pong with S[cur^1] for the update
+//            [X, P] = S [C_x, C_p] (section 5.1 writes in place through row
+//            chunks to save memory; with 288 GB of HBM two copies are cheap and
+//            the update needs no chunk buffer).
+//   W is stored with reversed column order (section 5.1), so the unconverged
+//   columns n_c..n_x-1 of R are the first n_x - n_c columns of the W block.
+//   AX, AW (n x ldX): A X is recomputed with the sparse product after every
+//   update by default (explicit products), AW for the Gram blocks.
+//   BXP = [B X | B P], BW when B != I.
+// Projected matrices GA, GB (n_s x n_s, column-major, FP64): the X and P blocks
+// come from eqs. (12)-(14) (Theta, 0, Theta_p, I); only the W columns are
+// computed (Gram kernel), then Algorithm 7 runs on the device in FP64.
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace lobpcg {
+
+namespace {
+constexpr double kEps64 = 2.220446049250313e-16;
+constexpr double kEps32 = 1.1920928955078125e-07;
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void validate_csr(const lobpcg_csr* M, const char* name, int64_t n_expect,
+                  std::vector<int64_t>& rp, std::vector<int32_t>& ci, std::vector<double>& va) {
+  LOBPCG_CHECK(M != nullptr, LOBPCG_ERR_ARG, std::string(name) + " is NULL");
+  LOBPCG_CHECK(M->n > 0, LOBPCG_ERR_ARG, std::string(name) + ": n must be positive");
+  LOBPCG_CHECK(n_expect < 0 || M->n == n_expect, LOBPCG_ERR_ARG,
+               std::string(name) + ": dimension mismatch");
+  LOBPCG_CHECK(M->rowptr && M->colind && M->values, LOBPCG_ERR_ARG,
+               std::string(name) + ": NULL array");
+  const int64_t n = M->n;
+  rp.resize(n + 1);
+  if (M->on_device) {
+    LOBPCG_HIP(hipMemcpy(rp.data(), M->rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(rp.data(), M->rowptr, sizeof(int64_t) * (n + 1));
+  }
+  LOBPCG_CHECK(rp[0] == 0 && rp[n] == M->nnz, LOBPCG_ERR_ARG,
+               std::string(name) + ": rowptr[0] != 0 or rowptr[n] != nnz");
+  const int64_t nnz = M->nnz;
+  ci.resize(nnz);
+  va.resize(nnz);
+  if (M->on_device) {
+    LOBPCG_HIP(hipMemcpy(ci.data(), M->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    LOBPCG_HIP(hipMemcpy(va.data(), M->values, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(ci.data(), M->colind, sizeof(int32_t) * nnz);
+    std::memcpy(va.data(), M->values, sizeof(double) * nnz);
+  }
+  for (int64_t r = 0; r < n; ++r) {
+    LOBPCG_CHECK(rp[r + 1] >= rp[r], LOBPCG_ERR_ARG,
+                 std::string(name) + ": rowptr not monotone at row " + std::to_string(r));
+    for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+      const int32_t c = ci[p];
+      LOBPCG_CHECK(c >= 0 && c < n, LOBPCG_ERR_ARG,
+                   std::string(name) + ": column index out of range in row " + std::to_string(r));
+      LOBPCG_CHECK(p == rp[r] || ci[p - 1] < c, LOBPCG_ERR_ARG,
+                   std::string(name) + ": columns not sorted/unique in row " + std::to_string(r));
+      LOBPCG_CHECK(std::isfinite(va[p]), LOBPCG_ERR_ARG,
+                   std::string(name) + ": non-finite value in row " + std::to_string(r));
+    }
+  }
+}
+
+void upload_csr(DevCsr& D, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                const std::vector<double>& va, bool need32, hipStream_t s) {
+  D.n = (int64_t)rp.size() - 1;
+  D.nnz = (int64_t)ci.size();
+  D.rowptr.alloc(sizeof(int64_t) * rp.size());
+  D.colind.alloc(sizeof(int32_t) * std::max<size_t>(ci.size(), 1));
+  D.v64.alloc(sizeof(double) * std::max<size_t>(va.size(), 1));
+  LOBPCG_HIP(hipMemcpyAsync(D.rowptr.get(), rp.data(), sizeof(int64_t) * rp.size(),
+                            hipMemcpyHostToDevice, s));
+  if (D.nnz) {
+    LOBPCG_HIP(hipMemcpyAsync(D.colind.get(), ci.data(), sizeof(int32_t) * ci.size(),
+                              hipMemcpyHostToDevice, s));
+    LOBPCG_HIP(hipMemcpyAsync(D.v64.get(), va.data(), sizeof(double) * va.size(),
+                              hipMemcpyHostToDevice, s));
+  }
+  if (need32) {
+    D.v32.alloc(sizeof(float) * std::max<size_t>(va.size(), 1));
+    launch_copy2d<double, float>(D.nnz, 1, D.v64.as<double>(), 1, D.v32.as<float>(), 1, s);
+  }
+  LOBPCG_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+}
+}  // namespace
+
+template <typename T>
+void Blocks<T>::alloc(int64_t n, int64_t ldS, int64_t ldX, bool haveB) {
+  const size_t e = sizeof(T);
+  S[0].alloc(e * n * ldS);
+  S[1].alloc(e * n * ldS);
+  AX.alloc(e * n * ldX);
+  AW.alloc(e * n * ldX);
+  U2.alloc(e * n * ldX);
+  R.alloc(e * n * ldX);
+  if (haveB) {
+    BXP.alloc(e * n * 2 * ldX);
+    BW.alloc(e * n * ldX);
+    MU.alloc(e * n * ldX);
+  }
+}
+
+Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_options& opt)
+    : opt_(opt) {
+  s_ = static_cast<hipStream_t>(opt.stream);
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> va;
+  validate_csr(A, "A", -1, rp, ci, va);
+  n_ = A->n;
+  LOBPCG_CHECK(k >= 1, LOBPCG_ERR_ARG, "k must be >= 1");
+  k_ = k;
+  nx_ = opt.block_size > 0 ? opt.block_size : k + (k + 9) / 10;
+  LOBPCG_CHECK(nx_ >= k, LOBPCG_ERR_ARG, "block_size must be >= k");
+  LOBPCG_CHECK(3 * (int64_t)nx_ <= n_, LOBPCG_ERR_ARG, "need 3 * block_size <= n");
+  LOBPCG_CHECK(opt.precision == 0 || opt.precision == 1, LOBPCG_ERR_ARG, "precision must be 0/1");
+  LOBPCG_CHECK(opt.precond >= 0 && opt.precond <= 2, LOBPCG_ERR_ARG, "precond must be 0/1/2");
+  const bool split = opt.precision == 1;
+  // Validate everything on the host before the first device allocation.
+  std::vector<int64_t> brp;
+  std::vector<int32_t> bci;
+  std::vector<double> bva;
+  if (B) validate_csr(B, "B", n_, brp, bci, bva);
+  upload_csr(A_, rp, ci, va, split, s_);
+  if (B) {
+    upload_csr(B_, brp, bci, bva, split, s_);
+    haveB_ = true;
+  }
+  nsmax_ = 3 * nx_;
+  ldS_ = round_up(nsmax_, 16);
+  ldX_ = round_up(nx_, 16);
+  b64_.alloc(n_, ldS_, ldX_, haveB_);
+  if (split) b32_.alloc(n_, ldS_, ldX_, haveB_);
+  const size_t sq = sizeof(double) * (size_t)nsmax_ * nsmax_;
+  GA_.alloc(sq);
+  GB_.alloc(sq);
+  C_.alloc(sizeof(double) * (size_t)nsmax_ * 2 * nx_);
+  theta_.alloc(sizeof(double) * nsmax_);
+  theta_p_.alloc(sizeof(double) * (size_t)nx_ * nx_);
+  rho_.alloc(sizeof(double) * nx_);
+  nc_.alloc(sizeof(int32_t) * 4);
+  nrm_.alloc(sizeof(double) * 8 * nx_);
+  X0buf_.alloc(sizeof(double) * (size_t)n_ * nx_);
+  int64_t ws = gram_workspace_bound(n_, nsmax_, 2 * nx_);
+  ws = std::max(ws, residual_workspace_bytes(n_, nx_));
+  ws = std::max(ws, colsq_workspace_bytes(n_, 2 * nx_));
+  ws = std::max(ws, jacobi_workspace_bytes(n_));
+  work_.alloc(ws);
+  if (opt.precond == 1) {
+    dinv_.alloc(sizeof(double) * n_);
+    launch_jacobi_setup(n_, A_.rowptr.as<int64_t>(), A_.colind.as<int32_t>(), A_.v64.as<double>(),
+                        dinv_.as<double>(), work_.get(), s_);
+  }
+  dense_.reset(new Dense(nsmax_, nx_, s_));
+  LOBPCG_HIP(hipHostMalloc((void**)&hbuf_, sizeof(int32_t) * 8, hipHostMallocDefault));
+  LOBPCG_HIP(hipHostMalloc((void**)&hdbl_, sizeof(double) * 8, hipHostMallocDefault));
+  LOBPCG_HIP(hipStreamSynchronize(s_));
+}
+
+Solver::~Solver() {
+  if (hbuf_) (void)hipHostFree(hbuf_);
+  if (hdbl_) (void)hipHostFree(hdbl_);
+}
+
+KernelTimer::~KernelTimer() {
+  for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+}
+
+void KernelTimer::enable(bool on) {
+  on_ = on;
+  if (on) {
+    for (auto& t : totals) t = lobpcg_kernel_stat{0, 0.0, 0.0};
+    recs_.clear();
+    used_ = 0;
+  }
+}
+
+hipEvent_t KernelTimer::event(size_t i) {
+  while (pool_.size() <= i) {
+    hipEvent_t e;
+    LOBPCG_HIP(hipEventCreate(&e));
+    pool_.push_back(e);
+  }
+  return pool_[i];
+}
+
+int KernelTimer::start(hipStream_t s) {
+  if (!on_) return -1;
+  const int tok = (int)used_++;
+  LOBPCG_HIP(hipEventRecord(event(tok), s));
+  return tok;
+}
+
+void KernelTimer::stop(int token, int kind, double work, hipStream_t s) {
+  if (!on_ || token < 0) return;
+  const int e1 = (int)used_++;
+  LOBPCG_HIP(hipEventRecord(event(e1), s));
+  recs_.push_back(Rec{kind, token, e1, work});
+  if (used_ > 4096) collect();  // bound the pool
+}
+
+void KernelTimer::collect() {
+  if (recs_.empty()) {
+    used_ = 0;
+    return;
+  }
+  LOBPCG_HIP(hipEventSynchronize(pool_[recs_.back().e1]));
+  for (const Rec& r : recs_) {
+    float ms = 0.f;
+    LOBPCG_HIP(hipEventElapsedTime(&ms, pool_[r.e0], pool_[r.e1]));
+    totals[r.kind].launches += 1;
+    totals[r.kind].seconds += 1e-3 * ms;
+    totals[r.kind].work += r.work;
+  }
+  recs_.clear();
+  used_ = 0;
+}
+
+void Solver::sync() { LOBPCG_HIP(hipStreamSynchronize(s_)); }
+
+void Solver::phase_mark(int phase) {
+  if (!profile_ || !phase_acc_) {
+    cur_phase_ = phase;
+    return;
+  }
+  sync();
+  const double t = now_s();
+  phase_acc_[cur_phase_] += t - tmark_;
+  tmark_ = t;
+  cur_phase_ = phase;
+}
+
+template <typename T>
+void Solver::spmm(const DevCsr& M, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols) {
+  if (ncols == 0) return;
+  const T* v;
+  if constexpr (sizeof(T) == 8) v = M.v64.as<T>();
+  else v = M.v32.as<T>();
+  const int tok = timer_.start(s_);
+  launch_spmm<T>(M.n, M.rowptr.as<int64_t>(), M.colind.as<int32_t>(), v, X, ldx, Y, ldy, ncols, s_);
+  const double sv = sizeof(T);
+  timer_.stop(tok, 0, (double)M.nnz * (sv + 4) + 8.0 * (M.n + 1) + 2.0 * M.n * ncols * sv, s_);
+}
+
+template <typename T>
+void Solver::gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const T* R1,
+                  int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,
+                  int64_t ldg, int mirror_rows) {
+  if (m == 0 || p == 0) return;
+  const int tok = timer_.start(s_);
+  launch_gram<T>(n, m, p, p1, L, ldl, R1, ldr1, R2, ldr2, G1, c1, G2, c2, ldg, mirror_rows,
+                 work_.get(), s_);
+  timer_.stop(tok, 1, 2.0 * n * m * p, s_);
+}
+
+template <typename T>
+void Solver::update(int64_t n, int K, int N, const T* S, int64_t lds, const double* C,
+                    int64_t ldc, double alpha, double beta, T* Y, int64_t ldy) {
+  if (N == 0) return;
+  const int tok = timer_.start(s_);
+  launch_update<T>(n, K, N, S, lds, C, ldc, alpha, beta, Y, ldy, s_);
+  timer_.stop(tok, 2, 2.0 * n * K * N, s_);
+}
+
+// Algorithm 5 (orthoDrop) with Algorithms 4 (svqb) and 6 (svqbDrop), metric
+// M = B (or I).  U: n x nu (ldu) in place; V: n x nv (ldv) M-orthonormal external
+// basis with MV = M V (ldmv).  M U is recomputed explicitly after every inner
+// pass (section 5.2: no implicit products inside orthogonalisation).  Returns the
+// number of columns kept.
+template <typename T>
+int Solver::ortho_drop(Blocks<T>& b, const DevCsr* B, T* U, int64_t ldu, int nu, const T* V,
+                       int64_t ldv, const T* MV, int64_t ldmv, int nv, double tau_ortho,
+                       double eps, lobpcg_info* info) {
+  if (info) info->ortho_calls++;
+  const int64_t ldg = nsmax_;
+  double* G = GB_.as<double>();        // scratch: Gram of U (nu x nu)
+  double* Gv = GA_.as<double>();       // scratch: V^T M U (nv x nu)
+  double* Tu = C_.as<double>();        // svqb transform (nu x nkeep, ld nu)
+  double* nrm = nrm_.as<double>();
+  T* U2 = b.U2.template as<T>();
+  T* MU = B ? b.MU.template as<T>() : U;
+  const int64_t ldmu = B ? ldX_ : ldu;
+  // ||MV||_F (for the outer test).
+  double mv_norm = 0.0;
+  if (nv > 0) {
+    launch_colsq<T>(n_, nv, MV, ldmv, nrm, work_.get(), s_);
+    launch_sqrt_sum(nv, nrm, nrm + 4 * nx_, s_);
+    LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx_, sizeof(double), hipMemcpyDeviceToHost, s_));
+    sync();
+    mv_norm = hdbl_[0];
+  }
+  auto gram_u = [&]() {
+    if (B) spmm<T>(*B, U, ldu, MU, ldmu, nu);
+    gram<T>(n_, nu, nu, nu, U, ldu, MU, ldmu, nullptr, 0, G, 0, nullptr, 0, ldg, 0);
+  };
+  double u_norm = 0.0;
+  for (int i = 0; i < 3 && nu > 0; ++i) {
+    // Line 4: U = U - V (V^T M U) (block classical Gram-Schmidt).
+    if (nv > 0) {
+      gram<T>(n_, nv, nu, nu, MV, ldmv, U, ldu, nullptr, 0, Gv, 0, nullptr, 0, ldg, 0);
+      update<T>(n_, nv, nu, V, ldv, Gv, ldg, -1.0, 1.0, U, ldu);
+    }
+    gram_u();
+    for (int j = 0; j < 3 && nu > 0; ++j) {
+      // Lines 6-10: svqb on the first pass, svqbDrop afterwards.
+      const bool drop = j > 0;
+      const double factor = drop ? (opt_.drop_factor > 0 ? opt_.drop_factor : 10.0)
+                                 : (opt_.replace_factor > 0 ? opt_.replace_factor : 10.0);
+      const double tau = factor * nu * eps;
+      const int keep = dense_->svqb_transform(G, ldg, nu, tau, drop, Tu);
+      if (info) info->svqb_calls++;
+      if (keep == 0) return 0;
+      update<T>(n_, nu, keep, U, ldu, Tu, nu, 1.0, 0.0, U2, ldX_);
+      launch_copy2d<T, T>(n_, keep, U2, ldX_, U, ldu, s_);
+      nu = keep;
+      // Line 11: ||U^T M U - I|| / (||MU|| ||U||) with MU recomputed.
+      gram_u();
+      launch_fro_minus_identity(nu, G, ldg, nrm + 4 * nx_, s_);
+      launch_colsq<T>(n_, nu, U, ldu, nrm, work_.get(), s_);
+      launch_sqrt_sum(nu, nrm, nrm + 4 * nx_ + 1, s_);
+      launch_colsq<T>(n_, nu, MU, ldmu, nrm, work_.get(), s_);
+      launch_sqrt_sum(nu, nrm, nrm + 4 * nx_ + 2, s_);
+      LOBPCG_HIP(
+          hipMemcpyAsync(hdbl_, nrm + 4 * nx_, sizeof(double) * 3, hipMemcpyDeviceToHost, s_));
+      sync();
+      u_norm = hdbl_[1];
+      const double err = hdbl_[0] / (hdbl_[2] * hdbl_[1]);
+      if (err <= tau_ortho) break;
+    }
+    if (nv == 0 || nu == 0) break;
+    // Line 12: ||V^T M U|| / (||MV|| ||U||).
+    gram<T>(n_, nv, nu, nu, MV, ldmv, U, ldu, nullptr, 0, Gv, 0, nullptr, 0, ldg, 0);
+    launch_fro(nv, nu, Gv, ldg, nrm + 4 * nx_, s_);
+    LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx_, sizeof(double), hipMemcpyDeviceToHost, s_));
+    sync();
+    const double err = hdbl_[0] / (mv_norm * u_norm);
+    if (err <= tau_ortho) break;
+  }
+  return nu;
+}
+
+template <typename T>
+int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int maxit,
+                const double* X0dev, double tau_skip, double tau_ortho, lobpcg_precond_fn K,
+                void* Kuser, lobpcg_info* info, int* iters_out) {
+  const int64_t n = n_;
+  const int nx = nx_;
+  const int64_t ldS = ldS_, ldX = ldX_, ldBXP = 2 * ldX_;
+  const int64_t ldg = nsmax_, ldc = nsmax_;
+  const double eps = sizeof(T) == 8 ? kEps64 : kEps32;
+  const bool lq_literal = opt_.lq_literal != 0;
+  const bool use_cb = opt_.precond == 2 && K != nullptr;
+  const double* dinv = opt_.precond == 1 ? dinv_.as<double>() : nullptr;
+  double* GA = GA_.as<double>();
+  double* GB = GB_.as<double>();
+  double* C = C_.as<double>();
+  double* theta = theta_.as<double>();
+  double* theta_p = theta_p_.as<double>();
+  T* AX = b.AX.template as<T>();
+  T* AW = b.AW.template as<T>();
+  T* BXP = B ? b.BXP.template as<T>() : nullptr;
+  T* BW = B ? b.BW.template as<T>() : nullptr;
+  T* Rb = b.R.template as<T>();
+  int cur = 0;
+  *iters_out = 0;
+
+  // Algorithm 8 lines 3-4: Rayleigh-Ritz on X0 (Algorithm 2), X = X0 C.
+  phase_mark(7);
+  T* S0 = b.S[0].template as<T>();
+  launch_copy2d<double, T>(n, nx, X0dev, nx, S0, ldS, s_);
+  phase_mark(0);
+  spmm<T>(A, S0, ldS, AX, ldX, nx);
+  if (B) spmm<T>(*B, S0, ldS, BXP, ldBXP, nx);
+  phase_mark(3);
+  gram<T>(n, nx, 2 * nx, nx, S0, ldS, AX, ldX, B ? BXP : S0, B ? ldBXP : ldS, GA, 0, GB, 0,
+                 ldg, 0);
+  phase_mark(4);
+  RROutput o0 = dense_->rr_modified(GA, GB, ldg, nx, nx, 0, false, false, 0.0, C, ldc, theta,
+                                    theta_p, nx);
+  if (o0.flipped)
+    throw Error(LOBPCG_ERR_BREAKDOWN,
+                "Cholesky of the initial block's Gram matrix failed (potrf info " +
+                    std::to_string(o0.potrf_info) + ", trtri info " + std::to_string(o0.trtri_info) +
+                    ", cond " + std::to_string(o0.cond) + ")");
+  phase_mark(5);
+  T* S1 = b.S[1].template as<T>();
+  update<T>(n, nx, nx, S0, ldS, C, ldc, 1.0, 0.0, S1, ldS);
+  cur = 1;
+  // Line 5: R = AX - BX Theta; W = K^-1 R stored reversed after X (P is empty).
+  phase_mark(0);
+  spmm<T>(A, S1, ldS, AX, ldX, nx);
+  if (B) spmm<T>(*B, S1, ldS, BXP, ldBXP, nx);
+  phase_mark(6);
+  int np = 0, nc = 0;
+  launch_residual<T>(n, nx, AX, ldX, B ? BXP : nullptr, ldBXP, S1, ldS, theta, dinv,
+                     use_cb ? Rb : S1 + nx, use_cb ? ldX : ldS, normA_, normB_, tol,
+                     rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
+  bool use_ortho = false;  // line 6
+  int rc = LOBPCG_NOT_CONVERGED;
+  int it = 0;
+  for (it = 1; it <= maxit; ++it) {
+    T* Sc = b.S[cur].template as<T>();
+    T* Sn = b.S[cur ^ 1].template as<T>();
+    const int nv = nx + np;
+    T* W = Sc + nv;
+    int nw = nx - nc;
+    // Lines 8-9 with the preconditioner applied to R (W0 = K^-1 R).
+    if (use_cb) {
+      phase_mark(1);
+      const int st = K(Kuser, n, nw, sizeof(T) == 8 ? 0 : 1, Rb, ldX, W, ldS, (void*)s_);
+      if (st != 0) throw Error(LOBPCG_ERR_CALLBACK, "preconditioner callback returned nonzero");
+    }
+    const T* MV = B ? BXP : Sc;
+    const int64_t ldmv = B ? ldBXP : ldS;
+    if (use_ortho) {
+      phase_mark(2);
+      nw = ortho_drop<T>(b, B, W, ldS, nw, Sc, ldS, MV, ldmv, nv, tau_ortho, eps, info);
+    }
+    RROutput o;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      const int ns = nv + nw;
+      // A W and B W (explicit: every block involving W is computed, section 5.2).
+      phase_mark(0);
+      spmm<T>(A, W, ldS, AW, ldX, nw);
+      if (B) spmm<T>(*B, W, ldS, BW, ldX, nw);
+      // Gram columns of W in S^T A S and S^T B S; the rest from eqs. (12)-(14).
+      phase_mark(3);
+      gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AW, ldX, B ? BW : W,
+                     B ? ldX : ldS, GA, nv, GB, nv, ldg, nv);
+      launch_fill_implicit(nx, np, theta, theta_p, nx, GA, use_ortho ? nullptr : GB, ldg, s_);
+      // Line 11: RayleighRitzModified.
+      phase_mark(4);
+      {
+        const int tok = timer_.start(s_);
+        o = dense_->rr_modified(GA, GB, ldg, ns, nx, nc, use_ortho, lq_literal, tau_skip, C, ldc,
+                                theta, theta_p, nx);
+        timer_.stop(tok, 4, 0.0, s_);
+      }
+      if (!o.flipped) break;
+      // Lines 12-15: switch to orthogonalised W for good and redo the step.
+      use_ortho = true;
+      if (info) {
+        info->flips++;
+        if (info->ortho_switch_iter < 0) info->ortho_switch_iter = info->iterations + it;
+      }
+      phase_mark(2);
+      nw = ortho_drop<T>(b, B, W, ldS, nw, Sc, ldS, MV, ldmv, nv, tau_ortho, eps, info);
+    }
+    if (o.flipped) throw Error(LOBPCG_ERR_BREAKDOWN, "Rayleigh-Ritz failed after orthoDrop");
+    const int ns = nv + nw;
+    const int npn = o.np;
+    // Line 16: [X, P] = S [C_x, C_p].
+    phase_mark(5);
+    update<T>(n, ns, nx + npn, Sc, ldS, C, ldc, 1.0, 0.0, Sn, ldS);
+    cur ^= 1;
+    np = npn;
+    // Line 17: R = AX - BX Theta with A X recomputed (explicit products).
+    phase_mark(0);
+    spmm<T>(A, Sn, ldS, AX, ldX, nx);
+    if (B) {
+      spmm<T>(*B, Sn, ldS, BXP, ldBXP, nx);
+      if (np > 0) spmm<T>(*B, Sn + nx, ldS, BXP + nx, ldBXP, np);
+    }
+    phase_mark(6);
+    {
+      const int tok = timer_.start(s_);
+      launch_residual<T>(n, nx, AX, ldX, B ? BXP : nullptr, ldBXP, Sn, ldS, theta, dinv,
+                         use_cb ? Rb : Sn + nx + np, use_cb ? ldX : ldS, normA_, normB_, tol,
+                         rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
+      timer_.stop(tok, 3, (double)n * nx * sizeof(T) * (B ? 4 : 3) + (dinv ? 8.0 * n : 0.0), s_);
+    }
+    // Line 18: number of converged pairs (leading run meeting criterion 9).
+    LOBPCG_HIP(hipMemcpyAsync(hbuf_, nc_.get(), sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
+    sync();
+    if (hbuf_[1]) throw Error(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
+    nc = hbuf_[0];
+    if (nc >= k_) {
+      rc = LOBPCG_OK;
+      break;
+    }
+    if (nx - nc == 0 && np == 0) throw Error(LOBPCG_ERR_BREAKDOWN, "search space collapsed");
+  }
+  phase_mark(7);
+  *iters_out = std::min(it, maxit);
+  final_nc_ = nc;
+  // Remember where X lives.
+  if constexpr (sizeof(T) == 8) {
+    Xres_ = b.S[cur].template as<double>();
+  } else {
+    launch_copy2d<float, double>(n, nx, b.S[cur].template as<float>(), ldS, X0buf_.as<double>(),
+                                 nx, s_);
+  }
+  return rc;
+}
+
+int Solver::solve(double tol, const double* X0, bool x0_dev, lobpcg_precond_fn K, void* Kuser,
+                  lobpcg_info* info) {
+  LOBPCG_CHECK(tol > 0.0, LOBPCG_ERR_ARG, "tol must be positive");
+  LOBPCG_CHECK(opt_.precond != 2 || K != nullptr, LOBPCG_ERR_ARG,
+               "precond = 2 needs a callback");
+  lobpcg_info local{};
+  lobpcg_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof(*inf));
+  inf->ortho_switch_iter = -1;
+  phase_acc_ = inf->seconds_phase;
+  tmark_ = now_s();
+  cur_phase_ = 7;
+  const double t0 = now_s();
+  solved_ = false;
+  const int64_t n = n_;
+  const int nx = nx_;
+  double* X0b = X0buf_.as<double>();
+  if (X0 == nullptr) {
+    launch_gaussian(n, nx, X0b, nx, opt_.seed, s_);
+  } else {
+    LOBPCG_HIP(hipMemcpyAsync(X0b, X0, sizeof(double) * n * nx,
+                              x0_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s_));
+  }
+  // Section 4.3: ||A||_2 >= ||Omega A||_F / ||Omega||_F with Omega = X0^T.
+  {
+    double* S0 = b64_.S[0].as<double>();
+    double* AX = b64_.AX.as<double>();
+    double* nrm = nrm_.as<double>();
+    launch_copy2d<double, double>(n, nx, X0b, nx, S0, ldS_, s_);
+    spmm<double>(A_, S0, ldS_, AX, ldX_, nx);
+    launch_colsq<double>(n, nx, AX, ldX_, nrm, work_.get(), s_);
+    launch_sqrt_sum(nx, nrm, nrm + 4 * nx, s_);
+    launch_colsq<double>(n, nx, S0, ldS_, nrm, work_.get(), s_);
+    launch_sqrt_sum(nx, nrm, nrm + 4 * nx + 1, s_);
+    if (haveB_) {
+      spmm<double>(B_, S0, ldS_, AX, ldX_, nx);
+      launch_colsq<double>(n, nx, AX, ldX_, nrm, work_.get(), s_);
+      launch_sqrt_sum(nx, nrm, nrm + 4 * nx + 2, s_);
+    }
+    LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx, sizeof(double) * 3, hipMemcpyDeviceToHost, s_));
+    sync();
+    LOBPCG_CHECK(hdbl_[1] > 0.0, LOBPCG_ERR_ARG, "X0 is zero");
+    normA_ = hdbl_[0] / hdbl_[1];
+    normB_ = haveB_ ? hdbl_[2] / hdbl_[1] : 1.0;
+  }
+  inf->norm_A_est = normA_;
+  inf->norm_B_est = normB_;
+  const int maxit = opt_.maxit > 0 ? opt_.maxit : 2000;
+  const double skip = opt_.skip_factor > 0 ? opt_.skip_factor : 10.0;
+  const DevCsr* B = haveB_ ? &B_ : nullptr;
+  int rc = LOBPCG_OK;
+  int iters = 0;
+  if (opt_.precision == 1) {
+    const double tol32 = std::max(opt_.fp32_tol > 0 ? opt_.fp32_tol : 1e-5, tol);
+    rc = run<float>(b32_, A_, B, tol32, maxit, X0b, skip * kEps32, 1e-5, K, Kuser, inf, &iters);
+    inf->fp32_iterations = iters;
+    inf->iterations = iters;
+    // FP64 refinement: Algorithm 8 again, started from the FP32 block (now in X0buf).
+    const int left = std::max(1, maxit - iters);
+    rc = run<double>(b64_, A_, B, tol, left, X0b, skip * kEps64,
+                     opt_.tau_ortho > 0 ? opt_.tau_ortho : 1e-12, K, Kuser, inf, &iters);
+    inf->fp64_iterations = iters;
+    inf->iterations += iters;
+  } else {
+    rc = run<double>(b64_, A_, B, tol, maxit, X0b, skip * kEps64,
+                     opt_.tau_ortho > 0 ? opt_.tau_ortho : 1e-12, K, Kuser, inf, &iters);
+    inf->fp64_iterations = iters;
+    inf->iterations = iters;
+  }
+  sync();
+  timer_.collect();
+  inf->n_converged = final_nc_;
+  inf->seconds_total = now_s() - t0;
+  phase_acc_ = nullptr;
+  solved_ = true;
+  return rc;
+}
+
+int Solver::eigpairs(int count, double* lambda, double* X, int64_t ldx, double* rho,
+                     bool on_device) {
+  LOBPCG_CHECK(solved_, LOBPCG_ERR_STATE, "eigpairs called before a successful solve");
+  LOBPCG_CHECK(count >= 0 && count <= nx_, LOBPCG_ERR_ARG, "count must be in [0, n_x]");
+  if (count == 0) return LOBPCG_OK;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (lambda)
+    LOBPCG_HIP(hipMemcpyAsync(lambda, theta_.get(), sizeof(double) * count, kind, s_));
+  if (rho) LOBPCG_HIP(hipMemcpyAsync(rho, rho_.get(), sizeof(double) * count, kind, s_));
+  if (X) {
+    LOBPCG_CHECK(ldx >= count, LOBPCG_ERR_ARG, "ldx < count");
+    LOBPCG_HIP(hipMemcpy2DAsync(X, sizeof(double) * ldx, Xres_, sizeof(double) * ldS_,
+                                sizeof(double) * count, n_, kind, s_));
+  }
+  sync();
+  return LOBPCG_OK;
+}
+
+template int Solver::run<double>(Blocks<double>&, const DevCsr&, const DevCsr*, double, int,
+                                 const double*, double, double, lobpcg_precond_fn, void*,
+                                 lobpcg_info*, int*);
+template int Solver::run<float>(Blocks<float>&, const DevCsr&, const DevCsr*, double, int,
+                                const double*, double, double, lobpcg_precond_fn, void*,
+                                lobpcg_info*, int*);
+template struct Blocks<double>;
+template struct Blocks<float>;
+
+}  // namespace lobpcg

@@ -1,0 +1,271 @@
+"""Step-by-step parity of the HIP kernels against the oracle's definitions.
+
+Every test runs one entry point of include/lobpcg_steps.h on the GPU and
+compares element by element with a FP64 host computation of the same step.
+Floating-point tolerances are the standard a-priori bounds for a sum of K
+products in any order, |fl(s) - s| <= gamma_K sum |a_k b_k| with
+gamma_K = K u / (1 - K u), taken with a factor 2 of slack.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import lobpcg as L
+from paper_1704_07458_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+def gamma(K, u):
+    return K * u / (1.0 - K * u)
+
+
+def _torch():
+    import torch
+
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch
+
+
+def _dev_csr(M, dtype=np.float64):
+    torch = _torch()
+    return (torch.from_numpy(M.rowptr).cuda(), torch.from_numpy(M.colind).cuda(),
+            torch.from_numpy(M.values.astype(dtype)).cuda())
+
+
+def _ragged_csr(seed, n):
+    """Random symmetric CSR with empty rows and one long row."""
+    rng = np.random.default_rng(seed)
+    R = sp.random(n, n, density=4.0 / n, random_state=rng, format="lil")
+    R[5, :] = rng.standard_normal(n) * (rng.random(n) < 0.5)  # a long row
+    R = sp.csr_matrix(R)
+    R = R + R.T
+    R = sp.lil_matrix(R)
+    for r in (0, 17, n - 1):  # empty rows (and columns)
+        R[r, :] = 0
+        R[:, r] = 0
+    M = sp.csr_matrix(R)
+    M.eliminate_zeros()
+    return P.from_scipy(M)
+
+
+@pytest.mark.parametrize("ncols", [1, 11, 64, 65, 130, 257, 330])
+def test_spmm_fp64_ragged(lib, ncols):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    A = _ragged_csr(1, 777)
+    rp, ci, va = _dev_csr(A)
+    rng = np.random.default_rng(ncols)
+    ld = ncols + 3
+    Xh = rng.standard_normal((A.n, ld))
+    X = torch.from_numpy(Xh).cuda()[:, :ncols]
+    Y = torch.full((A.n, ld), np.nan, dtype=torch.float64, device="cuda")[:, :ncols]
+    B.spmm(rp, ci, va, X, Y)
+    got = Y.cpu().numpy()
+    As = A.to_scipy()
+    ref = L.Operator(As)(Xh[:, :ncols])
+    bound = 2 * gamma(int(np.diff(A.rowptr).max()), U64) * (abs(As) @ np.abs(Xh[:, :ncols]))
+    assert np.all(np.abs(got - ref) <= bound + 1e-300)
+    # empty rows give exact zeros
+    assert np.all(got[[0, 17, A.n - 1]] == 0.0)
+
+
+def test_spmm_fp32(lib):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    A = P.laplacian_3d(10)
+    rp, ci, va = _dev_csr(A, np.float32)
+    rng = np.random.default_rng(0)
+    X32 = rng.standard_normal((A.n, 100)).astype(np.float32)
+    Y = B.spmm(rp, ci, va, torch.from_numpy(X32).cuda())
+    As = A.to_scipy()
+    ref = As @ X32.astype(np.float64)
+    bound = 2 * gamma(7, U32) * (abs(As) @ np.abs(X32.astype(np.float64)))
+    assert np.all(np.abs(Y.cpu().numpy() - ref) <= bound)
+
+
+@pytest.mark.parametrize("n,m,p,p1", [(1000, 33, 22, 22), (5003, 130, 70, 40), (300, 7, 5, 5),
+                                      (20000, 65, 128, 64)])
+def test_gram_fp64(lib, n, m, p, p1):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(n + m)
+    Lh = rng.standard_normal((n, m + 5))
+    R1h = rng.standard_normal((n, p1 + 2))
+    R2h = rng.standard_normal((n, max(p - p1, 1) + 1))
+    Lt = torch.from_numpy(Lh).cuda()[:, :m]
+    R1 = torch.from_numpy(R1h).cuda()[:, :p1]
+    R2 = torch.from_numpy(R2h).cuda()[:, :p - p1] if p > p1 else None
+    G = B.gram(Lt, R1, R2).cpu().numpy()
+    Rh = np.hstack([R1h[:, :p1], R2h[:, :p - p1]]) if p > p1 else R1h[:, :p1]
+    ref = Lh[:, :m].T @ Rh
+    bound = 2 * gamma(n, U64) * (np.abs(Lh[:, :m]).T @ np.abs(Rh))
+    assert np.all(np.abs(G - ref) <= bound)
+
+
+def test_gram_mirror_and_determinism(lib):
+    """Symmetric completion of S^T [S(:, W)] as the solver does it, bitwise repeatable."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(3)
+    n, m, w = 4099, 40, 12
+    Sh = rng.standard_normal((n, m))
+    S = torch.from_numpy(Sh).cuda()
+    G1 = B.gram(S, S[:, m - w:], col_offset=m - w, mirror=True).cpu().numpy()
+    G2 = B.gram(S, S[:, m - w:], col_offset=m - w, mirror=True).cpu().numpy()
+    assert np.array_equal(G1, G2)  # deterministic two-stage sum, no atomics
+    ref = Sh.T @ Sh
+    bound = 2 * gamma(n, U64) * (np.abs(Sh).T @ np.abs(Sh))
+    # computed columns and their mirrored rows; the leading (m-w) square stays untouched
+    assert np.all(np.abs(G1[:, m - w:] - ref[:, m - w:]) <= bound[:, m - w:])
+    assert np.all(np.abs(G1[m - w:, :m - w] - ref[m - w:, :m - w]) <= bound[m - w:, :m - w])
+    assert np.all(G1[:m - w, :m - w] == 0.0)
+
+
+def test_gram_fp32_accumulation(lib):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(4)
+    n, m, p = 30000, 50, 20
+    L32 = rng.standard_normal((n, m)).astype(np.float32)
+    R32 = rng.standard_normal((n, p)).astype(np.float32)
+    G = B.gram(torch.from_numpy(L32).cuda(), torch.from_numpy(R32).cuda()).cpu().numpy()
+    L64, R64 = L32.astype(np.float64), R32.astype(np.float64)
+    ref = L64.T @ R64
+    bound = 2 * gamma(n, U32) * (np.abs(L64).T @ np.abs(R64))
+    assert np.all(np.abs(G - ref) <= bound)
+
+
+@pytest.mark.parametrize("n,K,N", [(1000, 33, 22), (4097, 330, 220), (70, 5, 3), (2000, 130, 65)])
+def test_update_fp64(lib, n, K, N):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(K)
+    Sh = rng.standard_normal((n, K + 4))
+    Ch = rng.standard_normal((K, N))
+    S = torch.from_numpy(Sh).cuda()[:, :K]
+    Y = B.update(S, torch.from_numpy(Ch).cuda()).cpu().numpy()
+    ref = Sh[:, :K] @ Ch
+    bound = 2 * gamma(K, U64) * (np.abs(Sh[:, :K]) @ np.abs(Ch))
+    assert np.all(np.abs(Y - ref) <= bound)
+    # beta = 1, alpha = -1 (the Gram-Schmidt form U <- U - V G)
+    Y0h = rng.standard_normal((n, N))
+    Y0 = torch.from_numpy(Y0h).cuda()
+    B.update(S, torch.from_numpy(Ch).cuda(), Y0, alpha=-1.0, beta=1.0)
+    ref2 = Y0h - Sh[:, :K] @ Ch
+    assert np.all(np.abs(Y0.cpu().numpy() - ref2) <= bound + 2 * U64 * np.abs(Y0h))
+
+
+def test_update_fp32(lib):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(9)
+    n, K, N = 3000, 96, 70
+    S32 = rng.standard_normal((n, K)).astype(np.float32)
+    Ch = rng.standard_normal((K, N))
+    Y = B.update(torch.from_numpy(S32).cuda(), torch.from_numpy(Ch).cuda()).cpu().numpy()
+    C32 = Ch.astype(np.float32).astype(np.float64)  # C is rounded to FP32 in the kernel
+    ref = S32.astype(np.float64) @ C32
+    bound = 2 * gamma(K, U32) * (np.abs(S32.astype(np.float64)) @ np.abs(C32))
+    assert np.all(np.abs(Y - ref) <= bound)
+
+
+def test_residual_and_criterion9(lib):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(5)
+    A = P.add_diagonal(P.laplacian_3d(9), rng.uniform(0, 4, 729)).to_scipy()
+    n, nx = 729, 13
+    X = rng.standard_normal((n, nx))
+    AX = A @ X
+    theta = np.sort(rng.uniform(0.1, 3, nx))
+    dinv = 1.0 / L.jacobi_diagonal(A)
+    ldw = nx + 3
+    Wt = torch.zeros((n, ldw), dtype=torch.float64, device="cuda")
+    rho, nc = B.residual(torch.from_numpy(AX).cuda(), torch.from_numpy(X).cuda(),
+                         torch.from_numpy(theta).cuda(), dinv=torch.from_numpy(dinv).cuda(),
+                         W=Wt[:, :nx], normA=11.5, normB=1.0, tol=1e300)
+    R = AX - X * theta
+    ref_rho = L.criterion9(R, X, theta, 11.5, 1.0)
+    assert np.allclose(rho.cpu().numpy(), ref_rho, rtol=1e-13, atol=0)
+    W = Wt.cpu().numpy()[:, :nx]
+    refW = (R * dinv[:, None])[:, ::-1]  # reversed column order
+    assert np.allclose(W, refW, rtol=1e-14, atol=1e-14 * np.abs(refW).max())
+    assert nc.cpu().numpy()[0] == nx and nc.cpu().numpy()[1] == 0
+    # leading run: the third column fails
+    tol = np.sort(ref_rho)[0] * 0.999
+    ref_rho_mod = ref_rho.copy()
+    rho2, nc2 = B.residual(torch.from_numpy(AX).cuda(), torch.from_numpy(X).cuda(),
+                           torch.from_numpy(theta).cuda(), normA=11.5, normB=1.0,
+                           tol=float(max(ref_rho[0], ref_rho[1]) * 1.0000001))
+    ok = ref_rho_mod <= max(ref_rho[0], ref_rho[1]) * 1.0000001
+    expect = int(np.argmin(ok)) if not ok.all() else nx
+    assert nc2.cpu().numpy()[0] == expect
+    del tol
+
+
+def _signs_match(a, b, tol):
+    """Columns of a equal +-columns of b; returns the sign vector."""
+    s = np.sign(np.sum(a * b, axis=0))
+    s[s == 0] = 1
+    assert np.max(np.abs(a - b * s)) <= tol * max(1.0, np.abs(b).max())
+    return s
+
+
+@pytest.mark.parametrize("n_c,use_ortho,literal", [(0, False, False), (3, False, False),
+                                                   (2, True, False), (3, False, True)])
+def test_rr_step_against_oracle(lib, n_c, use_ortho, literal):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(11 + n_c)
+    n, n_x, n_s = 400, 9, 25
+    A = P.random_sparse_spd(7, n, 0.03).to_scipy()
+    S = rng.standard_normal((n, n_s))
+    if use_ortho:
+        S, _ = np.linalg.qr(S)
+    GA, GB = S.T @ (A @ S), S.T @ S
+    GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+    tol = L.Tolerances()
+    ref = L.rayleigh_ritz_modified(GA, GB, n_x, n_c, use_ortho, tol, literal_lq=literal)
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), n_x, n_c, use_ortho,
+                    tol.tau_skip, literal)
+    assert not got["flipped"] and not ref.flipped
+    th = got["theta"].cpu().numpy()
+    assert np.allclose(th, ref.theta_all, rtol=1e-11, atol=1e-12 * np.abs(th).max())
+    assert got["n_p"] == ref.Cp.shape[1]
+    Cx = got["Cx"].cpu().numpy()
+    _signs_match(Cx, ref.Cx, 1e-9)
+    Cp = got["Cp"].cpu().numpy()
+    s = _signs_match(Cp, ref.Cp, 1e-8)
+    tp = got["theta_p"].cpu().numpy()
+    assert np.allclose(tp, np.outer(s, s) * ref.theta_p, atol=1e-9 * np.abs(th).max())
+    if not use_ortho:
+        assert got["cond"] == pytest.approx(ref.cond_R, rel=1e-8)
+
+
+def test_rr_step_flags_ill_conditioned(lib):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(5)
+    n = 80
+    S = rng.standard_normal((n, 6))
+    S = np.hstack([S, S[:, :2] + 1e-9 * rng.standard_normal((n, 2))])
+    A = P.random_sparse_spd(3, n, 0.1).to_scipy()
+    GA, GB = S.T @ (A @ S), S.T @ S
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), 3, 0, False,
+                    L.Tolerances().tau_skip)
+    assert got["flipped"] and got["cond"] > 1e5
