@@ -92,6 +92,31 @@ def cpu_baseline(w, iters, gpu_iters):
     }
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_1704_07458_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary.
+
+    profiles/<kernel>_kernel_laplace64_k100_hbm_traffic.txt (JSON) holds FETCH_SIZE and
+    WRITE_SIZE per dispatch
+    (KiB), the copy-kernel calibration factor and the hash of kernels.hip the
+    counters were taken with; a different hash means the kernel changed since,
+    and the traffic is unknown (None).
+    """
+    path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_laplace64_k100_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    return d["hbm_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +125,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=5)
     ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 4 plain device copies of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--phases", action="store_true",
+                    help="one extra untimed FP64 solve with per-phase timing (stream syncs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -107,6 +136,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": nbytes, "copies": 4}), flush=True)
+        return
 
     from oracle import closed_forms as cf
     from paper_1704_07458_amd import binding as B
@@ -125,6 +165,14 @@ def main():
     lam64_h, X64_h = lam64.cpu().numpy(), X64.cpu().numpy()
     rho64, err64 = check_solution(w, lam64_h, X64_h, infos64[-1]["norm_A_est"], exact)
     iters64 = infos64[-1]["iterations"]
+
+    phases = None
+    if args.phases:
+        s64.set_profiling(True)
+        pinfo = s64.solve(w.tol, X0)
+        s64.set_profiling(False)
+        phases = pinfo["seconds_phase"]
+        _log(f"[bench] phases: {phases}")
 
     split = None
     if not args.no_split:
@@ -162,7 +210,7 @@ def main():
     dom = max(per_kernel, key=lambda k: per_kernel[k]["seconds"])
     roof = dict(per_kernel[dom])
     roof["kernel"] = dom
-    roof["traffic"] = None
+    roof["traffic"] = traffic_from_profiles(dom)
     total_kernel_s = sum(v["seconds"] for v in st64.values())
     cpu = None
     if not args.no_cpu:
@@ -200,6 +248,7 @@ def main():
         "rayleigh_ritz_seconds": st64["rayleigh_ritz"]["seconds"],
         "kernel_time_share": {k: v["seconds"] / (t64 * args.steps) for k, v in st64.items()},
         "cpu_baseline": cpu,
+        "phases_fp64_s": phases,
     }
     del total_kernel_s
     print(json.dumps(out), flush=True)

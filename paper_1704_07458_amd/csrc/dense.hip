@@ -5,6 +5,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <string>
 
@@ -21,6 +22,7 @@ namespace lobpcg {
   } while (0)
 
 Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax), s_(s) {
+  if (const char* e = std::getenv("LOBPCG_EIGENSOLVER")) eig_ = std::atoi(e);
   LOBPCG_ROCBLAS(rocblas_create_handle(&h_));
   LOBPCG_ROCBLAS(rocblas_set_stream(h_, s_));
   const size_t sq = sizeof(double) * (size_t)nsmax * nsmax;
@@ -32,7 +34,7 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax)
   ZQ_.alloc(sq);
   Qs_.alloc(sq);
   d_.alloc(sizeof(double) * nsmax);
-  E_.alloc(sizeof(double) * nsmax);
+  E_.alloc(sizeof(double) * 2 * nsmax);
   tau_.alloc(sizeof(double) * nsmax);
   th2_.alloc(sizeof(double) * nsmax);
   scale_.alloc(sizeof(double) * nsmax);
@@ -59,7 +61,13 @@ void Dense::gemm(rocblas_operation ta, rocblas_operation tb, int m, int n, int k
 
 void Dense::syev(int n, double* A, int64_t lda, double* w) {
   int32_t* dinfo = info_.as<int32_t>() + 2;
-  if (eig_ == 1) {
+  if (eig_ == 2) {
+    // Jacobi (sorted ascending), tolerance at the level of rounding.
+    double* resid = cond_.as<double>() + 1;
+    LOBPCG_ROCBLAS(rocsolver_dsyevj(h_, rocblas_esort_ascending, rocblas_evect_original,
+                                    rocblas_fill_upper, n, A, (rocblas_int)lda, 0.0, resid, 100,
+                                    dinfo + 1, w, dinfo));
+  } else if (eig_ == 1) {
     LOBPCG_ROCBLAS(rocsolver_dsyevdj(h_, rocblas_evect_original, rocblas_fill_upper, n, A,
                                      (rocblas_int)lda, w, dinfo));
   } else {
@@ -97,7 +105,7 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
         rocsolver_dtrtri(h_, rocblas_fill_upper, rocblas_diagonal_non_unit, ns, T, (rocblas_int)ld,
                          dinfo + 1));
     launch_zero_lower(ns, T, ld, s_);
-    launch_cond1_upper(ns, R, T, ld, cond_.as<double>(), s_);
+    launch_cond1_upper(ns, R, T, ld, cond_.as<double>(), E_.as<double>(), s_);
     LOBPCG_HIP(hipMemcpyAsync(hinfo_, dinfo, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipMemcpyAsync(hcond_, cond_.get(), sizeof(double), hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipStreamSynchronize(s_));

@@ -47,7 +47,8 @@ class Dense {
   rocblas_handle handle() const { return h_; }
   hipStream_t stream() const { return s_; }
 
-  // Eigen-solver selection for the projected problem (0 = syevd, 1 = syevdj).
+  // Eigen-solver selection for the projected problem (0 = syevd, 1 = syevdj,
+  // 2 = syevj); the environment variable LOBPCG_EIGENSOLVER overrides the default.
   void set_eigensolver(int which) { eig_ = which; }
 
  private:

@@ -128,104 +128,118 @@ struct Mfma<float> {
 };
 
 // ------------------------------------------------------------------ Gram
-// Workgroup tile 64 (m) x 64 (p): 2 x 2 waves, each wave 32 x 32 = 2 x 2 MFMA
-// blocks.  Grid: x = nsplit * tiles (tile index fastest).  Each workgroup sums
-// its row range [k0, k1) and writes a partial tile to part[split][i][j].
-constexpr int kGramTM = 64, kGramTP = 64;
+// Workgroup tile 128 (m) x 128 (p): 2 x 2 waves, each wave a 64 x 64 register
+// tile of 4 x 4 MFMA 16x16x4 blocks.  The row range is consumed in stages of
+// kKB rows: each stage's L and R tiles are loaded with coalesced global loads
+// into registers while the previous stage is multiplied out of LDS, then
+// stored to the other LDS buffer (double buffering, one barrier per stage).
+// Grid: x = nsplit * tiles (tile index fastest, so workgroups that share a row
+// range land together on one XCD).  Each workgroup sums its row range [k0, k1)
+// and writes a partial tile to part[split][i][j].
+constexpr int kGramTM = 128, kGramTP = 128, kKB = 16, kLdsPad = 2;
 
 template <typename T>
-__global__ __launch_bounds__(256) void gram_partial_kernel(
+__global__ __launch_bounds__(256, 2) void gram_partial_kernel(
     int64_t n, int m, int p, int p1, const T* __restrict__ L, int64_t ldl,
     const T* __restrict__ R1, int64_t ldr1, const T* __restrict__ R2, int64_t ldr2,
     double* __restrict__ part, int tiles_m, int tiles_p, int64_t rows_per_split) {
   using acc_t = typename Mfma<T>::acc_t;
+  __shared__ T Ls[2][kKB][kGramTM + kLdsPad];
+  __shared__ T Rs[2][kKB][kGramTP + kLdsPad];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int ntiles = tiles_m * tiles_p;
   const int split = lb / ntiles;
   const int tile = lb % ntiles;
   const int tm = tile / tiles_p, tp = tile % tiles_p;
-  const int wave = uniform(threadIdx.x / kWave);
-  const int lane = threadIdx.x % kWave;
+  const int tid = threadIdx.x;
+  const int wave = uniform(tid / kWave);
+  const int lane = tid % kWave;
   const int wm = wave >> 1, wp = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
 
   const int64_t k0 = (int64_t)split * rows_per_split;
   const int64_t k1 = k0 + rows_per_split < n ? k0 + rows_per_split : n;
 
-  // Column of L (A operand) and of R (B operand) this lane reads, per block.
-  int colA[2], colB[2];
-  bool okA[2], okB[2];
-  const T* baseB[2];
-  int64_t ldB[2];
-#pragma unroll
-  for (int f = 0; f < 2; ++f) {
-    colA[f] = tm * kGramTM + wm * 32 + f * 16 + li;
-    okA[f] = colA[f] < m;
-    const int cb = tp * kGramTP + wp * 32 + f * 16 + li;
-    okB[f] = cb < p;
-    if (cb < p1) {
-      baseB[f] = R1 + cb;
-      ldB[f] = ldr1;
-    } else {
-      baseB[f] = R2 + (cb - p1);
-      ldB[f] = ldr2;
-    }
-    colB[f] = cb;
+  // Global-load assignment: thread owns column c of the tile and rows r0 + 2i.
+  const int c = tid % kGramTM;
+  const int r0 = tid / kGramTM;
+  const int ca = tm * kGramTM + c;
+  const bool okA = ca < m;
+  const T* colA = L + (okA ? ca : 0);
+  const int cb = tp * kGramTP + c;
+  const bool okB = cb < p;
+  const T* colB;
+  int64_t ldB;
+  if (cb < p1) {
+    colB = R1 + cb;
+    ldB = ldr1;
+  } else {
+    colB = R2 + (okB ? cb - p1 : 0);
+    ldB = ldr2;
   }
+  constexpr int kPer = kKB / 2;  // rows per thread per stage
+  T ga[kPer], gb[kPer];
+  auto gload = [&](int64_t kb) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int64_t row = kb + r0 + 2 * i;
+      const bool rok = row < k1;
+      ga[i] = (rok && okA) ? colA[row * ldl] : T(0);
+      gb[i] = (rok && okB) ? colB[row * ldB] : T(0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      Ls[buf][r0 + 2 * i][c] = ga[i];
+      Rs[buf][r0 + 2 * i][c] = gb[i];
+    }
+  };
 
-  acc_t acc[2][2];
+  acc_t acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-  // Main loop: 4 rows per MFMA step, two steps per iteration so that the loads
-  // of the second step are in flight while the first step's MFMAs issue.
-  int64_t k = k0;
-  for (; k + 8 <= k1; k += 8) {
-    T a[2][2], b[2][2];
+  const int64_t nst = (k1 - k0 + kKB - 1) / kKB;
+  if (nst > 0) {
+    gload(k0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    const int buf = (int)(st & 1);
+    const bool more = st + 1 < nst;
+    if (more) gload(k0 + (st + 1) * kKB);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int64_t row = k + 4 * s + lk;
+    for (int s = 0; s < kKB / 4; ++s) {
+      T a[4], b[4];
 #pragma unroll
-      for (int f = 0; f < 2; ++f) {
-        a[s][f] = okA[f] ? L[row * ldl + colA[f]] : T(0);
-        b[s][f] = okB[f] ? baseB[f][row * ldB[f]] : T(0);
+      for (int f = 0; f < 4; ++f) {
+        a[f] = Ls[buf][4 * s + lk][wm * 64 + f * 16 + li];
+        b[f] = Rs[buf][4 * s + lk][wp * 64 + f * 16 + li];
       }
+#pragma unroll
+      for (int fa = 0; fa < 4; ++fa)
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
     }
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int fa = 0; fa < 2; ++fa)
-#pragma unroll
-        for (int fb = 0; fb < 2; ++fb) acc[fa][fb] = Mfma<T>::mma(a[s][fa], b[s][fb], acc[fa][fb]);
-  }
-  for (; k < k1; k += 4) {
-    const int64_t row = k + lk;
-    const bool rok = row < k1;
-    T a[2], b[2];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      a[f] = (rok && okA[f]) ? L[row * ldl + colA[f]] : T(0);
-      b[f] = (rok && okB[f]) ? baseB[f][row * ldB[f]] : T(0);
-    }
-#pragma unroll
-    for (int fa = 0; fa < 2; ++fa)
-#pragma unroll
-      for (int fb = 0; fb < 2; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
   }
 
   // Store the partial tile (FP64).
   double* out = part + (int64_t)split * m * p;
 #pragma unroll
-  for (int fa = 0; fa < 2; ++fa)
+  for (int fa = 0; fa < 4; ++fa)
 #pragma unroll
-    for (int fb = 0; fb < 2; ++fb) {
-      const int j = colB[fb];
+    for (int fb = 0; fb < 4; ++fb) {
+      const int j = tp * kGramTP + wp * 64 + fb * 16 + li;
       if (j >= p) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = tm * kGramTM + wm * 32 + fa * 16 + Mfma<T>::row(lk, q);
+        const int i = tm * kGramTM + wm * 64 + fa * 16 + Mfma<T>::row(lk, q);
         if (i < m) out[(int64_t)i * p + j] = (double)acc[fa][fb][q];
       }
     }
@@ -243,8 +257,17 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int p1, 
   const int64_t mp = (int64_t)m * p;
   if (idx >= mp) return;
   const int i = (int)(idx / p), j = (int)(idx % p);
-  double s = 0.0;
-  for (int t = 0; t < nsplit; ++t) s += part[(int64_t)t * mp + idx];
+  // Four independent accumulators (more loads in flight), combined in a fixed order.
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int t = 0;
+  for (; t + 4 <= nsplit; t += 4) {
+    s0 += part[(int64_t)t * mp + idx];
+    s1 += part[(int64_t)(t + 1) * mp + idx];
+    s2 += part[(int64_t)(t + 2) * mp + idx];
+    s3 += part[(int64_t)(t + 3) * mp + idx];
+  }
+  for (; t < nsplit; ++t) s0 += part[(int64_t)t * mp + idx];
+  const double s = (s0 + s1) + (s2 + s3);
   double* G = j < p1 ? G1 : G2;
   const int c = j < p1 ? c1 + j : c2 + (j - p1);
   G[i + (int64_t)c * ldg] = s;
@@ -256,18 +279,19 @@ struct GramPlan {
   int64_t rows_per_split;
 };
 
+constexpr int kGramTargetBlocks = 512;
+
 GramPlan gram_plan(int64_t n, int m, int p) {
   GramPlan g;
   g.tiles_m = (m + kGramTM - 1) / kGramTM;
   g.tiles_p = (p + kGramTP - 1) / kGramTP;
   const int ntiles = g.tiles_m * g.tiles_p;
-  // Aim for about 2048 workgroups (8 per CU) with at least 256 rows each.
-  int64_t target = std::max<int64_t>(1, 2048 / std::max(ntiles, 1));
+  // About kGramTargetBlocks workgroups (2 per CU) with at least 256 rows each.
+  int64_t target = std::max<int64_t>(1, kGramTargetBlocks / std::max(ntiles, 1));
   int64_t max_by_rows = std::max<int64_t>(1, n / 256);
   int64_t ns = std::min(target, max_by_rows);
-  ns = std::min<int64_t>(ns, 1024);
   int64_t rps = (n + ns - 1) / ns;
-  rps = round_up(std::max<int64_t>(rps, 8), 8);
+  rps = round_up(std::max<int64_t>(rps, kKB), kKB);
   g.nsplit = (int)((n + rps - 1) / rps);
   if (g.nsplit < 1) g.nsplit = 1;
   g.rows_per_split = rps;
@@ -275,89 +299,102 @@ GramPlan gram_plan(int64_t n, int m, int p) {
 }
 
 // ------------------------------------------------------------------ update
-// Y tile 64 rows x 64 cols per workgroup: 2 x 2 waves, each 32 x 32.
+// Y tile 128 rows x 128 cols per workgroup: 2 x 2 waves, each a 64 x 64
+// register tile of 4 x 4 MFMA blocks.  K is consumed in stages of kKB: the
+// S tile (128 rows x kKB, row segments of kKB contiguous elements) and the C
+// tile (kKB x 128, column segments of C, which is column-major) go through
+// double-buffered LDS as in the Gram kernel.
 // Grid: x = row tiles * col tiles (col tile fastest).
-constexpr int kUpdTM = 64, kUpdTN = 64;
+constexpr int kUpdTM = 128, kUpdTN = 128, kUpdPad = 1;
 
 template <typename T>
-__global__ __launch_bounds__(256) void update_kernel(int64_t n, int K, int N,
+__global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
                                                      const T* __restrict__ S, int64_t lds,
                                                      const double* __restrict__ C, int64_t ldc,
                                                      T alpha, int beta1, T* __restrict__ Y,
                                                      int64_t ldy, int tiles_n) {
   using acc_t = typename Mfma<T>::acc_t;
+  __shared__ T Ss[2][kUpdTM][kKB + kUpdPad];
+  __shared__ T Cs[2][kUpdTN][kKB + kUpdPad];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t tr = lb / tiles_n;
   const int tc = lb % tiles_n;
-  const int wave = uniform(threadIdx.x / kWave);
-  const int lane = threadIdx.x % kWave;
+  const int tid = threadIdx.x;
+  const int wave = uniform(tid / kWave);
+  const int lane = tid % kWave;
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
 
-  int64_t rowA[2];
-  bool okA[2];
-  int colB[2];
-  bool okB[2];
+  // Global-load assignment: thread owns k offset kk of the stage and rows
+  // (or columns) q0 + 16 i, i = 0..7.
+  const int kk = tid % kKB;
+  const int q0 = tid / kKB;
+  constexpr int kPer = kUpdTM / 16;
+  const int rows_valid = (int)(n - tr * kUpdTM < kUpdTM ? n - tr * kUpdTM : kUpdTM);
+  const int cols_valid = N - tc * kUpdTN < kUpdTN ? N - tc * kUpdTN : kUpdTN;
+  const T* sbase = S + (tr * kUpdTM + q0) * lds + kk;
+  const double* cbase = C + (int64_t)(tc * kUpdTN + q0) * ldc + kk;
+  const int64_t sstep = 16 * lds, cstep = 16 * ldc;
+  T gs[kPer], gc[kPer];
+  auto gload = [&](int kb) {
+    const bool kok = kb + kk < K;
 #pragma unroll
-  for (int f = 0; f < 2; ++f) {
-    rowA[f] = tr * kUpdTM + wr * 32 + f * 16 + li;
-    okA[f] = rowA[f] < n;
-    colB[f] = tc * kUpdTN + wc * 32 + f * 16 + li;
-    okB[f] = colB[f] < N;
+    for (int i = 0; i < kPer; ++i) {
+      const int q = q0 + 16 * i;
+      gs[i] = (kok && q < rows_valid) ? sbase[i * sstep + kb] : T(0);
+      gc[i] = (kok && q < cols_valid) ? (T)cbase[i * cstep + kb] : T(0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      Ss[buf][q0 + 16 * i][kk] = gs[i];
+      Cs[buf][q0 + 16 * i][kk] = gc[i];
+    }
+  };
+
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  const int nst = (K + kKB - 1) / kKB;
+  if (nst > 0) {
+    gload(0);
+    sstore(0);
   }
-  const T* srow[2] = {S + (okA[0] ? rowA[0] : 0) * lds, S + (okA[1] ? rowA[1] : 0) * lds};
-  const double* ccol[2] = {C + (int64_t)(okB[0] ? colB[0] : 0) * ldc,
-                           C + (int64_t)(okB[1] ? colB[1] : 0) * ldc};
-
-  acc_t acc[2][2];
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nst;
+    if (more) gload((st + 1) * kKB);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int s = 0; s < kKB / 4; ++s) {
+      T a[4], b[4];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-
-  int k = 0;
-  for (; k + 8 <= K; k += 8) {
-    T a[2][2], b[2][2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int kk = k + 4 * s + lk;
-#pragma unroll
-      for (int f = 0; f < 2; ++f) {
-        a[s][f] = okA[f] ? srow[f][kk] : T(0);
-        b[s][f] = okB[f] ? (T)ccol[f][kk] : T(0);
+      for (int f = 0; f < 4; ++f) {
+        a[f] = Ss[buf][wr * 64 + f * 16 + li][4 * s + lk];
+        b[f] = Cs[buf][wc * 64 + f * 16 + li][4 * s + lk];
       }
+#pragma unroll
+      for (int fa = 0; fa < 4; ++fa)
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
     }
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int fa = 0; fa < 2; ++fa)
-#pragma unroll
-        for (int fb = 0; fb < 2; ++fb) acc[fa][fb] = Mfma<T>::mma(a[s][fa], b[s][fb], acc[fa][fb]);
-  }
-  for (; k < K; k += 4) {
-    const int kk = k + lk;
-    const bool kok = kk < K;
-    T a[2], b[2];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      a[f] = (kok && okA[f]) ? srow[f][kk] : T(0);
-      b[f] = (kok && okB[f]) ? (T)ccol[f][kk] : T(0);
-    }
-#pragma unroll
-    for (int fa = 0; fa < 2; ++fa)
-#pragma unroll
-      for (int fb = 0; fb < 2; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
   }
 
 #pragma unroll
-  for (int fa = 0; fa < 2; ++fa)
+  for (int fa = 0; fa < 4; ++fa)
 #pragma unroll
-    for (int fb = 0; fb < 2; ++fb) {
-      const int j = colB[fb];
-      if (!okB[fb]) continue;
+    for (int fb = 0; fb < 4; ++fb) {
+      const int j = tc * kUpdTN + wc * 64 + fb * 16 + li;
+      if (j >= N) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t r = tr * kUpdTM + wr * 32 + fa * 16 + Mfma<T>::row(lk, q);
+        const int64_t r = tr * kUpdTM + wr * 64 + fa * 16 + Mfma<T>::row(lk, q);
         if (r < n) {
           T v = alpha * acc[fa][fb][q];
           if (beta1) v += Y[r * ldy + j];
@@ -409,22 +446,43 @@ __global__ __launch_bounds__(256) void residual_kernel(
   }
 }
 
-// One workgroup: rho_j, the leading run n_c[0] and a non-finite flag n_c[1].
-__global__ __launch_bounds__(256) void residual_finish_kernel(
+// Deterministic sum of column j's nblocks partials: one workgroup per column,
+// each thread sums a fixed strided subset, then a fixed-order tree in LDS.
+__device__ __forceinline__ double block_sum_column(const double* __restrict__ part, int ncols,
+                                                   int nblocks, int j, double* sbuf) {
+  double a = 0.0;
+  for (int t = threadIdx.x; t < nblocks; t += blockDim.x) a += part[(int64_t)t * ncols + j];
+  sbuf[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sbuf[threadIdx.x] += sbuf[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sbuf[0];
+  __syncthreads();
+  return r;
+}
+
+// Grid: one workgroup per column.  rho_j of eq. (9).
+__global__ __launch_bounds__(256) void residual_rho_kernel(
     int nx, int nblocks, const double* __restrict__ part_r, const double* __restrict__ part_x,
-    const double* __restrict__ theta, double normA, double normB, double tol,
-    double* __restrict__ rho, int32_t* __restrict__ n_c) {
+    const double* __restrict__ theta, double normA, double normB, double* __restrict__ rho) {
+  __shared__ double sbuf[256];
+  const int j = blockIdx.x;
+  const double a = block_sum_column(part_r, nx, nblocks, j, sbuf);
+  const double b = block_sum_column(part_x, nx, nblocks, j, sbuf);
+  if (threadIdx.x == 0) rho[j] = sqrt(a) / ((normA + fabs(theta[j]) * normB) * sqrt(b));
+}
+
+// One workgroup: the leading run n_c[0] of rho_j <= tol and a non-finite flag n_c[1].
+__global__ __launch_bounds__(256) void residual_nc_kernel(int nx, const double* __restrict__ rho,
+                                                          const double* __restrict__ theta,
+                                                          double tol, int32_t* __restrict__ n_c) {
   __shared__ int smin[256];
   __shared__ int sbad[256];
   int first_bad = nx, nonfinite = 0;
   for (int j = threadIdx.x; j < nx; j += blockDim.x) {
-    double a = 0.0, b = 0.0;
-    for (int t = 0; t < nblocks; ++t) {
-      a += part_r[(int64_t)t * nx + j];
-      b += part_x[(int64_t)t * nx + j];
-    }
-    const double r = sqrt(a) / ((normA + fabs(theta[j]) * normB) * sqrt(b));
-    rho[j] = r;
+    const double r = rho[j];
     if (!(r <= tol) && j < first_bad) first_bad = j;
     if (!isfinite(r) || !isfinite(theta[j])) nonfinite = 1;
   }
@@ -467,13 +525,14 @@ __global__ __launch_bounds__(256) void colsq_kernel(int64_t n, int ncols, const 
     part[(int64_t)lb * ncols + j] = ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane];
 }
 
-__global__ void colsq_finish_kernel(int ncols, int nblocks, const double* __restrict__ part,
-                                    double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ncols) return;
-  double a = 0.0;
-  for (int t = 0; t < nblocks; ++t) a += part[(int64_t)t * ncols + j];
-  out[j] = a;
+// Grid: one workgroup per column.
+__global__ __launch_bounds__(256) void colsq_finish_kernel(int ncols, int nblocks,
+                                                           const double* __restrict__ part,
+                                                           double* __restrict__ out) {
+  __shared__ double sbuf[256];
+  const int j = blockIdx.x;
+  const double a = block_sum_column(part, ncols, nblocks, j, sbuf);
+  if (threadIdx.x == 0) out[j] = a;
 }
 
 // ------------------------------------------------------------------ Jacobi
@@ -623,18 +682,35 @@ __global__ void diag_scale_kernel(int n, const double* __restrict__ G, int64_t l
   Gout[i + (int64_t)j * ldo] = d[i] * G[i + (int64_t)j * ldg] * d[j];
 }
 
-__global__ __launch_bounds__(256) void cond1_upper_kernel(int n, const double* __restrict__ R,
-                                                          const double* __restrict__ Ri,
-                                                          int64_t ld, double* __restrict__ cond) {
+// One wave per column: colsum[j] = sum_{i<=j} |A(i, j)| for A = R (slot 0) and Rinv (slot 1).
+__global__ __launch_bounds__(256) void upper_colsum_kernel(int n, const double* __restrict__ R,
+                                                           const double* __restrict__ Ri,
+                                                           int64_t ld, double* __restrict__ out) {
+  const int j = blockIdx.x * 4 + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (j >= n) return;
+  double a = 0.0, b = 0.0;
+  for (int i = lane; i <= j; i += kWave) {
+    a += fabs(R[i + (int64_t)j * ld]);
+    b += fabs(Ri[i + (int64_t)j * ld]);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, kWave);
+    b += __shfl_xor(b, off, kWave);
+  }
+  if (lane == 0) {
+    out[j] = a;
+    out[n + j] = b;
+  }
+}
+
+// One workgroup: cond = max_j colsum_R(j) * max_j colsum_Rinv(j) (NaN propagates).
+__global__ __launch_bounds__(256) void cond1_max_kernel(int n, const double* __restrict__ cs,
+                                                        double* __restrict__ cond) {
   __shared__ double s0[256], s1[256];
   double m0 = 0.0, m1 = 0.0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    double a = 0.0, b = 0.0;
-    for (int i = 0; i <= j; ++i) {
-      a += fabs(R[i + (int64_t)j * ld]);
-      b += fabs(Ri[i + (int64_t)j * ld]);
-    }
-    // NaN-propagating maximum: a NaN column makes the condition number NaN.
+    const double a = cs[j], b = cs[n + j];
     m0 = (a > m0 || a != a) ? a : m0;
     m1 = (b > m1 || b != b) ? b : m1;
   }
@@ -828,8 +904,8 @@ void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const
 
 int64_t gram_workspace_bound(int64_t n, int m, int p) {
   (void)n;
-  // nsplit <= max(1, 2048 / tiles) and m * p <= tiles * 64 * 64.
-  return 8 * std::max<int64_t>(2048LL * kGramTM * kGramTP, (int64_t)m * p);
+  // nsplit <= max(1, target / tiles) and m * p <= tiles * kGramTM * kGramTP.
+  return 8 * std::max<int64_t>((int64_t)kGramTargetBlocks * kGramTM * kGramTP, (int64_t)m * p);
 }
 
 template <typename T>
@@ -863,8 +939,9 @@ void launch_residual(int64_t n, int nx, const T* AX, int64_t ldax, const T* BX, 
                      dim3(256), 0, s, n, nx, AX, ldax, BX, ldbx, X, ldx, theta, dinv, W, ldw,
                      part_r, part_x);
   LOBPCG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(residual_finish_kernel, dim3(1), dim3(256), 0, s, nx, (int)nb, part_r, part_x,
-                     theta, normA, normB, tol, rho, n_c);
+  hipLaunchKernelGGL(residual_rho_kernel, dim3((unsigned)nx), dim3(256), 0, s, nx, (int)nb, part_r,
+                     part_x, theta, normA, normB, rho);
+  hipLaunchKernelGGL(residual_nc_kernel, dim3(1), dim3(256), 0, s, nx, rho, theta, tol, n_c);
   LOBPCG_HIP(hipGetLastError());
 }
 
@@ -882,7 +959,7 @@ void launch_colsq(int64_t n, int ncols, const T* Y, int64_t ldy, double* out, vo
   hipLaunchKernelGGL((colsq_kernel<T>), dim3((unsigned)nb, (unsigned)((ncols + 63) / 64)),
                      dim3(256), 0, s, n, ncols, Y, ldy, part);
   LOBPCG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(colsq_finish_kernel, dim3(blocks_for(ncols)), dim3(256), 0, s, ncols, (int)nb,
+  hipLaunchKernelGGL(colsq_finish_kernel, dim3((unsigned)ncols), dim3(256), 0, s, ncols, (int)nb,
                      part, out);
   LOBPCG_HIP(hipGetLastError());
 }
@@ -951,8 +1028,11 @@ void launch_diag_scale(int n, const double* G, int64_t ldg, double* d, double* G
 }
 
 void launch_cond1_upper(int n, const double* R, const double* Rinv, int64_t ld, double* cond,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(cond1_upper_kernel, dim3(1), dim3(256), 0, s, n, R, Rinv, ld, cond);
+                        double* scratch, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(upper_colsum_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, R,
+                     Rinv, ld, scratch);
+  hipLaunchKernelGGL(cond1_max_kernel, dim3(1), dim3(256), 0, s, n, scratch, cond);
   LOBPCG_HIP(hipGetLastError());
 }
 

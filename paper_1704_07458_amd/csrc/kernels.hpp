@@ -81,9 +81,9 @@ void launch_diag_scale(int n, const double* G, int64_t ldg, double* d, double* G
                        int64_t ldo, bool compute_d, hipStream_t s);
 
 // cond_1 of upper-triangular R given R and Rinv (both column-major): writes
-// ||R||_1 * ||Rinv||_1 to *cond.
+// ||R||_1 * ||Rinv||_1 to *cond.  scratch: 2n doubles.
 void launch_cond1_upper(int n, const double* R, const double* Rinv, int64_t ld, double* cond,
-                        hipStream_t s);
+                        double* scratch, hipStream_t s);
 
 // Zero the strictly lower triangle of an n x n column-major matrix.
 void launch_zero_lower(int n, double* A, int64_t ld, hipStream_t s);
