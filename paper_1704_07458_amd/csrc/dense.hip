@@ -23,6 +23,8 @@ namespace lobpcg {
 
 Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax), s_(s) {
   if (const char* e = std::getenv("LOBPCG_EIGENSOLVER")) eig_ = std::atoi(e);
+  kTridiagMaxN = std::min(512, sytd2_max_n());
+  if (const char* e = std::getenv("LOBPCG_TRIDIAG_MAX_N")) kTridiagMaxN = std::atoi(e);
   LOBPCG_ROCBLAS(rocblas_create_handle(&h_));
   LOBPCG_ROCBLAS(rocblas_set_stream(h_, s_));
   const size_t sq = sizeof(double) * (size_t)nsmax * nsmax;
@@ -59,6 +61,9 @@ void Dense::gemm(rocblas_operation ta, rocblas_operation tb, int m, int n, int k
                                (rocblas_int)ldb, &beta, C, (rocblas_int)ldc));
 }
 
+static void copy_cm(int m, int n, const double* src, int64_t lds, double* dst, int64_t ldd,
+                    hipStream_t s);
+
 void Dense::syev(int n, double* A, int64_t lda, double* w) {
   int32_t* dinfo = info_.as<int32_t>() + 2;
   if (eig_ == 2) {
@@ -70,6 +75,19 @@ void Dense::syev(int n, double* A, int64_t lda, double* w) {
   } else if (eig_ == 1) {
     LOBPCG_ROCBLAS(rocsolver_dsyevdj(h_, rocblas_evect_original, rocblas_fill_upper, n, A,
                                      (rocblas_int)lda, w, dinfo));
+  } else if (eig_ == 0 && n <= kTridiagMaxN && n >= 2) {
+    // Householder tridiagonalisation in one workgroup (kernels.hip), then
+    // divide and conquer on the tridiagonal and the back-transformation Q Z_T.
+    double* e = E_.as<double>();
+    double* tau = tau_.as<double>();
+    double* Z = T1_.as<double>();
+    launch_sytd2_lower(n, A, lda, w, e, tau, s_);
+    LOBPCG_ROCBLAS(rocsolver_dstedc(h_, rocblas_evect_tridiagonal, n, w, e, Z, (rocblas_int)nsmax_,
+                                    dinfo));
+    LOBPCG_ROCBLAS(rocsolver_dormtr(h_, rocblas_side_left, rocblas_fill_lower,
+                                    rocblas_operation_none, n, n, A, (rocblas_int)lda, tau, Z,
+                                    (rocblas_int)nsmax_));
+    copy_cm(n, n, Z, nsmax_, A, lda, s_);
   } else {
     LOBPCG_ROCBLAS(rocsolver_dsyevd(h_, rocblas_evect_original, rocblas_fill_upper, n, A,
                                     (rocblas_int)lda, w, E_.as<double>(), dinfo));

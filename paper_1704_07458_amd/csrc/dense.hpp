@@ -47,8 +47,10 @@ class Dense {
   rocblas_handle handle() const { return h_; }
   hipStream_t stream() const { return s_; }
 
-  // Eigen-solver selection for the projected problem (0 = syevd, 1 = syevdj,
-  // 2 = syevj); the environment variable LOBPCG_EIGENSOLVER overrides the default.
+  // Eigen-solver selection for the projected problem: 0 = automatic (the
+  // one-workgroup tridiagonalisation + stedc + ormtr up to kTridiagMaxN, syevd
+  // above), 1 = syevdj, 2 = syevj, 3 = syevd always.  The environment variable
+  // LOBPCG_EIGENSOLVER overrides the default.
   void set_eigensolver(int which) { eig_ = which; }
 
  private:
@@ -61,6 +63,7 @@ class Dense {
   hipStream_t s_;
   rocblas_handle h_ = nullptr;
   int eig_ = 0;
+  int kTridiagMaxN = 512;
   // scratch (column-major, leading dimension nsmax_)
   DevBuf H_, R_, Ri_, T1_, Mt_, ZQ_, Qs_, d_, E_, tau_, info_, cond_, th2_, scale_, sinfo_;
   int32_t* hinfo_ = nullptr;  // pinned host status words

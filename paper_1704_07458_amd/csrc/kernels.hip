@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 
 #include "common.hpp"
 
@@ -850,6 +851,137 @@ __global__ __launch_bounds__(256) void sqrt_sum_kernel(int n, const double* __re
   if (threadIdx.x == 0) *out = sqrt(s[0]);
 }
 
+// ------------------------------------------------------------------ tridiagonal
+// Householder reduction of a symmetric n x n matrix (column-major, both
+// triangles stored) to tridiagonal form, in one workgroup and one launch:
+// A = Q T Q^T with Q = H(0) H(1) ... H(n-2), H(i) = I - tau_i v_i v_i^T,
+// v_i(i+1) = 1, v_i(i+2:n) stored in A(i+2:n, i), d = diag(T), e = subdiag(T)
+// (the layout LAPACK's lower-triangle reduction produces).
+//
+// Step i: (a) bring column i up to date with the previous step's deferred
+// rank-2 update; (b) form the reflector from it; (c) one fused pass over the
+// trailing block A(i+1:n, i+1:n) that applies the deferred update and
+// accumulates p = A22 v_i; (d) w_i = tau_i p - (tau_i^2 / 2)(p^T v_i) v_i,
+// whose update A22 -= v w^T + w v^T is deferred to the next step.  The trailing
+// block stays in L2 (n <= 1024); every element is read and written once per
+// step, and all sums run in a fixed order (deterministic).
+constexpr int kTriThreads = 1024;
+constexpr int kTriMaxN = 1024;
+
+__device__ __forceinline__ double tri_block_sum(double v, double* red) {
+  // wave sums, then one wave over the partials (fixed order)
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (wave == 0) {
+    t = lane < (int)(blockDim.x / kWave) ? red[lane] : 0.0;
+    for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, kWave);
+    if (lane == 0) red[kTriThreads / kWave] = t;
+  }
+  __syncthreads();
+  return red[kTriThreads / kWave];
+}
+
+__global__ __launch_bounds__(kTriThreads) void sytd2_lower_kernel(int n, double* __restrict__ A,
+                                                                  int64_t lda,
+                                                                  double* __restrict__ d,
+                                                                  double* __restrict__ e,
+                                                                  double* __restrict__ tau) {
+  __shared__ double vb[2][kTriMaxN];  // v of the current / previous step (indexed by row)
+  __shared__ double wb[2][kTriMaxN];  // w of the current / previous step
+  __shared__ double pp[4][kTriMaxN];  // partial p per column group
+  __shared__ double red[kTriThreads / kWave + 1];
+  const int t = threadIdx.x;
+  bool pend = false;  // deferred update (vb[prev], wb[prev]) on block [i, n)^2
+  int cur = 0;
+  for (int i = 0; i < n - 1; ++i) {
+    const int prev = cur ^ 1;
+    double* col = A + (int64_t)i * lda;
+    // (a) column i, rows i..n-1
+    for (int r = i + t; r < n; r += kTriThreads) {
+      double a = col[r];
+      if (pend) a -= vb[prev][r] * wb[prev][i] + wb[prev][r] * vb[prev][i];
+      col[r] = a;
+    }
+    __syncthreads();
+    // (b) reflector annihilating A(i+2:n, i)
+    double part = 0.0;
+    for (int r = i + 2 + t; r < n; r += kTriThreads) part = fma(col[r], col[r], part);
+    const double xnorm2 = tri_block_sum(part, red);
+    const double alpha = col[i + 1];
+    double taui = 0.0, beta = alpha, scal = 0.0;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      taui = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (t == 0) {
+      d[i] = col[i];
+      e[i] = beta;
+      tau[i] = taui;
+    }
+    for (int r = i + 1 + t; r < n; r += kTriThreads) {
+      const double vr = (r == i + 1) ? 1.0 : col[r] * scal;
+      vb[cur][r] = vr;
+      if (r >= i + 2) col[r] = vr;
+    }
+    __syncthreads();
+    if (t == 0) col[i + 1] = beta;
+    // (c) fused pass over rows/cols [i+1, n): deferred update, p = A22 v
+    const int m = n - i - 1;
+    const int rows_pass = ((m + kWave - 1) / kWave) * kWave;
+    const int groups = rows_pass >= kTriThreads ? 1 : (kTriThreads / rows_pass < 4 ? kTriThreads / rows_pass : 4);
+    const int rr = t % rows_pass;
+    const int g = t / rows_pass;
+    if (taui != 0.0 || pend) {
+      for (int rbase = 0; rbase < m; rbase += rows_pass) {
+        const int r = i + 1 + rbase + rr;
+        double acc = 0.0;
+        if (g < groups && r < n) {
+          const double vpr = pend ? vb[prev][r] : 0.0, wpr = pend ? wb[prev][r] : 0.0;
+          double* arow = A + r;
+#pragma unroll 8
+          for (int c = i + 1 + g; c < n; c += groups) {
+            double a = arow[(int64_t)c * lda];
+            if (pend) a -= vpr * wb[prev][c] + wpr * vb[prev][c];
+            arow[(int64_t)c * lda] = a;
+            acc = fma(a, vb[cur][c], acc);
+          }
+        }
+        if (g < groups && r < n) pp[g][r] = acc;
+        __syncthreads();
+        if (g == 0 && r < n) {
+          double s = pp[0][r];
+          for (int q = 1; q < groups; ++q) s += pp[q][r];
+          wb[cur][r] = taui * s;  // p (scaled), finished to w below
+        }
+        __syncthreads();
+      }
+    }
+    // (d) w = p - (tau/2)(p^T v) v
+    double dp = 0.0;
+    if (taui != 0.0)
+      for (int r = i + 1 + t; r < n; r += kTriThreads) dp = fma(wb[cur][r], vb[cur][r], dp);
+    const double pv = tri_block_sum(dp, red);
+    const double alpha2 = -0.5 * taui * pv;
+    for (int r = i + 1 + t; r < n; r += kTriThreads)
+      wb[cur][r] = taui != 0.0 ? fma(alpha2, vb[cur][r], wb[cur][r]) : 0.0;
+    __syncthreads();
+    pend = taui != 0.0;
+    cur = prev;
+  }
+  // last diagonal element with the final deferred update
+  if (t == 0) {
+    const int prev = cur ^ 1;
+    double a = A[(int64_t)(n - 1) * lda + (n - 1)];
+    if (pend && n >= 2) a -= 2.0 * vb[prev][n - 1] * wb[prev][n - 1];
+    d[n - 1] = a;
+  }
+}
+
 inline unsigned blocks_for(int64_t total, int threads = 256) {
   return (unsigned)((total + threads - 1) / threads);
 }
@@ -1087,6 +1219,19 @@ void launch_fro(int m, int n, const double* A, int64_t lda, double* out, hipStre
   hipLaunchKernelGGL(fro_kernel, dim3(1), dim3(256), 0, s, m, n, A, lda, 0, out);
   LOBPCG_HIP(hipGetLastError());
 }
+
+void launch_sytd2_lower(int n, double* A, int64_t lda, double* d, double* e, double* tau,
+                        hipStream_t s) {
+  LOBPCG_CHECK(n >= 1 && n <= kTriMaxN, LOBPCG_ERR_ARG, "sytd2: n out of range");
+  if (n == 1) {
+    LOBPCG_HIP(hipMemcpyAsync(d, A, sizeof(double), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  hipLaunchKernelGGL(sytd2_lower_kernel, dim3(1), dim3(kTriThreads), 0, s, n, A, lda, d, e, tau);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+int sytd2_max_n() { return kTriMaxN; }
 
 void launch_sqrt_sum(int n, const double* v, double* out, hipStream_t s) {
   hipLaunchKernelGGL(sqrt_sum_kernel, dim3(1), dim3(256), 0, s, n, v, out);

@@ -114,6 +114,12 @@ void launch_svqb_theta(int n, double* theta, double tau, int drop, double* scale
 void launch_fro_minus_identity(int n, const double* A, int64_t lda, double* out, hipStream_t s);
 // Frobenius norm of an m x n column-major block, written to *out.
 void launch_fro(int m, int n, const double* A, int64_t lda, double* out, hipStream_t s);
+// Householder tridiagonalisation of a symmetric n x n matrix (column-major,
+// both triangles stored; n <= sytd2_max_n()) in one workgroup: d, e (n-1), tau
+// (n-1) and the reflectors below the subdiagonal, in LAPACK's lower layout.
+void launch_sytd2_lower(int n, double* A, int64_t lda, double* d, double* e, double* tau,
+                        hipStream_t s);
+int sytd2_max_n();
 // out = sqrt(sum of v[0..n)) for a vector of squares.
 void launch_sqrt_sum(int n, const double* v, double* out, hipStream_t s);
 

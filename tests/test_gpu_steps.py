@@ -269,3 +269,47 @@ def test_rr_step_flags_ill_conditioned(lib):
     got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), 3, 0, False,
                     L.Tolerances().tau_skip)
     assert got["flipped"] and got["cond"] > 1e5
+
+
+@pytest.mark.parametrize("n_s,use_ortho", [(330, False), (330, True), (600, False)])
+def test_rr_step_full_size_with_clustered_spectrum(lib, n_s, use_ortho):
+    """The projected problem at the bench's size (n_s = 3 n_x = 330) and above.
+
+    A is a 2D Laplacian (many exactly repeated eigenvalues), so individual Ritz
+    vectors inside clusters are not unique: check the Ritz values against the
+    oracle and the output contract C^T G_B C = I, C^T G_A C = blockdiag(Theta).
+    n_s = 600 exercises the library eigensolver used above the one-workgroup
+    tridiagonalisation's size range.
+    """
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(n_s)
+    n, n_x = 3000, n_s // 3
+    A = P.laplacian_2d_dirichlet(55).to_scipy()[:n, :n]
+    S = rng.standard_normal((n, n_s))
+    if use_ortho:
+        S, _ = np.linalg.qr(S)
+        # an exactly degenerate projected matrix: repeat a block of eigenvalues
+        GA = np.diag(np.repeat(np.arange(1.0, n_s // 6 + 1.0), 6)[:n_s])
+        Qr, _ = np.linalg.qr(rng.standard_normal((n_s, n_s)))
+        GA = Qr @ GA @ Qr.T
+        GB = np.eye(n_s)
+    else:
+        GA, GB = S.T @ (A @ S), S.T @ S
+    GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+    tol = L.Tolerances()
+    ref = L.rayleigh_ritz_modified(GA, GB, n_x, 0, use_ortho, tol)
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), n_x, 0, use_ortho,
+                    tol.tau_skip)
+    assert not got["flipped"]
+    th = got["theta"].cpu().numpy()
+    scale = np.abs(ref.theta_all).max()
+    assert np.allclose(th, ref.theta_all, rtol=0, atol=1e-12 * scale)
+    Cx, Cp = got["Cx"].cpu().numpy(), got["Cp"].cpu().numpy()
+    C = np.hstack([Cx, Cp])
+    assert np.allclose(C.T @ GB @ C, np.eye(C.shape[1]), atol=1e-10)
+    T = np.zeros((C.shape[1],) * 2)
+    T[:n_x, :n_x] = np.diag(th[:n_x])
+    T[n_x:, n_x:] = got["theta_p"].cpu().numpy()
+    assert np.allclose(C.T @ GA @ C, T, atol=1e-10 * scale)
