@@ -158,7 +158,12 @@ int lobpcg_eigpairs(lobpcg_t h, int32_t count, double* lambda, double* X, int64_
  * DEVICE block with leading dimension ld_xbar (may be NULL = 0); grad: nnz(A)
  * DEVICE values.  cg_tol: relative residual of the projected solve (<= 0: 1e-12);
  * cg_maxit <= 0: 10000.  cg_iters (host, may be NULL) receives the largest CG
- * iteration count.  Errors: LOBPCG_ERR_STATE, LOBPCG_ERR_ARG (B != I). */
+ * iteration count.  The CG residual is re-projected against X every step; a
+ * column whose curvature p^T (projected operator) p is no longer positive has
+ * reached the rounding floor and stops there.  Returns LOBPCG_OK, or
+ * LOBPCG_NOT_CONVERGED when cg_maxit is reached with columns above cg_tol (grad
+ * is still written, from the last iterate).  Errors: LOBPCG_ERR_STATE,
+ * LOBPCG_ERR_ARG (B != I). */
 int lobpcg_adjoint(lobpcg_t h, int32_t count, const double* lambda_bar, const double* X_bar,
                    int64_t ld_xbar, double* grad, double cg_tol, int32_t cg_maxit,
                    int32_t* cg_iters);

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import warnings
 from typing import Optional
 
 import numpy as np
@@ -332,9 +333,13 @@ class Solver:
             lb = np.ascontiguousarray(np.asarray(lambda_bar, dtype=np.float64))
         xb = X_bar.to(torch.float64).contiguous() if X_bar is not None else None
         iters = C.c_int32()
-        check(load().lobpcg_adjoint(self._h, int(count), lb.ctypes.data if lb is not None else None,
-                                    _ptr(xb) if xb is not None else None, int(count),
-                                    _ptr(grad), float(cg_tol), int(cg_maxit), C.byref(iters)))
+        st = check(load().lobpcg_adjoint(self._h, int(count),
+                                         lb.ctypes.data if lb is not None else None,
+                                         _ptr(xb) if xb is not None else None, int(count),
+                                         _ptr(grad), float(cg_tol), int(cg_maxit), C.byref(iters)))
+        if st == LOBPCG_NOT_CONVERGED:
+            warnings.warn(f"lobpcg_adjoint: projected CG reached cg_maxit ({int(iters.value)}) "
+                          f"above cg_tol {cg_tol:g}", RuntimeWarning, stacklevel=2)
         return grad, int(iters.value)
 
 

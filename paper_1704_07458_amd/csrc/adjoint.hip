@@ -81,12 +81,24 @@ __global__ void colsum_finish_kernel(int m, int nb, const double* __restrict__ p
   out[j] = a;
 }
 
-// alpha_i = active_i ? rr_i / pAp_i : 0
-__global__ void cg_alpha_kernel(int m, const double* rr, const double* pap, const int* active,
-                                double* alpha) {
+// alpha_i = rr_i / pAp_i for active columns.  A column whose curvature pAp is
+// not positive (or not finite) has reached the rounding floor of the projected
+// operator, which is positive definite in exact arithmetic: it stops there
+// (alpha = 0, inactive) and is counted in *nbreak.
+__global__ void cg_alpha_kernel(int m, const double* rr, const double* pap, int* active,
+                                double* alpha, int* nbreak) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
-  alpha[j] = (active[j] && pap[j] != 0.0) ? rr[j] / pap[j] : 0.0;
+  double a = 0.0;
+  if (active[j]) {
+    if (pap[j] > 0.0 && pap[j] < INFINITY) {
+      a = rr[j] / pap[j];
+    } else {
+      active[j] = 0;
+      atomicAdd(nbreak, 1);
+    }
+  }
+  alpha[j] = a;
 }
 
 // Z += alpha P; R -= alpha AP
@@ -227,7 +239,9 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
   LOBPCG_HIP(hipMemsetAsync(Yp, 0, sizeof(double) * n * ld, s));
   LOBPCG_HIP(hipMemsetAsync(Zp, 0, sizeof(double) * n * ld, s));
   int iters = 0;
+  bool converged = true;
   if (X_bar) {
+    converged = false;
     // In-block part: Y = X coef, coef(j, i) = -(x_j^T xbar_i) / (lambda_j - lambda_i).
     launch_gram<double>(n, m, m, m, X, ldx, X_bar, ld_xbar, nullptr, 0, G, 0, nullptr, 0, m, 0,
                         gws.get(), s);
@@ -249,6 +263,7 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
     coldot(Rp, Rp, rr);
     LOBPCG_HIP(hipMemcpyAsync(bn2, rr, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(init_active_kernel, dim3(nblk(m)), dim3(256), 0, s, m, bn2, active);
+    LOBPCG_HIP(hipMemsetAsync(nact, 0, sizeof(int) * 2, s));
     const double tol2 = tol * tol;
     int32_t* hflag = nullptr;
     LOBPCG_HIP(hipHostMalloc((void**)&hflag, sizeof(int32_t) * 2, hipHostMallocDefault));
@@ -264,19 +279,26 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
         launch_update<double>(n, m, m, X, ldx, G, m, -1.0, 1.0, APp, ld, s);
         coldot(Pp, APp, pap);
         hipLaunchKernelGGL(cg_alpha_kernel, dim3(nblk(m)), dim3(256), 0, s, m, rr, pap, active,
-                           alpha);
+                           alpha, nact + 1);
         hipLaunchKernelGGL(cg_step_kernel, dim3(nblk(n * m)), dim3(256), 0, s, n, m, alpha, Pp,
                            APp, Zp, Rp, ld);
+        // R <- (I - X X^T) R: AP is orthogonal to X only up to rounding, and the
+        // part of R inside span(X) would otherwise accumulate, never decay, and
+        // put a floor under ||R|| that the projected operator cannot see.
+        launch_gram<double>(n, m, m, m, X, ldx, Rp, ld, nullptr, 0, G, 0, nullptr, 0, m, 0,
+                            gws.get(), s);
+        launch_update<double>(n, m, m, X, ldx, G, m, -1.0, 1.0, Rp, ld, s);
         coldot(Rp, Rp, rrn);
         hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(256), 0, s, m, rr, rrn, bn2, tol2, active,
                            beta, nact);
         hipLaunchKernelGGL(cg_dir_kernel, dim3(nblk(n * m)), dim3(256), 0, s, n, m, beta, Rp, Pp,
                            ld);
         LOBPCG_HIP(hipGetLastError());
-        LOBPCG_HIP(hipMemcpyAsync(hflag, nact, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LOBPCG_HIP(hipMemcpyAsync(hflag, nact, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
         LOBPCG_HIP(hipStreamSynchronize(s));
         if (hflag[0] == 0) {
           ++iters;
+          converged = true;
           break;
         }
       }
@@ -297,7 +319,7 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
   LOBPCG_HIP(hipGetLastError());
   LOBPCG_HIP(hipStreamSynchronize(s));
   if (cg_iters) *cg_iters = iters;
-  return LOBPCG_OK;
+  return converged ? LOBPCG_OK : LOBPCG_NOT_CONVERGED;
 }
 
 }  // namespace lobpcg
