@@ -1,7 +1,8 @@
 // HIP kernels of the robust LOBPCG path for gfx950 (CDNA4, wave64).
 //
-//  spmm      CSR sparse x row-major block (HBM-bound): one wave per row, lanes
-//            across columns, XCD-contiguous row ranges.
+//  spmm      CSR sparse x row-major block (HBM-bound): a wave owns 8 rows and
+//            walks their nonzeros 64 at a time, lanes across columns,
+//            XCD-contiguous row ranges.
 //  gram      tall-skinny L^T R on MFMA (v_mfma_f64_16x16x4f64 / f32_16x16x4f32),
 //            split-K over rows, deterministic FP64 second-stage sum.
 //  update    row-tiled S C on MFMA (section 5.1 basis update).
@@ -40,65 +41,98 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ------------------------------------------------------------------ SpMM
-// Grid: x = row blocks of kRowsPerBlock rows, y = column panels of 64*NC.
+// Y = A X for CSR A and row-major X (ncols columns).  Grid: x = blocks of
+// kSpmmRowsPerBlock rows (XCD-contiguous), y = column panels of 64*NC; each
+// lane owns NC columns.  Each wave owns kSpmmRowsPerWave consecutive rows.  It
+// loads their row pointers with one vector load, then the column indices and values
+// of up to 64 nonzeros at a time (one per lane), and walks the nonzeros with
+// each index and value broadcast from its lane (readlane, wave-uniform),
+// issuing kSpmmBatch X-row loads before consuming them, so that a row costs a
+// fraction of one memory latency instead of a chain of them.
 constexpr int kSpmmRowsPerBlock = 32;
+constexpr int kSpmmRowsPerWave = kSpmmRowsPerBlock / 4;
+constexpr int kSpmmBatch = 8;
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlane_val(double v, int l) {
+  return __builtin_bit_cast(double, readlane64(__builtin_bit_cast(int64_t, v), l));
+}
+__device__ __forceinline__ float readlane_val(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
 
 template <typename T, int NC>
-__global__ __launch_bounds__(256) void spmm_kernel(int64_t n, const int64_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ colind,
-                                                   const T* __restrict__ vals,
-                                                   const T* __restrict__ X, int64_t ldx,
-                                                   T* __restrict__ Y, int64_t ldy, int ncols) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void spmm_kernel(int64_t n,
+                                                         const int64_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ colind,
+                                                         const T* __restrict__ vals,
+                                                         const T* __restrict__ X, int64_t ldx,
+                                                         T* __restrict__ Y, int64_t ldy,
+                                                         int ncols) {
+  const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
   const int wave = uniform(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   const int col0 = blockIdx.y * (kWave * NC) + lane;
-  const int64_t rbeg = (int64_t)lb * kSpmmRowsPerBlock;
-  const int64_t rend = rbeg + kSpmmRowsPerBlock < n ? rbeg + kSpmmRowsPerBlock : n;
+  const int64_t r0 = lb * kSpmmRowsPerBlock + (int64_t)wave * kSpmmRowsPerWave;
+  if (r0 >= n) return;
+  const int nr = (int)(n - r0 < kSpmmRowsPerWave ? n - r0 : kSpmmRowsPerWave);
   bool cok[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) cok[j] = col0 + kWave * j < ncols;
-
-  for (int64_t r = rbeg + wave; r < rend; r += 4) {
-    T acc[NC];
+  const int64_t rpl = lane <= nr ? rowptr[r0 + lane] : 0;
+  const int64_t pbeg = readlane64(rpl, 0), pend = readlane64(rpl, nr);
+  int cr = 0;                       // current row (offset from r0), wave-uniform
+  int64_t ce = readlane64(rpl, 1);  // end of the current row's nonzeros
+  T acc[NC];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) acc[j] = T(0);
-    int64_t p = rowptr[r];
-    const int64_t pe = rowptr[r + 1];
-    // Four nonzeros per step: their column indices and values are wave-uniform
-    // (scalar loads); the X-row loads are independent and issued together.
-    for (; p + 4 <= pe; p += 4) {
-      const int64_t c0 = colind[p], c1 = colind[p + 1], c2 = colind[p + 2], c3 = colind[p + 3];
-      const T a0 = vals[p], a1 = vals[p + 1], a2 = vals[p + 2], a3 = vals[p + 3];
-      T x0[NC], x1[NC], x2[NC], x3[NC];
+  for (int j = 0; j < NC; ++j) acc[j] = T(0);
+  for (int64_t chunk = pbeg; chunk < pend; chunk += kWave) {
+    const int cnt = (int)(pend - chunk < kWave ? pend - chunk : kWave);
+    const int32_t cl = lane < cnt ? colind[chunk + lane] : 0;
+    const T al = lane < cnt ? vals[chunk + lane] : T(0);
+    for (int q = 0; q < cnt; q += kSpmmBatch) {
+      T xb[kSpmmBatch][NC];
+      T ab[kSpmmBatch];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const int c = col0 + kWave * j;
-        x0[j] = cok[j] ? X[c0 * ldx + c] : T(0);
-        x1[j] = cok[j] ? X[c1 * ldx + c] : T(0);
-        x2[j] = cok[j] ? X[c2 * ldx + c] : T(0);
-        x3[j] = cok[j] ? X[c3 * ldx + c] : T(0);
+      for (int u = 0; u < kSpmmBatch; ++u) {
+        const bool ok = q + u < cnt;
+        const int li = ok ? q + u : 0;
+        const int64_t c = (int64_t)__builtin_amdgcn_readlane(cl, li);
+        ab[u] = ok ? readlane_val(al, li) : T(0);
+#pragma unroll
+        for (int j = 0; j < NC; ++j)
+          xb[u][j] = (ok && cok[j]) ? X[c * ldx + col0 + kWave * j] : T(0);
       }
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        acc[j] = fma(a0, x0[j], acc[j]);
-        acc[j] = fma(a1, x1[j], acc[j]);
-        acc[j] = fma(a2, x2[j], acc[j]);
-        acc[j] = fma(a3, x3[j], acc[j]);
+      for (int u = 0; u < kSpmmBatch; ++u) {
+        if (q + u < cnt) {
+          const int64_t p = chunk + q + u;
+          while (cr + 1 < nr && p >= ce) {  // the current row is complete (rows may be empty)
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              if (cok[j]) Y[(r0 + cr) * ldy + col0 + kWave * j] = acc[j];
+              acc[j] = T(0);
+            }
+            ++cr;
+            ce = readlane64(rpl, cr + 1);
+          }
+#pragma unroll
+          for (int j = 0; j < NC; ++j) acc[j] = fma(ab[u], xb[u][j], acc[j]);
+        }
       }
     }
-    for (; p < pe; ++p) {
-      const int64_t c0 = colind[p];
-      const T a0 = vals[p];
+  }
+  for (; cr < nr; ++cr) {
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const int c = col0 + kWave * j;
-        if (cok[j]) acc[j] = fma(a0, X[c0 * ldx + c], acc[j]);
-      }
+    for (int j = 0; j < NC; ++j) {
+      if (cok[j]) Y[(r0 + cr) * ldy + col0 + kWave * j] = acc[j];
+      acc[j] = T(0);
     }
-#pragma unroll
-    for (int j = 0; j < NC; ++j)
-      if (cok[j]) Y[r * ldy + col0 + kWave * j] = acc[j];
   }
 }
 
