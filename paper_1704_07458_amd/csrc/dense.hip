@@ -23,7 +23,7 @@ namespace lobpcg {
 
 Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax), s_(s) {
   if (const char* e = std::getenv("LOBPCG_EIGENSOLVER")) eig_ = std::atoi(e);
-  kTridiagMaxN = std::min(512, sytd2_max_n());
+  kTridiagMaxN = std::min(512, sytrd_max_n());
   if (const char* e = std::getenv("LOBPCG_TRIDIAG_MAX_N")) kTridiagMaxN = std::atoi(e);
   LOBPCG_ROCBLAS(rocblas_create_handle(&h_));
   LOBPCG_ROCBLAS(rocblas_set_stream(h_, s_));
@@ -81,12 +81,10 @@ void Dense::syev(int n, double* A, int64_t lda, double* w) {
     double* e = E_.as<double>();
     double* tau = tau_.as<double>();
     double* Z = T1_.as<double>();
-    launch_sytd2_lower(n, A, lda, w, e, tau, s_);
+    launch_sytrd_lower(n, A, lda, w, e, tau, s_);
     LOBPCG_ROCBLAS(rocsolver_dstedc(h_, rocblas_evect_tridiagonal, n, w, e, Z, (rocblas_int)nsmax_,
                                     dinfo));
-    LOBPCG_ROCBLAS(rocsolver_dormtr(h_, rocblas_side_left, rocblas_fill_lower,
-                                    rocblas_operation_none, n, n, A, (rocblas_int)lda, tau, Z,
-                                    (rocblas_int)nsmax_));
+    launch_ormtr_lower(n, A, lda, tau, Z, nsmax_, s_);
     copy_cm(n, n, Z, nsmax_, A, lda, s_);
   } else {
     LOBPCG_ROCBLAS(rocsolver_dsyevd(h_, rocblas_evect_original, rocblas_fill_upper, n, A,

@@ -889,130 +889,287 @@ __global__ __launch_bounds__(256) void sqrt_sum_kernel(int n, const double* __re
 // Householder reduction of a symmetric n x n matrix (column-major, both
 // triangles stored) to tridiagonal form, in one workgroup and one launch:
 // A = Q T Q^T with Q = H(0) H(1) ... H(n-2), H(i) = I - tau_i v_i v_i^T,
-// v_i(i+1) = 1, v_i(i+2:n) stored in A(i+2:n, i), d = diag(T), e = subdiag(T)
-// (the layout LAPACK's lower-triangle reduction produces).
+// v_i(i+1) = 1, v_i(i+2:n) stored in A(i+2:n, i), d = diag(T), e = subdiag(T).
+// All sums run in a fixed order (deterministic).
 //
-// Step i: (a) bring column i up to date with the previous step's deferred
-// rank-2 update; (b) form the reflector from it; (c) one fused pass over the
-// trailing block A(i+1:n, i+1:n) that applies the deferred update and
-// accumulates p = A22 v_i; (d) w_i = tau_i p - (tau_i^2 / 2)(p^T v_i) v_i,
-// whose update A22 -= v w^T + w v^T is deferred to the next step.  The trailing
-// block stays in L2 (n <= 1024); every element is read and written once per
-// step, and all sums run in a fixed order (deterministic).
-constexpr int kTriThreads = 1024;
-constexpr int kTriMaxN = 1024;
+// Blocked Householder tridiagonalisation (lower), one workgroup, after the
+// panel scheme of LAPACK's dsytrd / dlatrd: within a panel of kTrdNb columns
+// the trailing matrix is left as it was at the panel start, each step
+// corrects its column and its product A v with the panel's reflectors and
+// their w vectors (V, W, kept in LDS), and the trailing matrix receives the
+// rank-2 kTrdNb update V W^T + W V^T once per panel.  A step therefore reads
+// the trailing matrix once (the product) instead of reading and writing it.
+// Output as LAPACK's dsytrd with uplo = 'L': d, e, tau, reflectors below the
+// subdiagonal of A.
+constexpr int kTrdThreads = 1024;
+constexpr int kTrdMaxN = 512;
+constexpr int kTrdNb = 16;
+static_assert(kTrdMaxN <= kTrdThreads, "one row per thread in the column steps");
 
-__device__ __forceinline__ double tri_block_sum(double v, double* red) {
-  // wave sums, then one wave over the partials (fixed order)
+__device__ __forceinline__ double wave_sum(double v) {
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (wave == 0) {
-    t = lane < (int)(blockDim.x / kWave) ? red[lane] : 0.0;
-    for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, kWave);
-    if (lane == 0) red[kTriThreads / kWave] = t;
-  }
-  __syncthreads();
-  return red[kTriThreads / kWave];
+  return v;
 }
 
-__global__ __launch_bounds__(kTriThreads) void sytd2_lower_kernel(int n, double* __restrict__ A,
+// Workgroup sum with one barrier: wave sums into red[wave], then every thread
+// adds the partials in the same fixed order.  Callers alternate between two
+// red buffers with a barrier between successive uses of the same one.
+__device__ __forceinline__ double trd_block_sum(double v, double* red) {
+  v = wave_sum(v);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTrdThreads / kWave; ++q) s += red[q];
+  return s;
+}
+
+__global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double* __restrict__ A,
                                                                   int64_t lda,
                                                                   double* __restrict__ d,
                                                                   double* __restrict__ e,
                                                                   double* __restrict__ tau) {
-  __shared__ double vb[2][kTriMaxN];  // v of the current / previous step (indexed by row)
-  __shared__ double wb[2][kTriMaxN];  // w of the current / previous step
-  __shared__ double pp[4][kTriMaxN];  // partial p per column group
-  __shared__ double red[kTriThreads / kWave + 1];
+  __shared__ double V[kTrdNb * kTrdMaxN];  // V[k * kTrdMaxN + r]: reflector k of the panel
+  __shared__ double W[kTrdNb * kTrdMaxN];  // W[k * kTrdMaxN + r]
+  __shared__ double cv[kTrdMaxN];          // the current column, updated
+  __shared__ double pp[kTrdThreads];       // partial products per column group
+  __shared__ double yv[2 * kTrdNb];        // W^T v, V^T v
+  __shared__ double redA[kTrdThreads / kWave], redB[kTrdThreads / kWave];
   const int t = threadIdx.x;
-  bool pend = false;  // deferred update (vb[prev], wb[prev]) on block [i, n)^2
-  int cur = 0;
-  for (int i = 0; i < n - 1; ++i) {
-    const int prev = cur ^ 1;
-    double* col = A + (int64_t)i * lda;
-    // (a) column i, rows i..n-1
-    for (int r = i + t; r < n; r += kTriThreads) {
-      double a = col[r];
-      if (pend) a -= vb[prev][r] * wb[prev][i] + wb[prev][r] * vb[prev][i];
-      col[r] = a;
-    }
-    __syncthreads();
-    // (b) reflector annihilating A(i+2:n, i)
-    double part = 0.0;
-    for (int r = i + 2 + t; r < n; r += kTriThreads) part = fma(col[r], col[r], part);
-    const double xnorm2 = tri_block_sum(part, red);
-    const double alpha = col[i + 1];
-    double taui = 0.0, beta = alpha, scal = 0.0;
-    if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      taui = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
-    }
-    if (t == 0) {
-      d[i] = col[i];
-      e[i] = beta;
-      tau[i] = taui;
-    }
-    for (int r = i + 1 + t; r < n; r += kTriThreads) {
-      const double vr = (r == i + 1) ? 1.0 : col[r] * scal;
-      vb[cur][r] = vr;
-      if (r >= i + 2) col[r] = vr;
-    }
-    __syncthreads();
-    if (t == 0) col[i + 1] = beta;
-    // (c) fused pass over rows/cols [i+1, n): deferred update, p = A22 v
-    const int m = n - i - 1;
-    const int rows_pass = ((m + kWave - 1) / kWave) * kWave;
-    const int groups = rows_pass >= kTriThreads ? 1 : (kTriThreads / rows_pass < 4 ? kTriThreads / rows_pass : 4);
-    const int rr = t % rows_pass;
-    const int g = t / rows_pass;
-    if (taui != 0.0 || pend) {
-      for (int rbase = 0; rbase < m; rbase += rows_pass) {
-        const int r = i + 1 + rbase + rr;
+  const int lane = t % kWave, wave = t / kWave;
+  constexpr int nwaves = kTrdThreads / kWave;
+  // n <= kTrdMaxN <= kTrdThreads: thread t owns row i + t of column i in (a),
+  // and keeps A(i + 1 + t, i + 1) from step i's product for step i + 1.
+  double pre = 0.0;
+  bool have_pre = false;
+  for (int i0 = 0; i0 < n - 1; i0 += kTrdNb) {
+    const int nbp = n - 1 - i0 < kTrdNb ? n - 1 - i0 : kTrdNb;
+    for (int j = 0; j < nbp; ++j) {
+      const int i = i0 + j;
+      double* col = A + (int64_t)i * lda;
+      const double* vj = V + j * kTrdMaxN;
+      // (a) column i with the panel's deferred update; |A(i+2:n, i)|^2
+      double part = 0.0;
+      {
+        const int r = i + t;
+        if (r < n) {
+          double a = have_pre ? pre : col[r];
+          for (int k = 0; k < j; ++k)
+            a -= V[k * kTrdMaxN + r] * W[k * kTrdMaxN + i] + W[k * kTrdMaxN + r] * V[k * kTrdMaxN + i];
+          cv[r] = a;
+          if (r >= i + 2) part = fma(a, a, part);
+        }
+      }
+      const double xnorm2 = trd_block_sum(part, redA);
+      // (b) the reflector H = I - tau v v^T with H A(i+1:n, i) = beta e_1
+      const double alpha = cv[i + 1];
+      double taui = 0.0, beta = alpha, scal = 0.0;
+      if (xnorm2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        taui = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      if (t == 0) {
+        d[i] = cv[i];
+        e[i] = beta;
+        tau[i] = taui;
+      }
+      for (int r = i0 + t; r < n; r += kTrdThreads) {
+        double vr = 0.0;
+        if (r == i + 1) {
+          vr = 1.0;
+          col[r] = beta;
+        } else if (r >= i + 2) {
+          vr = cv[r] * scal;
+          col[r] = vr;
+        }
+        V[j * kTrdMaxN + r] = vr;
+      }
+      __syncthreads();
+      // (c) y1 = W^T v, y2 = V^T v over the panel's earlier columns (one wave
+      // per value) and the partial products of the unupdated trailing matrix.
+      for (int q = wave; q < 2 * j; q += nwaves) {
+        const double* M = q < j ? W + q * kTrdMaxN : V + (q - j) * kTrdMaxN;
         double acc = 0.0;
-        if (g < groups && r < n) {
-          const double vpr = pend ? vb[prev][r] : 0.0, wpr = pend ? wb[prev][r] : 0.0;
-          double* arow = A + r;
-#pragma unroll 8
-          for (int c = i + 1 + g; c < n; c += groups) {
-            double a = arow[(int64_t)c * lda];
-            if (pend) a -= vpr * wb[prev][c] + wpr * vb[prev][c];
-            arow[(int64_t)c * lda] = a;
-            acc = fma(a, vb[cur][c], acc);
+        for (int r = i + 1 + lane; r < n; r += kWave) acc = fma(M[r], vj[r], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) yv[q] = acc;
+      }
+      const int m = n - i - 1;
+      const int rows_pass = ((m + kWave - 1) / kWave) * kWave;
+      const int groups = kTrdThreads / rows_pass;  // 2..16 column groups
+      {
+        const int g = t / rows_pass, rr = t % rows_pass;
+        // column i + 1 is not modified again within the panel: keep its raw
+        // entry for the next step (thread t owns row i + 1 + t there)
+        have_pre = j + 1 < nbp && i + 1 + t < n;
+        if (have_pre) pre = A[(int64_t)(i + 1) * lda + i + 1 + t];
+        if (g < groups) {
+          const int r = i + 1 + rr;
+          double acc = 0.0;
+          if (r < n) {
+            // batches of 8 independent loads, issued before their sums
+            const int64_t step = (int64_t)groups * lda;
+            const double* ap = A + (int64_t)(i + 1 + g) * lda + r;
+            int c = i + 1 + g;
+            for (; c + 7 * groups < n; c += 8 * groups) {
+              double a[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) a[u] = ap[u * step];
+              ap += 8 * step;
+#pragma unroll
+              for (int u = 0; u < 8; ++u) acc = fma(a[u], vj[c + u * groups], acc);
+            }
+            for (; c < n; c += groups) {
+              acc = fma(*ap, vj[c], acc);
+              ap += step;
+            }
           }
+          pp[g * rows_pass + rr] = acc;
         }
-        if (g < groups && r < n) pp[g][r] = acc;
-        __syncthreads();
-        if (g == 0 && r < n) {
-          double s = pp[0][r];
-          for (int q = 1; q < groups; ++q) s += pp[q][r];
-          wb[cur][r] = taui * s;  // p (scaled), finished to w below
+      }
+      __syncthreads();
+      // (d) p = tau (A v - V y1 - W y2);  w = p - (tau/2)(p^T v) v
+      double dp = 0.0;
+      for (int r = i + 1 + t; r < n; r += kTrdThreads) {
+        const int rr = r - i - 1;
+        double pr = 0.0;
+        for (int q = 0; q < groups; ++q) pr += pp[q * rows_pass + rr];
+        for (int k = 0; k < j; ++k)
+          pr -= V[k * kTrdMaxN + r] * yv[k] + W[k * kTrdMaxN + r] * yv[j + k];
+        pr *= taui;
+        W[j * kTrdMaxN + r] = pr;
+        dp = fma(pr, vj[r], dp);
+      }
+      const double pv = trd_block_sum(dp, redB);
+      const double alpha2 = -0.5 * taui * pv;
+      for (int r = i0 + t; r < n; r += kTrdThreads)
+        W[j * kTrdMaxN + r] = r >= i + 1 ? fma(alpha2, vj[r], W[j * kTrdMaxN + r]) : 0.0;
+      __syncthreads();
+    }
+    // (e) A(c0:n, c0:n) -= V W^T + W V^T, both triangles, 4 x 4 tiles per thread.
+    const int c0 = i0 + nbp;
+    const int mt = n - c0;
+    const int ntr = (mt + 3) / 4;
+    for (int q = t; q < ntr * ntr; q += kTrdThreads) {
+      const int r0 = c0 + 4 * (q % ntr), cc0 = c0 + 4 * (q / ntr);
+      // the tile's entries are loaded first; their latency hides behind the sums
+      double acc[4][4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          acc[a][b] = (cc0 + b < n && r0 + a < n) ? A[(int64_t)(cc0 + b) * lda + r0 + a] : 0.0;
+      for (int k = 0; k < nbp; ++k) {
+        double vr[4], wr[4], vc[4], wc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const bool okr = r0 + a < n, okc = cc0 + a < n;
+          vr[a] = okr ? V[k * kTrdMaxN + r0 + a] : 0.0;
+          wr[a] = okr ? W[k * kTrdMaxN + r0 + a] : 0.0;
+          vc[a] = okc ? V[k * kTrdMaxN + cc0 + a] : 0.0;
+          wc[a] = okc ? W[k * kTrdMaxN + cc0 + a] : 0.0;
         }
-        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(-vr[a], wc[b], fma(-wr[a], vc[b], acc[a][b]));
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (cc0 + b >= n) continue;
+        double* ac = A + (int64_t)(cc0 + b) * lda;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          if (r0 + a < n) ac[r0 + a] = acc[a][b];
       }
     }
-    // (d) w = p - (tau/2)(p^T v) v
-    double dp = 0.0;
-    if (taui != 0.0)
-      for (int r = i + 1 + t; r < n; r += kTriThreads) dp = fma(wb[cur][r], vb[cur][r], dp);
-    const double pv = tri_block_sum(dp, red);
-    const double alpha2 = -0.5 * taui * pv;
-    for (int r = i + 1 + t; r < n; r += kTriThreads)
-      wb[cur][r] = taui != 0.0 ? fma(alpha2, vb[cur][r], wb[cur][r]) : 0.0;
     __syncthreads();
-    pend = taui != 0.0;
-    cur = prev;
   }
-  // last diagonal element with the final deferred update
-  if (t == 0) {
-    const int prev = cur ^ 1;
-    double a = A[(int64_t)(n - 1) * lda + (n - 1)];
-    if (pend && n >= 2) a -= 2.0 * vb[prev][n - 1] * wb[prev][n - 1];
-    d[n - 1] = a;
+  if (t == 0) d[n - 1] = A[(int64_t)(n - 1) * lda + (n - 1)];
+}
+
+// Z <- Q Z with Q = H(0) H(1) ... H(n-2) from sytrd_lower_kernel (the
+// back-transformation of the tridiagonal eigenvectors, LAPACK's dormtr with
+// side = 'L', uplo = 'L', trans = 'N').  A workgroup owns kOrmCols columns of
+// Z; 32 lanes of one wave own a column and hold its rows l, l + 32, ... in
+// registers, so applying a reflector is a shuffle reduction and an update in
+// registers, with no workgroup barrier.  Reflectors are staged through LDS
+// kOrmBatch at a time (last one first), each batch loaded into registers
+// while the previous one is applied.  Staged v_j is zero above row j + 1 and
+// beyond n, so the per-reflector loops need no bounds.
+constexpr int kOrmCols = 8;
+constexpr int kOrmBatch = 16;
+constexpr int kOrmThreads = 32 * kOrmCols;
+constexpr int kOrmRows = kTrdMaxN / 32;                  // rows per lane
+constexpr int kOrmLoad = kTrdMaxN / kOrmThreads;         // staged rows per thread per reflector
+
+__global__ __launch_bounds__(kOrmThreads) void ormtr_lower_kernel(int n, const double* __restrict__ A,
+                                                                  int64_t lda,
+                                                                  const double* __restrict__ tau,
+                                                                  double* __restrict__ Z,
+                                                                  int64_t ldz) {
+  __shared__ double Vb[kOrmBatch * kTrdMaxN];
+  __shared__ double tb[kOrmBatch];
+  const int t = threadIdx.x;
+  const int cc = t / 32, l32 = t % 32;
+  const int c = blockIdx.x * kOrmCols + cc;
+  double z[kOrmRows];
+#pragma unroll
+  for (int q = 0; q < kOrmRows; ++q) {
+    const int r = l32 + 32 * q;
+    z[q] = (c < n && r < n) ? Z[(int64_t)c * ldz + r] : 0.0;
+  }
+  // staged value of reflector j at row r
+  auto vload = [&](int j, int r) -> double {
+    if (j < 0 || r >= n || r <= j) return 0.0;
+    return r == j + 1 ? 1.0 : A[(int64_t)j * lda + r];
+  };
+  double nb[kOrmBatch][kOrmLoad];
+  double ntau = 0.0;
+  {
+    const int hi = n - 2;
+#pragma unroll
+    for (int b = 0; b < kOrmBatch; ++b)
+#pragma unroll
+      for (int q = 0; q < kOrmLoad; ++q) nb[b][q] = vload(hi - b, t + kOrmThreads * q);
+    if (t < kOrmBatch && hi - t >= 0) ntau = tau[hi - t];
+  }
+  for (int hi = n - 2; hi >= 0; hi -= kOrmBatch) {
+    __syncthreads();  // the previous batch is no longer read
+#pragma unroll
+    for (int b = 0; b < kOrmBatch; ++b)
+#pragma unroll
+      for (int q = 0; q < kOrmLoad; ++q) Vb[b * kTrdMaxN + t + kOrmThreads * q] = nb[b][q];
+    if (t < kOrmBatch) tb[t] = hi - t >= 0 ? ntau : 0.0;
+    __syncthreads();
+    const int hn = hi - kOrmBatch;
+    if (hn >= 0) {
+#pragma unroll
+      for (int b = 0; b < kOrmBatch; ++b)
+#pragma unroll
+        for (int q = 0; q < kOrmLoad; ++q) nb[b][q] = vload(hn - b, t + kOrmThreads * q);
+      ntau = (t < kOrmBatch && hn - t >= 0) ? tau[hn - t] : 0.0;
+    }
+    const int nbat = hi + 1 < kOrmBatch ? hi + 1 : kOrmBatch;
+    for (int b = 0; b < nbat; ++b) {
+      const double* v = Vb + b * kTrdMaxN + l32;
+      double sdot = 0.0;
+#pragma unroll
+      for (int q = 0; q < kOrmRows; ++q) sdot = fma(v[32 * q], z[q], sdot);
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) sdot += __shfl_xor(sdot, off, 32);
+      const double f = tb[b] * sdot;
+#pragma unroll
+      for (int q = 0; q < kOrmRows; ++q) z[q] = fma(-f, v[32 * q], z[q]);
+    }
+  }
+  if (c < n) {
+#pragma unroll
+    for (int q = 0; q < kOrmRows; ++q) {
+      const int r = l32 + 32 * q;
+      if (r < n) Z[(int64_t)c * ldz + r] = z[q];
+    }
   }
 }
 
@@ -1254,18 +1411,28 @@ void launch_fro(int m, int n, const double* A, int64_t lda, double* out, hipStre
   LOBPCG_HIP(hipGetLastError());
 }
 
-void launch_sytd2_lower(int n, double* A, int64_t lda, double* d, double* e, double* tau,
+void launch_sytrd_lower(int n, double* A, int64_t lda, double* d, double* e, double* tau,
                         hipStream_t s) {
-  LOBPCG_CHECK(n >= 1 && n <= kTriMaxN, LOBPCG_ERR_ARG, "sytd2: n out of range");
+  LOBPCG_CHECK(n >= 1 && n <= kTrdMaxN, LOBPCG_ERR_ARG, "sytrd: n out of range");
   if (n == 1) {
     LOBPCG_HIP(hipMemcpyAsync(d, A, sizeof(double), hipMemcpyDeviceToDevice, s));
     return;
   }
-  hipLaunchKernelGGL(sytd2_lower_kernel, dim3(1), dim3(kTriThreads), 0, s, n, A, lda, d, e, tau);
+  hipLaunchKernelGGL(sytrd_lower_kernel, dim3(1), dim3(kTrdThreads), 0, s, n, A, lda, d, e, tau);
   LOBPCG_HIP(hipGetLastError());
 }
 
-int sytd2_max_n() { return kTriMaxN; }
+int sytrd_max_n() { return kTrdMaxN; }
+
+void launch_ormtr_lower(int n, const double* A, int64_t lda, const double* tau, double* Z,
+                        int64_t ldz, hipStream_t s) {
+  LOBPCG_CHECK(n >= 1 && n <= kTrdMaxN, LOBPCG_ERR_ARG, "ormtr: n out of range");
+  if (n < 2) return;
+  const unsigned grid = (unsigned)((n + kOrmCols - 1) / kOrmCols);
+  hipLaunchKernelGGL(ormtr_lower_kernel, dim3(grid), dim3(kOrmThreads), 0, s, n, A, lda, tau, Z,
+                     ldz);
+  LOBPCG_HIP(hipGetLastError());
+}
 
 void launch_sqrt_sum(int n, const double* v, double* out, hipStream_t s) {
   hipLaunchKernelGGL(sqrt_sum_kernel, dim3(1), dim3(256), 0, s, n, v, out);

