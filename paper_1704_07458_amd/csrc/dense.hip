@@ -175,8 +175,13 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
            Z + nc * ld, ld, 0.0, Mt, ldm);
     }
     // LQ of Mt^T == QR of Mt (Householder): Q (m x np) orthonormal columns.
-    LOBPCG_ROCBLAS(rocsolver_dgeqrf(h_, m, na, Mt, (rocblas_int)ldm, tau_.as<double>()));
-    LOBPCG_ROCBLAS(rocsolver_dorgqr(h_, m, np, np, Mt, (rocblas_int)ldm, tau_.as<double>()));
+    // Only the first np columns enter Q (np = min(na, m)).
+    if (geqrf_orgqr_fits(m, np)) {
+      launch_geqrf_orgqr(m, np, Mt, ldm, s_);
+    } else {
+      LOBPCG_ROCBLAS(rocsolver_dgeqrf(h_, m, na, Mt, (rocblas_int)ldm, tau_.as<double>()));
+      LOBPCG_ROCBLAS(rocsolver_dorgqr(h_, m, np, np, Mt, (rocblas_int)ldm, tau_.as<double>()));
+    }
     // C_p = T Z_perp Q.
     double* ZQ = ZQ_.as<double>();
     gemm(rocblas_operation_none, rocblas_operation_none, ns, np, m, 1.0, Z + nx * ld, ld, Mt, ldm,

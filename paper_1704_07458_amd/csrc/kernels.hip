@@ -1173,6 +1173,134 @@ __global__ __launch_bounds__(kOrmThreads) void ormtr_lower_kernel(int n, const d
   }
 }
 
+// ------------------------------------------------------------------ QR
+// Householder QR of an m x k block (column-major, ld) followed by the
+// explicit Q (m x k): LAPACK's dgeqrf + dorgqr conventions (beta = -sign(alpha)
+// |x|, tau = (beta - alpha) / beta, v = x / (alpha - beta), H = I when the
+// column below the diagonal is zero).  One workgroup, the block in registers:
+// thread (c, g) holds column c, rows [g kQrRows, (g + 1) kQrRows).  A step is a
+// norm from kQrGroups partials, the reflector broadcast through LDS, one dot
+// product per column reduced over the kQrGroups row groups through LDS, and a register
+// update.  Q overwrites the block.  m <= kQrMaxM, k <= kQrCols.
+constexpr int kQrThreads = 1024;
+constexpr int kQrCols = 128;
+constexpr int kQrGroups = kQrThreads / kQrCols;
+constexpr int kQrRows = 32;
+constexpr int kQrMaxM = kQrGroups * kQrRows;
+
+__global__ __launch_bounds__(kQrThreads) void geqrf_orgqr_kernel(int m, int k,
+                                                                 double* __restrict__ M,
+                                                                 int64_t ldm) {
+  __shared__ double vbuf[2][kQrMaxM];
+  __shared__ double wpart[kQrGroups][kQrCols];
+  __shared__ double taus[kQrCols];
+  const int t = threadIdx.x;
+  const int c = t % kQrCols, g = t / kQrCols;
+  const int r0 = g * kQrRows;
+  double a[kQrRows];
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int r = r0 + q;
+    a[q] = (c < k && r < m) ? M[(int64_t)c * ldm + r] : 0.0;
+  }
+  for (int r = t; r < kQrMaxM; r += kQrThreads) vbuf[0][r] = vbuf[1][r] = 0.0;
+  // ---- factorisation
+  for (int j = 0; j < k; ++j) {
+    // column j to LDS; wave 0 forms the reflector and the stored column
+    // (R above the diagonal, beta on it, v below) there, so the register
+    // loops below need no tests against the diagonal
+    double* col = vbuf[1];
+    if (c == j) {
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) col[r0 + q] = a[q];
+    }
+    __syncthreads();
+    if (t < kWave) {
+      double sq = 0.0;
+      for (int r = j + 1 + t; r < m; r += kWave) sq = fma(col[r], col[r], sq);
+      sq = wave_sum(sq);
+      const double alpha = col[j];
+      double tj = 0.0, beta = alpha, scal = 0.0;
+      if (sq > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + sq), alpha);
+        tj = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      for (int r = t; r < kQrMaxM; r += kWave) {
+        const double x = col[r];
+        const double v = r > j ? x * scal : (r == j ? 1.0 : 0.0);
+        vbuf[0][r] = v;
+        col[r] = r > j ? v : (r == j ? beta : x);
+      }
+      if (t == 0) taus[j] = tj;
+    }
+    __syncthreads();
+    if (c == j) {
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) a[q] = col[r0 + q];
+    }
+    const bool act = c > j && c < k;
+    if (act) {
+      double sdot = 0.0;
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) sdot = fma(vbuf[0][r0 + q], a[q], sdot);
+      wpart[g][c] = sdot;
+    }
+    __syncthreads();
+    if (act) {
+      double w = 0.0;
+#pragma unroll
+      for (int q = 0; q < kQrGroups; ++q) w += wpart[q][c];
+      const double f = taus[j] * w;
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) a[q] = fma(-f, vbuf[0][r0 + q], a[q]);
+    }
+  }
+  // reflectors (below the diagonal) back to M; Q is built from them below
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int r = r0 + q;
+    if (c < k && r < m) M[(int64_t)c * ldm + r] = a[q];
+  }
+  __syncthreads();
+  // ---- Q = H(0) ... H(k-1) I(:, 0:k), last reflector first
+  auto vval = [&](int j, int r) -> double {
+    if (j < 0 || r < j || r >= m) return 0.0;
+    return r == j ? 1.0 : M[(int64_t)j * ldm + r];
+  };
+  double pre = t < kQrMaxM ? vval(k - 1, t) : 0.0;
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) a[q] = (c < k && r0 + q == c) ? 1.0 : 0.0;
+  for (int j = k - 1; j >= 0; --j) {
+    double* vb = vbuf[j & 1];
+    if (t < kQrMaxM) vb[t] = pre;
+    __syncthreads();
+    if (t < kQrMaxM) pre = vval(j - 1, t);
+    const double tj = taus[j];
+    if (c < k) {
+      double sdot = 0.0;
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) sdot = fma(vb[r0 + q], a[q], sdot);
+      wpart[g][c] = sdot;
+    }
+    __syncthreads();
+    if (c < k) {
+      double w = 0.0;
+#pragma unroll
+      for (int q = 0; q < kQrGroups; ++q) w += wpart[q][c];
+      const double f = tj * w;
+#pragma unroll
+      for (int q = 0; q < kQrRows; ++q) a[q] = fma(-f, vb[r0 + q], a[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kQrRows; ++q) {
+    const int r = r0 + q;
+    if (c < k && r < m) M[(int64_t)c * ldm + r] = a[q];
+  }
+}
+
 inline unsigned blocks_for(int64_t total, int threads = 256) {
   return (unsigned)((total + threads - 1) / threads);
 }
@@ -1423,6 +1551,14 @@ void launch_sytrd_lower(int n, double* A, int64_t lda, double* d, double* e, dou
 }
 
 int sytrd_max_n() { return kTrdMaxN; }
+
+bool geqrf_orgqr_fits(int m, int k) { return m >= 1 && m <= kQrMaxM && k >= 1 && k <= kQrCols && k <= m; }
+
+void launch_geqrf_orgqr(int m, int k, double* M, int64_t ldm, hipStream_t s) {
+  LOBPCG_CHECK(geqrf_orgqr_fits(m, k) && ldm >= m, LOBPCG_ERR_ARG, "geqrf_orgqr: sizes out of range");
+  hipLaunchKernelGGL(geqrf_orgqr_kernel, dim3(1), dim3(kQrThreads), 0, s, m, k, M, ldm);
+  LOBPCG_HIP(hipGetLastError());
+}
 
 void launch_ormtr_lower(int n, const double* A, int64_t lda, const double* tau, double* Z,
                         int64_t ldz, hipStream_t s) {

@@ -120,6 +120,11 @@ void launch_fro(int m, int n, const double* A, int64_t lda, double* out, hipStre
 void launch_sytrd_lower(int n, double* A, int64_t lda, double* d, double* e, double* tau,
                         hipStream_t s);
 int sytrd_max_n();
+// Householder QR of the m x k block M (column-major, ld ldm, k <= m) and the
+// explicit Q (m x k) in its place, in one workgroup (dgeqrf + dorgqr); valid
+// when geqrf_orgqr_fits(m, k).
+bool geqrf_orgqr_fits(int m, int k);
+void launch_geqrf_orgqr(int m, int k, double* M, int64_t ldm, hipStream_t s);
 // Z <- Q Z (n x n, column-major, ldz) with Q the product of the reflectors
 // that launch_sytrd_lower left in A and tau (n <= sytrd_max_n()).
 void launch_ormtr_lower(int n, const double* A, int64_t lda, const double* tau, double* Z,
