@@ -184,8 +184,13 @@ const char* lobpcg_last_error(void);
  *   kind 1 Gram blocks          work = flops: 2*n*m*p
  *   kind 2 basis updates        work = flops: 2*n*K*N
  *   kind 3 residual + test      work = bytes: (3 or 4)*n*n_x*s_v + 8*n
- *   kind 4 Rayleigh-Ritz        work = 0 (dense FP64 on the projected pencil)
- * (s_v = 8 for FP64, 4 for FP32 blocks.)  kinds 5-7 are reserved (zero). */
+ *   kind 4 Rayleigh-Ritz        work = 0 (dense FP64 on the projected pencil,
+ *                               kinds 5-7 included)
+ *   kind 5 tridiagonalisation   work = flops: (4/3) n_s^3 (one-workgroup Householder)
+ *   kind 6 tridiagonal eigenproblem (library divide and conquer)   work = 0
+ *   kind 7 P-block QR and eigenvector back-transformation kernels  work = 0
+ * (s_v = 8 for FP64, 4 for FP32 blocks.)  Kinds 5-7 are recorded only for
+ * projected problems within the one-workgroup kernels' size range. */
 typedef struct {
   int64_t launches;
   double seconds;

@@ -94,7 +94,8 @@ class lobpcg_kernel_stat(C.Structure):
     _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("work", C.c_double)]
 
 
-KERNEL_KINDS = ["spmm", "gram", "update", "residual", "rayleigh_ritz"]
+KERNEL_KINDS = ["spmm", "gram", "update", "residual", "rayleigh_ritz", "tridiagonalise",
+                "tridiagonal_eig", "qr_backtransform"]
 
 PRECOND_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
                          C.c_int64, C.c_void_p, C.c_int64, C.c_void_p)

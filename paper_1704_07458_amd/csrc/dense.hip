@@ -27,6 +27,9 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax)
   if (const char* e = std::getenv("LOBPCG_TRIDIAG_MAX_N")) kTridiagMaxN = std::atoi(e);
   LOBPCG_ROCBLAS(rocblas_create_handle(&h_));
   LOBPCG_ROCBLAS(rocblas_set_stream(h_, s_));
+  // Reproducible results: no split-K GEMM kernels that accumulate with
+  // atomics (run-to-run rounding differences would change the iteration).
+  LOBPCG_ROCBLAS(rocblas_set_atomics_mode(h_, rocblas_atomics_not_allowed));
   const size_t sq = sizeof(double) * (size_t)nsmax * nsmax;
   H_.alloc(sq);
   R_.alloc(sq);
@@ -81,10 +84,20 @@ void Dense::syev(int n, double* A, int64_t lda, double* w) {
     double* e = E_.as<double>();
     double* tau = tau_.as<double>();
     double* Z = T1_.as<double>();
+    int tok = timer_ ? timer_->start(s_) : -1;
     launch_sytrd_lower(n, A, lda, w, e, tau, s_);
+    if (timer_) {
+      timer_->stop(tok, 5, 4.0 / 3.0 * n * (double)n * n, s_);
+      tok = timer_->start(s_);
+    }
     LOBPCG_ROCBLAS(rocsolver_dstedc(h_, rocblas_evect_tridiagonal, n, w, e, Z, (rocblas_int)nsmax_,
                                     dinfo));
+    if (timer_) {
+      timer_->stop(tok, 6, 0.0, s_);
+      tok = timer_->start(s_);
+    }
     launch_ormtr_lower(n, A, lda, tau, Z, nsmax_, s_);
+    if (timer_) timer_->stop(tok, 7, 0.0, s_);
     copy_cm(n, n, Z, nsmax_, A, lda, s_);
   } else {
     LOBPCG_ROCBLAS(rocsolver_dsyevd(h_, rocblas_evect_original, rocblas_fill_upper, n, A,
@@ -177,7 +190,9 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
     // LQ of Mt^T == QR of Mt (Householder): Q (m x np) orthonormal columns.
     // Only the first np columns enter Q (np = min(na, m)).
     if (geqrf_orgqr_fits(m, np)) {
+      const int tok = timer_ ? timer_->start(s_) : -1;
       launch_geqrf_orgqr(m, np, Mt, ldm, s_);
+      if (timer_) timer_->stop(tok, 7, 0.0, s_);
     } else {
       LOBPCG_ROCBLAS(rocsolver_dgeqrf(h_, m, na, Mt, (rocblas_int)ldm, tau_.as<double>()));
       LOBPCG_ROCBLAS(rocsolver_dorgqr(h_, m, np, np, Mt, (rocblas_int)ldm, tau_.as<double>()));

@@ -10,6 +10,7 @@
 #include <cstdint>
 
 #include "common.hpp"
+#include "timer.hpp"
 
 namespace lobpcg {
 
@@ -52,6 +53,9 @@ class Dense {
   // above), 1 = syevdj, 2 = syevj, 3 = syevd always.  The environment variable
   // LOBPCG_EIGENSOLVER overrides the default.
   void set_eigensolver(int which) { eig_ = which; }
+  // Kernel-class timing of the tridiagonalisation (kind 5), the tridiagonal
+  // eigensolver (kind 6) and the QR / back-transformation kernels (kind 7).
+  void set_timer(KernelTimer* t) { timer_ = t; }
 
  private:
   void gemm(rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double alpha,
@@ -63,6 +67,7 @@ class Dense {
   hipStream_t s_;
   rocblas_handle h_ = nullptr;
   int eig_ = 0;
+  KernelTimer* timer_ = nullptr;
   int kTridiagMaxN = 512;
   // scratch (column-major, leading dimension nsmax_)
   DevBuf H_, R_, Ri_, T1_, Mt_, ZQ_, Qs_, d_, E_, tau_, info_, cond_, th2_, scale_, sinfo_;

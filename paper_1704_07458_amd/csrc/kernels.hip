@@ -1204,6 +1204,7 @@ __global__ __launch_bounds__(kQrThreads) void geqrf_orgqr_kernel(int m, int k,
     a[q] = (c < k && r < m) ? M[(int64_t)c * ldm + r] : 0.0;
   }
   for (int r = t; r < kQrMaxM; r += kQrThreads) vbuf[0][r] = vbuf[1][r] = 0.0;
+  __syncthreads();  // the first step stages column 0 into vbuf[1]
   // ---- factorisation
   for (int j = 0; j < k; ++j) {
     // column j to LDS; wave 0 forms the reflector and the stored column

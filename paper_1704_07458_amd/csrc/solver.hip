@@ -167,6 +167,7 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
                         dinv_.as<double>(), work_.get(), s_);
   }
   dense_.reset(new Dense(nsmax_, nx_, s_));
+  dense_->set_timer(&timer_);
   LOBPCG_HIP(hipHostMalloc((void**)&hbuf_, sizeof(int32_t) * 8, hipHostMallocDefault));
   LOBPCG_HIP(hipHostMalloc((void**)&hdbl_, sizeof(double) * 8, hipHostMallocDefault));
   LOBPCG_HIP(hipStreamSynchronize(s_));

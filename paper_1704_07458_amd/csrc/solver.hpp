@@ -27,31 +27,6 @@ struct Blocks {
   void alloc(int64_t n, int64_t ldS, int64_t ldX, bool haveB);
 };
 
-// HIP-event timing of kernel classes (roofline accounting).
-class KernelTimer {
- public:
-  ~KernelTimer();
-  void enable(bool on);
-  bool on() const { return on_; }
-  // Record a start event for `kind`; returns a token for stop().
-  int start(hipStream_t s);
-  void stop(int token, int kind, double work, hipStream_t s);
-  // Synchronise, fold finished records into the totals.
-  void collect();
-  lobpcg_kernel_stat totals[8] = {};
-
- private:
-  hipEvent_t event(size_t i);
-  struct Rec {
-    int kind;
-    int e0, e1;
-    double work;
-  };
-  bool on_ = false;
-  std::vector<hipEvent_t> pool_;
-  size_t used_ = 0;
-  std::vector<Rec> recs_;
-};
 
 class Solver {
  public:

@@ -144,7 +144,10 @@ class _AdjointCase:
         self.wts = rng.uniform(0.0, 1.0, k)
         self.m = rng.uniform(0.0, 1.0, w.A.n)
         self.A = A = w.A.to_scipy()
-        s = B.Solver(w.A, k, precond="jacobi", maxit=4000)
+        # tol 1e-13 is below the residual floor that orthogonalised W keeps at
+        # the default tau_ortho (~1e-12) should the iteration switch to it, so
+        # tau_ortho is tightened as for the perturbed solves below
+        s = B.Solver(w.A, k, precond="jacobi", maxit=4000, tau_ortho=1e-15)
         info = s.solve(1e-13, w.X0)
         assert info["converged"], info
         lam, X, _ = s.eigpairs(k)

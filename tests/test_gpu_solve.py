@@ -263,3 +263,20 @@ def test_adjoint_matches_dense_reference_8cubed(lib):
     g = grad.cpu().numpy()
     assert np.linalg.norm(g - g_ref) <= 1e-7 * np.linalg.norm(g_ref)
     assert iters > 0
+
+
+def test_solve_is_bitwise_reproducible(lib):
+    """Fresh solvers on the same input take the same iterations to the same bits."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    w = P.workload(4, small=True)
+    res = []
+    for _ in range(3):
+        s = B.Solver(w.A, w.k, precond="jacobi")
+        info = s.solve(w.tol, torch.from_numpy(w.X0).cuda())
+        lam, X, _ = s.eigpairs(w.k)
+        res.append((info["iterations"], lam.cpu().numpy(), X.cpu().numpy()))
+    for it, lam, X in res[1:]:
+        assert it == res[0][0]
+        assert np.array_equal(lam, res[0][1]) and np.array_equal(X, res[0][2])
