@@ -21,7 +21,10 @@ namespace lobpcg {
                                                 rocblas_status_to_string(st_));            \
   } while (0)
 
-Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax), s_(s) {
+// The internal leading dimension is even: the tridiagonalisation then reads
+// rows in 16-byte pairs.
+Dense::Dense(int nsmax, int nxmax, hipStream_t s)
+    : nsmax_(nsmax + (nsmax & 1)), nxmax_(nxmax), s_(s) {
   if (const char* e = std::getenv("LOBPCG_EIGENSOLVER")) eig_ = std::atoi(e);
   kTridiagMaxN = std::min(512, sytrd_max_n());
   if (const char* e = std::getenv("LOBPCG_TRIDIAG_MAX_N")) kTridiagMaxN = std::atoi(e);
@@ -30,7 +33,7 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax)
   // Reproducible results: no split-K GEMM kernels that accumulate with
   // atomics (run-to-run rounding differences would change the iteration).
   LOBPCG_ROCBLAS(rocblas_set_atomics_mode(h_, rocblas_atomics_not_allowed));
-  const size_t sq = sizeof(double) * (size_t)nsmax * nsmax;
+  const size_t sq = sizeof(double) * (size_t)nsmax_ * nsmax_;
   H_.alloc(sq);
   R_.alloc(sq);
   Ri_.alloc(sq);
@@ -38,11 +41,11 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s) : nsmax_(nsmax), nxmax_(nxmax)
   Mt_.alloc(sq);
   ZQ_.alloc(sq);
   Qs_.alloc(sq);
-  d_.alloc(sizeof(double) * nsmax);
-  E_.alloc(sizeof(double) * 2 * nsmax);
-  tau_.alloc(sizeof(double) * nsmax);
-  th2_.alloc(sizeof(double) * nsmax);
-  scale_.alloc(sizeof(double) * nsmax);
+  d_.alloc(sizeof(double) * nsmax_);
+  E_.alloc(sizeof(double) * 2 * nsmax_);
+  tau_.alloc(sizeof(double) * nsmax_);
+  th2_.alloc(sizeof(double) * nsmax_);
+  scale_.alloc(sizeof(double) * nsmax_);
   info_.alloc(sizeof(int32_t) * 8);
   cond_.alloc(sizeof(double) * 2);
   sinfo_.alloc(sizeof(int32_t) * 2);

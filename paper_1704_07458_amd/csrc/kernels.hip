@@ -924,6 +924,7 @@ __device__ __forceinline__ double trd_block_sum(double v, double* red) {
   return s;
 }
 
+template <bool kPairs>
 __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double* __restrict__ A,
                                                                   int64_t lda,
                                                                   double* __restrict__ d,
@@ -932,7 +933,7 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
   __shared__ double V[kTrdNb * kTrdMaxN];  // V[k * kTrdMaxN + r]: reflector k of the panel
   __shared__ double W[kTrdNb * kTrdMaxN];  // W[k * kTrdMaxN + r]
   __shared__ double cv[kTrdMaxN];          // the current column, updated
-  __shared__ double pp[kTrdThreads];       // partial products per column group
+  __shared__ double pp[2 * kTrdThreads];   // partial products per column group
   __shared__ double yv[2 * kTrdNb];        // W^T v, V^T v
   __shared__ double redA[kTrdThreads / kWave], redB[kTrdThreads / kWave];
   const int t = threadIdx.x;
@@ -995,44 +996,73 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
         acc = wave_sum(acc);
         if (lane == 0) yv[q] = acc;
       }
-      const int m = n - i - 1;
-      const int rows_pass = ((m + kWave - 1) / kWave) * kWave;
-      const int groups = kTrdThreads / rows_pass;  // 2..16 column groups
+      // Rows are taken in pairs [rb + 2q, rb + 2q + 1] (rb = i + 1, rounded down
+      // to even when kPairs) so that one 16-byte load covers two rows: the
+      // product is bound by load instructions, not bytes.  Column groups split
+      // the columns; a thread sums its rows over its group's columns.
+      constexpr int kR = kPairs ? 2 : 1;
+      const int rb = kPairs ? ((i + 1) & ~1) : i + 1;
+      const int nq = (n - rb + kR - 1) / kR;
+      const int q_pass = ((nq + kWave - 1) / kWave) * kWave;
+      const int groups = kTrdThreads / q_pass;  // 2..16 column groups
+      const int rows_pass = kR * q_pass;
       {
-        const int g = t / rows_pass, rr = t % rows_pass;
+        const int g = t / q_pass, qq = t % q_pass;
         // column i + 1 is not modified again within the panel: keep its raw
         // entry for the next step (thread t owns row i + 1 + t there)
         have_pre = j + 1 < nbp && i + 1 + t < n;
         if (have_pre) pre = A[(int64_t)(i + 1) * lda + i + 1 + t];
         if (g < groups) {
-          const int r = i + 1 + rr;
-          double acc = 0.0;
-          if (r < n) {
+          const int r0 = rb + kR * qq;
+          double acc0 = 0.0, acc1 = 0.0;
+          if (r0 < n) {
             // batches of 8 independent loads, issued before their sums
             const int64_t step = (int64_t)groups * lda;
-            const double* ap = A + (int64_t)(i + 1 + g) * lda + r;
+            const double* ap = A + (int64_t)(i + 1 + g) * lda + r0;
             int c = i + 1 + g;
-            for (; c + 7 * groups < n; c += 8 * groups) {
-              double a[8];
+            if (kPairs && r0 + 1 < n) {
+              for (; c + 7 * groups < n; c += 8 * groups) {
+                double2 av[8];
 #pragma unroll
-              for (int u = 0; u < 8; ++u) a[u] = ap[u * step];
-              ap += 8 * step;
+                for (int u = 0; u < 8; ++u) av[u] = *reinterpret_cast<const double2*>(ap + u * step);
+                ap += 8 * step;
 #pragma unroll
-              for (int u = 0; u < 8; ++u) acc = fma(a[u], vj[c + u * groups], acc);
-            }
-            for (; c < n; c += groups) {
-              acc = fma(*ap, vj[c], acc);
-              ap += step;
+                for (int u = 0; u < 8; ++u) {
+                  const double vc = vj[c + u * groups];
+                  acc0 = fma(av[u].x, vc, acc0);
+                  acc1 = fma(av[u].y, vc, acc1);
+                }
+              }
+              for (; c < n; c += groups) {
+                const double2 av = *reinterpret_cast<const double2*>(ap);
+                acc0 = fma(av.x, vj[c], acc0);
+                acc1 = fma(av.y, vj[c], acc1);
+                ap += step;
+              }
+            } else {
+              for (; c + 7 * groups < n; c += 8 * groups) {
+                double av[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) av[u] = ap[u * step];
+                ap += 8 * step;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc0 = fma(av[u], vj[c + u * groups], acc0);
+              }
+              for (; c < n; c += groups) {
+                acc0 = fma(*ap, vj[c], acc0);
+                ap += step;
+              }
             }
           }
-          pp[g * rows_pass + rr] = acc;
+          pp[g * rows_pass + kR * qq] = acc0;
+          if (kPairs) pp[g * rows_pass + kR * qq + 1] = acc1;
         }
       }
       __syncthreads();
       // (d) p = tau (A v - V y1 - W y2);  w = p - (tau/2)(p^T v) v
       double dp = 0.0;
       for (int r = i + 1 + t; r < n; r += kTrdThreads) {
-        const int rr = r - i - 1;
+        const int rr = r - rb;
         double pr = 0.0;
         for (int q = 0; q < groups; ++q) pr += pp[q * rows_pass + rr];
         for (int k = 0; k < j; ++k)
@@ -1547,7 +1577,12 @@ void launch_sytrd_lower(int n, double* A, int64_t lda, double* d, double* e, dou
     LOBPCG_HIP(hipMemcpyAsync(d, A, sizeof(double), hipMemcpyDeviceToDevice, s));
     return;
   }
-  hipLaunchKernelGGL(sytrd_lower_kernel, dim3(1), dim3(kTrdThreads), 0, s, n, A, lda, d, e, tau);
+  if (lda % 2 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0)
+    hipLaunchKernelGGL(sytrd_lower_kernel<true>, dim3(1), dim3(kTrdThreads), 0, s, n, A, lda, d, e,
+                       tau);
+  else
+    hipLaunchKernelGGL(sytrd_lower_kernel<false>, dim3(1), dim3(kTrdThreads), 0, s, n, A, lda, d, e,
+                       tau);
   LOBPCG_HIP(hipGetLastError());
 }
 
