@@ -10,6 +10,7 @@
 #include <string>
 
 #include "kernels.hpp"
+#include "tridiag_dc.hpp"
 
 namespace lobpcg {
 
@@ -49,6 +50,11 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s)
   info_.alloc(sizeof(int32_t) * 8);
   cond_.alloc(sizeof(double) * 2);
   sinfo_.alloc(sizeof(int32_t) * 2);
+  dcY_.alloc(sq);
+  dcv_.alloc(sizeof(double) * 4 * nsmax_);
+  dci_.alloc(sizeof(int32_t) * tridiag_dc_int_workspace());
+  dcw_.alloc(sizeof(double) * 2 * tridiag_dc_max_n());
+  dcr_.alloc(sizeof(double) * 64);
   LOBPCG_HIP(hipHostMalloc((void**)&hinfo_, sizeof(int32_t) * 8, hipHostMallocDefault));
   LOBPCG_HIP(hipHostMalloc((void**)&hcond_, sizeof(double) * 2, hipHostMallocDefault));
 }
@@ -81,7 +87,7 @@ void Dense::syev(int n, double* A, int64_t lda, double* w) {
   } else if (eig_ == 1) {
     LOBPCG_ROCBLAS(rocsolver_dsyevdj(h_, rocblas_evect_original, rocblas_fill_upper, n, A,
                                      (rocblas_int)lda, w, dinfo));
-  } else if (eig_ == 0 && n <= kTridiagMaxN && n >= 2) {
+  } else if ((eig_ == 0 || eig_ == 4) && n <= kTridiagMaxN && n >= 2) {
     // Householder tridiagonalisation in one workgroup (kernels.hip), then
     // divide and conquer on the tridiagonal and the back-transformation Q Z_T.
     double* e = E_.as<double>();
@@ -93,8 +99,14 @@ void Dense::syev(int n, double* A, int64_t lda, double* w) {
       timer_->stop(tok, 5, 4.0 / 3.0 * n * (double)n * n, s_);
       tok = timer_->start(s_);
     }
-    LOBPCG_ROCBLAS(rocsolver_dstedc(h_, rocblas_evect_tridiagonal, n, w, e, Z, (rocblas_int)nsmax_,
-                                    dinfo));
+    if (eig_ == 0 && n <= tridiag_dc_max_n()) {
+      tridiag_dc(n, w, e, w, Z, nsmax_, Mt_.as<double>(), ZQ_.as<double>(), Qs_.as<double>(),
+                 dcY_.as<double>(), dcv_.as<double>(), dci_.as<int32_t>(), dcw_.as<double>(),
+                 dcr_.as<double>(), h_, s_);
+    } else {
+      LOBPCG_ROCBLAS(rocsolver_dstedc(h_, rocblas_evect_tridiagonal, n, w, e, Z,
+                                      (rocblas_int)nsmax_, dinfo));
+    }
     if (timer_) {
       timer_->stop(tok, 6, 0.0, s_);
       tok = timer_->start(s_);

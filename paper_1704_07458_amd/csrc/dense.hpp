@@ -49,9 +49,10 @@ class Dense {
   hipStream_t stream() const { return s_; }
 
   // Eigen-solver selection for the projected problem: 0 = automatic (the
-  // one-workgroup tridiagonalisation + stedc + ormtr up to kTridiagMaxN, syevd
-  // above), 1 = syevdj, 2 = syevj, 3 = syevd always.  The environment variable
-  // LOBPCG_EIGENSOLVER overrides the default.
+  // one-workgroup tridiagonalisation, divide and conquer on the tridiagonal and
+  // the back-transformation up to kTridiagMaxN, syevd above), 1 = syevdj,
+  // 2 = syevj, 3 = syevd always, 4 = as 0 with rocSOLVER's stedc for the
+  // tridiagonal.  The environment variable LOBPCG_EIGENSOLVER overrides it.
   void set_eigensolver(int which) { eig_ = which; }
   // Kernel-class timing of the tridiagonalisation (kind 5), the tridiagonal
   // eigensolver (kind 6) and the QR / back-transformation kernels (kind 7).
@@ -71,6 +72,7 @@ class Dense {
   int kTridiagMaxN = 512;
   // scratch (column-major, leading dimension nsmax_)
   DevBuf H_, R_, Ri_, T1_, Mt_, ZQ_, Qs_, d_, E_, tau_, info_, cond_, th2_, scale_, sinfo_;
+  DevBuf dcY_, dcv_, dci_, dcw_, dcr_;  // divide-and-conquer workspace
   int32_t* hinfo_ = nullptr;  // pinned host status words
   double* hcond_ = nullptr;
 };

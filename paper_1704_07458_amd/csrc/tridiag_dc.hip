@@ -1,0 +1,623 @@
+// Divide and conquer for the symmetric tridiagonal eigenproblem T = Z diag(lam) Z^T
+// (the step after the Householder tridiagonalisation of the projected matrix).
+//
+// Cuppen's tear: T = diag(T1, T2) + |b| w w^T with b = e[mid-1], w = e_{mid-1} +
+// sign(b) e_mid, so T1's last and T2's first diagonal entries lose |b|.  A
+// merge solves D + rho z z^T (D, Q from the halves, z = Q^T w / sqrt 2, rho = 2|b|)
+// with LAPACK-style deflation (tiny rho |z_i|, and close pairs rotated until one
+// z component vanishes), the secular equation 1 + rho sum z_i^2 / (d_i - lam) = 0
+// solved root by root by bisection in the variable shifted to the nearer pole
+// (so d_i - lam keeps full relative accuracy), z recomputed from the computed
+// roots (Gu and Eisenstat) so that the eigenvectors z_i / (d_i - lam_j) are
+// orthogonal to working precision, and one GEMM Q U per merge.  Leaves (at
+// most kDcLeaf rows) use cyclic Jacobi.
+//
+// The recursion tree depends only on n: node idx of level l (root level 0)
+// covers the range obtained by halving [0, n) l times along the bits of idx
+// (mid = (lo + hi) / 2), and all leaves sit at the same depth.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "tridiag_dc.hpp"
+
+#include "common.hpp"
+
+namespace lobpcg {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kDcLeaf = 32;
+constexpr int kDcMaxN = 512;
+constexpr int kDcThreads = 256;
+constexpr int kDcJacobiSweeps = 40;
+constexpr int kDcBisect = 256;
+
+__device__ __forceinline__ void dc_range(int n, int level, int idx, int& lo, int& hi) {
+  lo = 0;
+  hi = n;
+  for (int l = level - 1; l >= 0; --l) {
+    const int mid = (lo + hi) / 2;
+    if ((idx >> l) & 1)
+      lo = mid;
+    else
+      hi = mid;
+  }
+}
+
+__device__ __forceinline__ double dc_wave_sum(double v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// ---------------------------------------------------------------- tear
+// d[mid - 1] and d[mid] lose |e[mid - 1]| for every internal node (distinct
+// indices: children are at least kDcLeaf / 2 rows apart from their parent's mid).
+__global__ void dc_tear_kernel(int n, int depth, const double* __restrict__ e, double* d) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int level = 0, base = 0;
+  while (level < depth && t >= base + (1 << level)) {
+    base += 1 << level;
+    ++level;
+  }
+  if (level >= depth) return;
+  int lo, hi;
+  dc_range(n, level, t - base, lo, hi);
+  const int mid = (lo + hi) / 2;
+  const double b = fabs(e[mid - 1]);
+  d[mid - 1] -= b;
+  d[mid] -= b;
+}
+
+// ---------------------------------------------------------------- leaves
+// One wave per leaf: threshold cyclic Jacobi with the round-robin (circle)
+// ordering, up to 16 disjoint rotations per round.  An off-diagonal entry below
+// 1e-18 sqrt(|a_pp a_qq|) (or exactly zero) is set to zero instead of rotated;
+// the sweeps stop when one performs no rotation.  Writes lam[lo:hi) ascending
+// and the leaf block Z[lo:hi, lo:hi).
+__global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const double* __restrict__ d,
+                                                         const double* __restrict__ e,
+                                                         double* __restrict__ lam,
+                                                         double* __restrict__ Z, int64_t ldz) {
+  __shared__ double A[kDcLeaf][kDcLeaf + 1];
+  __shared__ double V[kDcLeaf][kDcLeaf + 1];
+  __shared__ double cs[kDcLeaf / 2][2];
+  __shared__ int pr[kDcLeaf / 2][2];
+  __shared__ double wv[kDcLeaf];
+  __shared__ int perm[kDcLeaf];
+  const int lane = threadIdx.x;
+  int lo, hi;
+  dc_range(n, depth, blockIdx.x, lo, hi);
+  const int m = hi - lo;
+  const int mp = m + (m & 1);  // players (a dummy when m is odd)
+  for (int q = lane; q < kDcLeaf * kDcLeaf; q += kWave) {
+    const int r = q % kDcLeaf, c = q / kDcLeaf;
+    double a = 0.0;
+    if (r < m && c < m) {
+      if (r == c)
+        a = d[lo + r];
+      else if (r == c + 1)
+        a = e[lo + c];
+      else if (c == r + 1)
+        a = e[lo + r];
+    }
+    A[r][c] = a;
+    V[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < kDcJacobiSweeps && m > 1; ++sweep) {
+    int rotated = 0;
+    for (int round = 0; round < mp - 1; ++round) {
+      if (lane < mp / 2) {
+        // circle slots s = 0..mp-2 hold players 1 + (s + round) mod (mp - 1):
+        // pairs (0, slot 0) and (slot k, slot mp - 1 - k)
+        int p, qd;
+        if (lane == 0) {
+          p = 0;
+          qd = 1 + round % (mp - 1);
+        } else {
+          p = 1 + (lane + round) % (mp - 1);
+          qd = 1 + (mp - 1 - lane + round) % (mp - 1);
+        }
+        if (p > qd) {
+          const int tmp = p;
+          p = qd;
+          qd = tmp;
+        }
+        double c = 1.0, s = 0.0;
+        bool rot = false;
+        if (qd < m) {
+          const double apq = A[p][qd];
+          if (fabs(apq) <= 1e-18 * sqrt(fabs(A[p][p] * A[qd][qd]))) {
+            A[p][qd] = 0.0;
+            A[qd][p] = 0.0;
+          } else {
+            const double th = (A[qd][qd] - A[p][p]) / (2.0 * apq);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+            c = 1.0 / sqrt(fma(t, t, 1.0));
+            s = t * c;
+            rot = true;
+          }
+        }
+        rotated |= rot ? 1 : 0;
+        pr[lane][0] = p;
+        pr[lane][1] = rot ? qd : p;
+        cs[lane][0] = c;
+        cs[lane][1] = s;
+      }
+      __syncthreads();
+      // rows: A <- G^T A
+      for (int q = lane; q < (mp / 2) * m; q += kWave) {
+        const int k = q / m, col = q % m;
+        const int p = pr[k][0], qq = pr[k][1];
+        if (p == qq) continue;
+        const double c = cs[k][0], s = cs[k][1];
+        const double ap = A[p][col], aq = A[qq][col];
+        A[p][col] = c * ap - s * aq;
+        A[qq][col] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns: A <- A G, V <- V G
+      for (int q = lane; q < (mp / 2) * m; q += kWave) {
+        const int k = q / m, row = q % m;
+        const int p = pr[k][0], qq = pr[k][1];
+        if (p == qq) continue;
+        const double c = cs[k][0], s = cs[k][1];
+        const double ap = A[row][p], aq = A[row][qq];
+        A[row][p] = c * ap - s * aq;
+        A[row][qq] = s * ap + c * aq;
+        const double vp = V[row][p], vq = V[row][qq];
+        V[row][p] = c * vp - s * vq;
+        V[row][qq] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    // the wave agrees on whether any rotation happened in the sweep
+    if (__ballot(rotated) == 0) break;
+  }
+  // ascending order (rank sort, ties by index)
+  if (lane < m) wv[lane] = A[lane][lane];
+  __syncthreads();
+  if (lane < m) {
+    int rank = 0;
+    for (int j = 0; j < m; ++j)
+      rank += (wv[j] < wv[lane] || (wv[j] == wv[lane] && j < lane)) ? 1 : 0;
+    perm[rank] = lane;
+  }
+  __syncthreads();
+  for (int q = lane; q < m * m; q += kWave) {
+    const int r = q % m, k = q / m;
+    Z[(int64_t)(lo + k) * ldz + lo + r] = V[r][perm[k]];
+  }
+  if (lane < m) lam[lo + lane] = wv[perm[lane]];
+}
+
+// Per-node bookkeeping in the int workspace (offsets from the base):
+//   [node]                 K (values entering the secular equation)
+//   [kNrot + node]         number of rotations
+//   [kOrd + lo + k]        position of sorted slot k ([kept ascending | deflated])
+//   [kSrc + lo + k]        child column of position k (< n1: left, else right)
+//   [kRp / kRi + lo + r]   rotation r acts on positions (p, i), in order
+//   [kPerm + lo + k]       slot of the k-th smallest eigenvalue of the node
+// and in the double workspace: rotation cosines / sines at [lo + r] and [kDcMaxN + lo + r].
+constexpr int kNrot = 64, kOrd = 128, kSrc = kOrd + kDcMaxN, kRp = kSrc + kDcMaxN,
+              kRi = kRp + kDcMaxN, kPerm = kRi + kDcMaxN, kDcInts = kPerm + kDcMaxN;
+static_assert(kDcInts <= 4096, "int workspace");
+
+// ---------------------------------------------------------------- merge: prepare
+// One workgroup per node: sorted d and z, deflation (sequential scan), the
+// order [kept ascending | deflated], the rotation list, rho of the kept set.
+__global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
+    int n, int level, const double* __restrict__ e, const double* __restrict__ lam,
+    const double* __restrict__ Z, int64_t ldz, double* __restrict__ dsort,
+    double* __restrict__ zsort, int* __restrict__ iw, double* __restrict__ rw,
+    double* __restrict__ rhoK) {
+  __shared__ double ds[kDcMaxN], zs[kDcMaxN];
+  __shared__ int src[kDcMaxN], defl[kDcMaxN];
+  __shared__ int K_s;
+  __shared__ double rho_s, znorm_s;
+  const int t = threadIdx.x;
+  const int node = blockIdx.x;
+  int lo, hi;
+  dc_range(n, level, node, lo, hi);
+  const int mid = (lo + hi) / 2;
+  const int m = hi - lo, n1 = mid - lo, n2 = hi - mid;
+  const double b = e[mid - 1];
+  const double rho = 2.0 * fabs(b);
+  const double sg = b < 0.0 ? -1.0 : 1.0;
+  const double rs2 = 0.70710678118654752440;
+  // merge the two ascending eigenvalue lists (ties: left half first)
+  for (int i = t; i < m; i += kDcThreads) {
+    double di, zi;
+    int rank;
+    if (i < n1) {
+      di = lam[lo + i];
+      zi = Z[(int64_t)(lo + i) * ldz + (mid - 1)] * rs2;
+      int a = 0, c = n2;  // number of right entries < di
+      while (a < c) {
+        const int h = (a + c) / 2;
+        if (lam[mid + h] < di) a = h + 1; else c = h;
+      }
+      rank = i + a;
+    } else {
+      const int i2 = i - n1;
+      di = lam[mid + i2];
+      zi = sg * Z[(int64_t)(mid + i2) * ldz + mid] * rs2;
+      int a = 0, c = n1;  // number of left entries <= di
+      while (a < c) {
+        const int h = (a + c) / 2;
+        if (lam[lo + h] <= di) a = h + 1; else c = h;
+      }
+      rank = i2 + a;
+    }
+    ds[rank] = di;
+    zs[rank] = zi;
+    src[rank] = i;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double dmax = 0.0, zmax = 0.0;
+    for (int i = 0; i < m; ++i) {
+      dmax = fmax(dmax, fabs(ds[i]));
+      zmax = fmax(zmax, fabs(zs[i]));
+    }
+    const double tol = 8.0 * 2.220446049250313e-16 * fmax(dmax, zmax);
+    int nrot = 0, prev = -1;
+    for (int i = 0; i < m; ++i) {
+      defl[i] = (rho * fabs(zs[i]) <= tol) ? 1 : 0;
+      if (defl[i]) continue;
+      if (prev >= 0) {
+        const double s = zs[prev], c = zs[i];
+        const double tau = hypot(c, s);
+        const double cc = c / tau, ss = -s / tau;
+        const double dt = ds[i] - ds[prev];
+        if (fabs(dt * cc * ss) <= tol) {
+          zs[i] = tau;
+          zs[prev] = 0.0;
+          const double dp = ds[prev], di = ds[i];
+          ds[prev] = dp * cc * cc + di * ss * ss;
+          ds[i] = dp * ss * ss + di * cc * cc;
+          defl[prev] = 1;
+          iw[kRp + lo + nrot] = prev;
+          iw[kRi + lo + nrot] = i;
+          rw[lo + nrot] = cc;
+          rw[kDcMaxN + lo + nrot] = ss;
+          ++nrot;
+        }
+      }
+      prev = i;
+    }
+    int K = 0;
+    double zn = 0.0;
+    for (int i = 0; i < m; ++i)
+      if (!defl[i]) {
+        ++K;
+        zn = fma(zs[i], zs[i], zn);
+      }
+    K_s = K;
+    znorm_s = sqrt(zn);
+    rho_s = rho * zn;
+    iw[node] = K;
+    iw[kNrot + node] = nrot;
+    rhoK[node] = rho * zn;
+  }
+  __syncthreads();
+  const int K = K_s;
+  for (int i = t; i < m; i += kDcThreads) {
+    int rank = 0;
+    if (!defl[i]) {
+      for (int j = 0; j < m; ++j)
+        if (!defl[j] && (ds[j] < ds[i] || (ds[j] == ds[i] && j < i))) ++rank;
+    } else {
+      rank = K;
+      for (int j = 0; j < i; ++j) rank += defl[j] ? 1 : 0;
+    }
+    iw[kOrd + lo + rank] = i;
+    dsort[lo + rank] = ds[i];
+    if (rank < K) zsort[lo + rank] = zs[i] / znorm_s;
+    iw[kSrc + lo + i] = src[i];
+  }
+}
+
+// ---------------------------------------------------------------- merge: stage
+// One workgroup per (node, position k): Qs[lo:hi, lo + k] = column src[k] of
+// diag(Q1, Q2) (the other child's rows zero).
+__global__ __launch_bounds__(kDcThreads) void dc_stage_kernel(int n, int level, int mmax,
+                                                              const int* __restrict__ iw,
+                                                              const double* __restrict__ Z,
+                                                              double* __restrict__ Qs,
+                                                              int64_t ldz) {
+  const int node = blockIdx.x / mmax, k = blockIdx.x % mmax;
+  int lo, hi;
+  dc_range(n, level, node, lo, hi);
+  const int m = hi - lo, n1 = (lo + hi) / 2 - lo;
+  if (k >= m) return;
+  // child column sidx sits at global column lo + sidx (the right child's
+  // columns follow the left child's)
+  const int sidx = iw[kSrc + lo + k];
+  const bool left = sidx < n1;
+  const double* zc = Z + (int64_t)(lo + sidx) * ldz;
+  double* qc = Qs + (int64_t)(lo + k) * ldz + lo;
+  for (int r = threadIdx.x; r < m; r += kDcThreads)
+    qc[r] = (left ? r < n1 : r >= n1) ? zc[lo + r] : 0.0;
+}
+
+// ---------------------------------------------------------------- merge: rotate
+// One thread per (node, row): the deflation rotations, in order, on the row.
+__global__ __launch_bounds__(kDcThreads) void dc_rotate_kernel(int n, int level, int rblocks,
+                                                               const int* __restrict__ iw,
+                                                               const double* __restrict__ rw,
+                                                               double* __restrict__ Qs,
+                                                               int64_t ldz) {
+  const int node = blockIdx.x / rblocks;
+  const int r = (blockIdx.x % rblocks) * kDcThreads + threadIdx.x;
+  int lo, hi;
+  dc_range(n, level, node, lo, hi);
+  if (r >= hi - lo) return;
+  const int nrot = iw[kNrot + node];
+  double* row = Qs + lo + r;
+  for (int k = 0; k < nrot; ++k) {
+    const int p = iw[kRp + lo + k], i = iw[kRi + lo + k];
+    const double cc = rw[lo + k], ss = rw[kDcMaxN + lo + k];
+    double* qp = row + (int64_t)(lo + p) * ldz;
+    double* qi = row + (int64_t)(lo + i) * ldz;
+    const double a = *qp, c = *qi;
+    *qp = cc * a + ss * c;
+    *qi = -ss * a + cc * c;
+  }
+}
+
+// ---------------------------------------------------------------- merge: secular roots
+// One wave per (node, root j < K), lanes sharing the sums over the kept set.
+// The root is located in the variable tau shifted to the nearer pole; a few
+// bisection steps, then Newton steps safeguarded by the bracketing interval.
+// lamk[lo + j] = root j;  Dl[lo + i, lo + j] = d_i - root_j.
+__global__ __launch_bounds__(kDcThreads) void dc_secular_kernel(
+    int n, int level, int rblocks, const double* __restrict__ dsort,
+    const double* __restrict__ zsort, const int* __restrict__ iw,
+    const double* __restrict__ rhoK, double* __restrict__ lamk, double* __restrict__ Dl,
+    int64_t ldz) {
+  const int node = blockIdx.x / rblocks;
+  const int lane = threadIdx.x % kWave;
+  const int j = (blockIdx.x % rblocks) * (kDcThreads / kWave) + threadIdx.x / kWave;
+  int lo, hi;
+  dc_range(n, level, node, lo, hi);
+  const int K = iw[node];
+  if (j >= K) return;
+  const double rho = rhoK[node];
+  const double* dd = dsort + lo;
+  const double* zz = zsort + lo;
+  int o;
+  double a, c;
+  if (j < K - 1) {
+    const double half = 0.5 * (dd[j + 1] - dd[j]);
+    double f = 0.0;
+    for (int i = lane; i < K; i += kWave) f += zz[i] * zz[i] / ((dd[i] - dd[j]) - half);
+    f = 1.0 + rho * dc_wave_sum(f);
+    if (f >= 0.0) {
+      o = j;
+      a = 0.0;
+      c = half;
+    } else {
+      o = j + 1;
+      a = -half;
+      c = 0.0;
+    }
+  } else {
+    o = K - 1;
+    a = 0.0;
+    c = rho;  // |z| = 1: the last root lies within rho of d_K
+  }
+  const double dor = dd[o];
+  double tau = 0.5 * (a + c);
+  for (int it = 0; it < kDcBisect; ++it) {
+    double f = 0.0, fp = 0.0;
+    for (int i = lane; i < K; i += kWave) {
+      const double q = zz[i] / ((dd[i] - dor) - tau);
+      f = fma(zz[i], q, f);
+      fp = fma(q, q, fp);
+    }
+    f = 1.0 + rho * dc_wave_sum(f);
+    fp = rho * dc_wave_sum(fp);
+    if (f > 0.0)
+      c = tau;
+    else if (f < 0.0)
+      a = tau;
+    else
+      break;
+    // Newton from tau when it stays inside the bracket, else bisection
+    double nt = tau - f / fp;
+    if (it < 4 || !(nt > a && nt < c)) nt = 0.5 * (a + c);
+    if (nt == tau || nt == a || nt == c) break;
+    if (fabs(nt - tau) <= 2.220446049250313e-16 * fabs(nt)) {
+      tau = nt;
+      break;
+    }
+    tau = nt;
+  }
+  if (lane == 0) lamk[lo + j] = dor + tau;
+  for (int i = lane; i < K; i += kWave) Dl[(int64_t)(lo + j) * ldz + lo + i] = (dd[i] - dor) - tau;
+}
+
+// ---------------------------------------------------------------- merge: zhat
+// One thread per (node, i < K): z recomputed from the roots (Gu-Eisenstat),
+// zhat_i^2 = (root_i - d_i) / rho  prod_{j != i} (root_j - d_i) / (d_j - d_i).
+__global__ __launch_bounds__(kDcThreads) void dc_zhat_kernel(int n, int level, int rblocks,
+                                                             const double* __restrict__ dsort,
+                                                             const double* __restrict__ zsort,
+                                                             const int* __restrict__ iw,
+                                                             const double* __restrict__ rhoK,
+                                                             const double* __restrict__ Dl,
+                                                             double* __restrict__ zh,
+                                                             int64_t ldz) {
+  const int node = blockIdx.x / rblocks;
+  const int i = (blockIdx.x % rblocks) * kDcThreads + threadIdx.x;
+  int lo, hi;
+  dc_range(n, level, node, lo, hi);
+  const int K = iw[node];
+  if (i >= K) return;
+  const double* dd = dsort + lo;
+  double prod = -Dl[(int64_t)(lo + i) * ldz + lo + i] / rhoK[node];
+  for (int j = 0; j < K; ++j)
+    if (j != i) prod *= -Dl[(int64_t)(lo + j) * ldz + lo + i] / (dd[j] - dd[i]);
+  zh[lo + i] = copysign(sqrt(fmax(prod, 0.0)), zsort[lo + i]);
+}
+
+// ---------------------------------------------------------------- merge: vectors
+// One workgroup (one wave) per (node, column j < m): U(:, j) = zhat / (d - root_j)
+// normalised (zero below row K), and the GEMM operand G(:, j) = kept column j of
+// Qs (zero for j >= K).
+__global__ __launch_bounds__(kWave) void dc_vectors_kernel(int n, int level, int mmax,
+                                                           const int* __restrict__ iw,
+                                                           const double* __restrict__ zh,
+                                                           const double* __restrict__ Qs,
+                                                           double* __restrict__ Dl,
+                                                           double* __restrict__ G, int64_t ldz) {
+  const int node = blockIdx.x / mmax, j = blockIdx.x % mmax;
+  const int lane = threadIdx.x;
+  int lo, hi;
+  dc_range(n, level, node, lo, hi);
+  const int m = hi - lo;
+  if (j >= m) return;
+  const int K = iw[node];
+  double* gc = G + (int64_t)(lo + j) * ldz + lo;
+  if (j < K) {
+    const double* qc = Qs + (int64_t)(lo + iw[kOrd + lo + j]) * ldz + lo;
+    for (int r = lane; r < m; r += kWave) gc[r] = qc[r];
+    double* u = Dl + (int64_t)(lo + j) * ldz + lo;
+    double s = 0.0;
+    for (int i = lane; i < K; i += kWave) {
+      const double v = zh[lo + i] / u[i];
+      u[i] = v;
+      s = fma(v, v, s);
+    }
+    const double inv = 1.0 / sqrt(dc_wave_sum(s));
+    for (int i = lane; i < m; i += kWave) u[i] = i < K ? u[i] * inv : 0.0;
+  } else {
+    for (int r = lane; r < m; r += kWave) gc[r] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- merge: order
+// One workgroup per node: ascending order of the node's eigenvalues (kept
+// roots, then deflated d), lam[lo:hi) and the slot of each.
+__global__ __launch_bounds__(kDcThreads) void dc_order_kernel(int n, int level,
+                                                              int* __restrict__ iw,
+                                                              const double* __restrict__ lamk,
+                                                              const double* __restrict__ dsort,
+                                                              double* __restrict__ lam) {
+  __shared__ double w[kDcMaxN];
+  const int t = threadIdx.x;
+  const int node = blockIdx.x;
+  int lo, hi;
+  dc_range(n, level, node, lo, hi);
+  const int m = hi - lo;
+  const int K = iw[node];
+  for (int i = t; i < m; i += kDcThreads) w[i] = i < K ? lamk[lo + i] : dsort[lo + i];
+  __syncthreads();
+  for (int i = t; i < m; i += kDcThreads) {
+    int rank = 0;
+    for (int j = 0; j < m; ++j) rank += (w[j] < w[i] || (w[j] == w[i] && j < i)) ? 1 : 0;
+    iw[kPerm + lo + rank] = i;
+    lam[lo + rank] = w[i];
+  }
+}
+
+// ---------------------------------------------------------------- merge: scatter
+// One workgroup per (node, output column k): Z[lo:hi, lo + k] from the GEMM
+// output (kept slots) or the staged deflated column.
+__global__ __launch_bounds__(kDcThreads) void dc_scatter_kernel(int n, int level, int mmax,
+                                                                const int* __restrict__ iw,
+                                                                const double* __restrict__ Y,
+                                                                const double* __restrict__ Qs,
+                                                                double* __restrict__ Z,
+                                                                int64_t ldz) {
+  const int node = blockIdx.x / mmax, k = blockIdx.x % mmax;
+  int lo, hi;
+  dc_range(n, level, node, lo, hi);
+  const int m = hi - lo;
+  if (k >= m) return;
+  const int K = iw[node];
+  const int slot = iw[kPerm + lo + k];
+  const double* sc = slot < K ? Y + (int64_t)(lo + slot) * ldz + lo
+                              : Qs + (int64_t)(lo + iw[kOrd + lo + slot]) * ldz + lo;
+  double* zc = Z + (int64_t)(lo + k) * ldz + lo;
+  for (int r = threadIdx.x; r < m; r += kDcThreads) zc[r] = sc[r];
+}
+
+inline void dc_check(rocblas_status st, const char* what) {
+  if (st != rocblas_status_success)
+    throw Error(LOBPCG_ERR_HIP, std::string(what) + ": " + rocblas_status_to_string(st));
+}
+
+inline unsigned dc_blocks(int64_t total, int per) { return (unsigned)((total + per - 1) / per); }
+
+}  // namespace
+
+int tridiag_dc_max_n() { return kDcMaxN; }
+int tridiag_dc_int_workspace() { return kDcInts; }
+
+void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64_t ldz,
+                double* Qs, double* Dl, double* G, double* Y, double* vec4, int* iw, double* rw,
+                double* rhoK, rocblas_handle h, hipStream_t s) {
+  LOBPCG_CHECK(n >= 1 && n <= kDcMaxN && ldz >= n, LOBPCG_ERR_ARG, "tridiag_dc: bad sizes");
+  int depth = 0;
+  while (((n + (1 << depth) - 1) >> depth) > kDcLeaf) ++depth;
+  double* dsort = vec4;
+  double* zsort = vec4 + n;
+  double* lamk = vec4 + 2 * n;
+  double* zh = vec4 + 3 * n;
+  if (depth > 0) {
+    const int internal = (1 << depth) - 1;
+    hipLaunchKernelGGL(dc_tear_kernel, dim3(dc_blocks(internal, 64)), dim3(64), 0, s, n, depth, e,
+                       d);
+  }
+  hipLaunchKernelGGL(dc_leaf_kernel, dim3(1u << depth), dim3(kWave), 0, s, n, depth, d, e, lam, Z,
+                     ldz);
+  LOBPCG_HIP(hipGetLastError());
+  for (int level = depth - 1; level >= 0; --level) {
+    const int nodes = 1 << level;
+    const int mmax = (n + nodes - 1) / nodes;
+    const int rb = (int)dc_blocks(mmax, kDcThreads);
+    const int sb = (int)dc_blocks(mmax, kDcThreads / kWave);
+    hipLaunchKernelGGL(dc_prepare_kernel, dim3(nodes), dim3(kDcThreads), 0, s, n, level, e, lam,
+                       Z, ldz, dsort, zsort, iw, rw, rhoK);
+    hipLaunchKernelGGL(dc_stage_kernel, dim3(nodes * mmax), dim3(kDcThreads), 0, s, n, level, mmax,
+                       iw, Z, Qs, ldz);
+    hipLaunchKernelGGL(dc_rotate_kernel, dim3(nodes * rb), dim3(kDcThreads), 0, s, n, level, rb, iw,
+                       rw, Qs, ldz);
+    hipLaunchKernelGGL(dc_secular_kernel, dim3(nodes * sb), dim3(kDcThreads), 0, s, n, level, sb,
+                       dsort, zsort, iw, rhoK, lamk, Dl, ldz);
+    hipLaunchKernelGGL(dc_zhat_kernel, dim3(nodes * rb), dim3(kDcThreads), 0, s, n, level, rb,
+                       dsort, zsort, iw, rhoK, Dl, zh, ldz);
+    hipLaunchKernelGGL(dc_vectors_kernel, dim3(nodes * mmax), dim3(kWave), 0, s, n, level, mmax,
+                       iw, zh, Qs, Dl, G, ldz);
+    LOBPCG_HIP(hipGetLastError());
+    // Y = G U over each node's full block: G is zero beyond the kept columns
+    // and U zero below the kept rows (the kept count is known on the device only)
+    for (int node = 0; node < nodes; ++node) {
+      int lo = 0, hi = n;
+      for (int l = level - 1; l >= 0; --l) {
+        const int mid = (lo + hi) / 2;
+        if ((node >> l) & 1) lo = mid; else hi = mid;
+      }
+      const int m = hi - lo;
+      const double one = 1.0, zero = 0.0;
+      dc_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, m, m, &one,
+                             G + (int64_t)lo * ldz + lo, (rocblas_int)ldz,
+                             Dl + (int64_t)lo * ldz + lo, (rocblas_int)ldz, &zero,
+                             Y + (int64_t)lo * ldz + lo, (rocblas_int)ldz),
+               "tridiag_dc gemm");
+    }
+    hipLaunchKernelGGL(dc_order_kernel, dim3(nodes), dim3(kDcThreads), 0, s, n, level, iw, lamk,
+                       dsort, lam);
+    hipLaunchKernelGGL(dc_scatter_kernel, dim3(nodes * mmax), dim3(kDcThreads), 0, s, n, level,
+                       mmax, iw, Y, Qs, Z, ldz);
+    LOBPCG_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace lobpcg

@@ -1,0 +1,24 @@
+// Divide and conquer for the symmetric tridiagonal eigenproblem (tridiag_dc.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+
+namespace lobpcg {
+
+int tridiag_dc_max_n();
+int tridiag_dc_int_workspace();
+
+// Eigen-decomposition T = Z diag(lam) Z^T of the n x n symmetric tridiagonal
+// (d, e), n <= tridiag_dc_max_n(): lam ascending (may alias d, which is
+// overwritten), Z column-major with leading dimension ldz.  Workspace (device):
+// Qs, Dl, G, Y: n x n each with leading dimension ldz; vec4: 4 n doubles;
+// iw: tridiag_dc_int_workspace() ints; rw: 2 tridiag_dc_max_n() doubles; rhoK: 64
+// doubles.  All on stream s; h runs the merge GEMMs.
+void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64_t ldz,
+                double* Qs, double* Dl, double* G, double* Y, double* vec4, int* iw, double* rw,
+                double* rhoK, rocblas_handle h, hipStream_t s);
+
+}  // namespace lobpcg
