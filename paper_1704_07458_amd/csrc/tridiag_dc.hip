@@ -33,8 +33,8 @@ constexpr int kWave = 64;
 constexpr int kDcLeaf = 32;
 constexpr int kDcMaxN = 512;
 constexpr int kDcThreads = 256;
-constexpr int kDcJacobiSweeps = 40;
-constexpr int kDcBisect = 256;
+constexpr int kDcJacobiSweeps = 12;
+constexpr int kDcBisect = 128;
 
 __device__ __forceinline__ void dc_range(int n, int level, int idx, int& lo, int& hi) {
   lo = 0;
@@ -75,8 +75,10 @@ __global__ void dc_tear_kernel(int n, int depth, const double* __restrict__ e, d
 // ---------------------------------------------------------------- leaves
 // One wave per leaf: threshold cyclic Jacobi with the round-robin (circle)
 // ordering, up to 16 disjoint rotations per round.  An off-diagonal entry below
-// 1e-18 sqrt(|a_pp a_qq|) (or exactly zero) is set to zero instead of rotated;
-// the sweeps stop when one performs no rotation.  Writes lam[lo:hi) ascending
+// eps sqrt(|a_pp a_qq|) or 4 eps ||A||_F (the rounding level of a rotation) is
+// set to zero instead of rotated (the relative criterion of Demmel and Veselic,
+// with an absolute floor); the sweeps stop when one performs no rotation, and
+// after kDcJacobiSweeps (cyclic Jacobi converges quadratically: 6-8 sweeps).  Writes lam[lo:hi) ascending
 // and the leaf block Z[lo:hi, lo:hi).
 __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const double* __restrict__ d,
                                                          const double* __restrict__ e,
@@ -108,6 +110,12 @@ __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const 
     V[r][c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
+  double fro2 = 0.0;
+  for (int q = lane; q < m * m; q += kWave) {
+    const double a = A[q % m][q / m];
+    fro2 = fma(a, a, fro2);
+  }
+  const double floor_abs = 4.0 * 2.220446049250313e-16 * sqrt(dc_wave_sum(fro2));
   for (int sweep = 0; sweep < kDcJacobiSweeps && m > 1; ++sweep) {
     int rotated = 0;
     for (int round = 0; round < mp - 1; ++round) {
@@ -131,7 +139,8 @@ __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const 
         bool rot = false;
         if (qd < m) {
           const double apq = A[p][qd];
-          if (fabs(apq) <= 1e-18 * sqrt(fabs(A[p][p] * A[qd][qd]))) {
+          if (fabs(apq) <= 2.220446049250313e-16 * sqrt(fabs(A[p][p] * A[qd][qd])) ||
+              fabs(apq) <= floor_abs) {
             A[p][qd] = 0.0;
             A[qd][p] = 0.0;
           } else {
@@ -372,8 +381,8 @@ __global__ __launch_bounds__(kDcThreads) void dc_rotate_kernel(int n, int level,
 
 // ---------------------------------------------------------------- merge: secular roots
 // One wave per (node, root j < K), lanes sharing the sums over the kept set.
-// The root is located in the variable tau shifted to the nearer pole; a few
-// bisection steps, then Newton steps safeguarded by the bracketing interval.
+// The root is located in the variable tau shifted to the nearer pole, by Newton
+// steps on -tau f(tau) safeguarded by the bracketing interval.
 // lamk[lo + j] = root j;  Dl[lo + i, lo + j] = d_i - root_j.
 __global__ __launch_bounds__(kDcThreads) void dc_secular_kernel(
     int n, int level, int rblocks, const double* __restrict__ dsort,
@@ -414,23 +423,28 @@ __global__ __launch_bounds__(kDcThreads) void dc_secular_kernel(
   const double dor = dd[o];
   double tau = 0.5 * (a + c);
   for (int it = 0; it < kDcBisect; ++it) {
-    double f = 0.0, fp = 0.0;
+    double f = 0.0, fp = 0.0, fa = 0.0;
     for (int i = lane; i < K; i += kWave) {
       const double q = zz[i] / ((dd[i] - dor) - tau);
       f = fma(zz[i], q, f);
       fp = fma(q, q, fp);
+      fa += fabs(zz[i] * q);
     }
     f = 1.0 + rho * dc_wave_sum(f);
     fp = rho * dc_wave_sum(fp);
+    fa = 1.0 + rho * dc_wave_sum(fa);
+    // |f| at the level of its own rounding error: tau is as good as it gets
+    if (fabs(f) <= 8.0 * 2.220446049250313e-16 * fa) break;
     if (f > 0.0)
       c = tau;
-    else if (f < 0.0)
-      a = tau;
     else
-      break;
-    // Newton from tau when it stays inside the bracket, else bisection
-    double nt = tau - f / fp;
-    if (it < 4 || !(nt > a && nt < c)) nt = 0.5 * (a + c);
+      a = tau;
+    // Newton on F(tau) = -tau f(tau), which has no pole at the origin (the
+    // pole the root is nearest to): tau <- tau^2 f' / (f + tau f'); bisection
+    // when the step leaves the bracket
+    const double den = f + tau * fp;
+    double nt = tau * tau * fp / den;
+    if (!(nt > a && nt < c)) nt = 0.5 * (a + c);
     if (nt == tau || nt == a || nt == c) break;
     if (fabs(nt - tau) <= 2.220446049250313e-16 * fabs(nt)) {
       tau = nt;
@@ -460,9 +474,23 @@ __global__ __launch_bounds__(kDcThreads) void dc_zhat_kernel(int n, int level, i
   const int K = iw[node];
   if (i >= K) return;
   const double* dd = dsort + lo;
-  double prod = -Dl[(int64_t)(lo + i) * ldz + lo + i] / rhoK[node];
-  for (int j = 0; j < K; ++j)
-    if (j != i) prod *= -Dl[(int64_t)(lo + j) * ldz + lo + i] / (dd[j] - dd[i]);
+  const double* dcol = Dl + (int64_t)lo * ldz + lo + i;  // Dl(i, j) = dcol[j ldz]
+  const double di = dd[i];
+  double prod = -dcol[(int64_t)i * ldz] / rhoK[node];
+  int j = 0;
+  for (; j + 8 <= K; j += 8) {  // batches of independent loads, then the products
+    double v[8], w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      v[u] = dcol[(int64_t)(j + u) * ldz];
+      w[u] = dd[j + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j + u != i) prod *= -v[u] / (w[u] - di);
+  }
+  for (; j < K; ++j)
+    if (j != i) prod *= -dcol[(int64_t)j * ldz] / (dd[j] - di);
   zh[lo + i] = copysign(sqrt(fmax(prod, 0.0)), zsort[lo + i]);
 }
 
