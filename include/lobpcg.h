@@ -187,10 +187,13 @@ const char* lobpcg_last_error(void);
  *   kind 4 Rayleigh-Ritz        work = 0 (dense FP64 on the projected pencil,
  *                               kinds 5-7 included)
  *   kind 5 tridiagonalisation   work = flops: (4/3) n_s^3 (one-workgroup Householder)
- *   kind 6 tridiagonal eigenproblem (library divide and conquer)   work = 0
+ *   kind 6 tridiagonal eigenproblem (divide and conquer)   work = 0
  *   kind 7 P-block QR and eigenvector back-transformation kernels  work = 0
- * (s_v = 8 for FP64, 4 for FP32 blocks.)  Kinds 5-7 are recorded only for
+ *   kind 8 Cholesky factor R of the scaled B-Gram matrix and R^-1 together
+ *          (one workgroup, Algorithm 7)   work = flops: (2/3) n_s^3
+ * (s_v = 8 for FP64, 4 for FP32 blocks.)  Kinds 5-8 are recorded only for
  * projected problems within the one-workgroup kernels' size range. */
+#define LOBPCG_KERNEL_KINDS 9
 typedef struct {
   int64_t launches;
   double seconds;
@@ -198,7 +201,7 @@ typedef struct {
 } lobpcg_kernel_stat;
 
 /* enable = 1: reset and start collecting; 0: stop.  out (may be NULL) receives
- * 8 entries indexed by kind, accumulated since the last reset. */
+ * LOBPCG_KERNEL_KINDS entries indexed by kind, accumulated since the last reset. */
 int lobpcg_kernel_stats(lobpcg_t h, int32_t enable, lobpcg_kernel_stat* out);
 
 /* 1 = time the phases in lobpcg_info.seconds_phase (adds a stream

@@ -76,7 +76,8 @@ int lobpcg_residual(int64_t n, int32_t nx, int32_t dtype, const void* AX, int64_
  *   theta: n_s Ritz values ascending; theta_p: n_p x n_p column-major (ld n_x)
  *   block Q^T Theta_perp Q;
  * host outputs: *n_p, *flipped (1 when Cholesky was rejected: no coefficients
- * are produced), *cond (cond_1 of the scaled Cholesky factor; 0 if unused).
+ * are produced), *cond (cond_1 of the scaled Cholesky factor; +inf when the
+ * factorisation breaks down at a pivot that is not positive; 0 if unused).
  * tau_skip: section 5.3 threshold.  Synchronises the stream. */
 int lobpcg_rr_step(int32_t n_s, int32_t n_x, int32_t n_c, int32_t use_ortho,
                    int32_t lq_literal, const double* GA, const double* GB, int64_t ldg,

@@ -95,7 +95,7 @@ class lobpcg_kernel_stat(C.Structure):
 
 
 KERNEL_KINDS = ["spmm", "gram", "update", "residual", "rayleigh_ritz", "tridiagonalise",
-                "tridiagonal_eig", "qr_backtransform"]
+                "tridiagonal_eig", "qr_backtransform", "cholesky_inverse"]
 
 PRECOND_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
                          C.c_int64, C.c_void_p, C.c_int64, C.c_void_p)
@@ -273,7 +273,7 @@ class Solver:
 
     def kernel_stats(self, enable: bool) -> dict:
         """Per-kernel-class HIP-event totals since the last reset; then (re)enable or stop."""
-        arr = (lobpcg_kernel_stat * 8)()
+        arr = (lobpcg_kernel_stat * len(KERNEL_KINDS))()
         check(load().lobpcg_kernel_stats(self._h, 1 if enable else 0, arr))
         return {name: {"launches": int(arr[i].launches), "seconds": float(arr[i].seconds),
                        "work": float(arr[i].work)} for i, name in enumerate(KERNEL_KINDS)}

@@ -133,7 +133,7 @@ int lobpcg_kernel_stats(lobpcg_t h, int32_t enable, lobpcg_kernel_stat* out) {
     lobpcg::KernelTimer& t = h->solver->timer();
     t.collect();
     if (out)
-      for (int i = 0; i < 8; ++i) out[i] = t.totals[i];
+      for (int i = 0; i < LOBPCG_KERNEL_KINDS; ++i) out[i] = t.totals[i];
     t.enable(enable != 0);
     return LOBPCG_OK;
   });

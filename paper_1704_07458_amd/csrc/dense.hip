@@ -10,6 +10,7 @@
 #include <string>
 
 #include "kernels.hpp"
+#include "cholinv.hpp"
 #include "tridiag_dc.hpp"
 
 namespace lobpcg {
@@ -142,20 +143,27 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
     // Algorithm 7 lines 7-8: D = diag(S^T B S)^-1/2, R^T R = D S^T B S D.
     launch_diag_scale(ns, GB, ldg, d, R, ld, true, s_);
     launch_diag_scale(ns, GA, ldg, d, H, ld, false, s_);
-    LOBPCG_ROCBLAS(rocsolver_dpotrf(h_, rocblas_fill_upper, ns, R, (rocblas_int)ld, dinfo));
-    launch_zero_lower(ns, R, ld, s_);
-    copy_cm(ns, ns, R, ld, T, ld, s_);
-    LOBPCG_ROCBLAS(
-        rocsolver_dtrtri(h_, rocblas_fill_upper, rocblas_diagonal_non_unit, ns, T, (rocblas_int)ld,
-                         dinfo + 1));
-    launch_zero_lower(ns, T, ld, s_);
+    if (ns <= cholinv_max_n()) {
+      // R and R^-1 from one sweep over [R^T R | I] in one workgroup.
+      const int tok = timer_ ? timer_->start(s_) : -1;
+      launch_cholinv_upper(ns, R, ld, T, ld, dinfo, s_);
+      if (timer_) timer_->stop(tok, 8, 2.0 / 3.0 * ns * (double)ns * ns, s_);
+    } else {
+      LOBPCG_ROCBLAS(rocsolver_dpotrf(h_, rocblas_fill_upper, ns, R, (rocblas_int)ld, dinfo));
+      launch_zero_lower(ns, R, ld, s_);
+      copy_cm(ns, ns, R, ld, T, ld, s_);
+      LOBPCG_ROCBLAS(rocsolver_dtrtri(h_, rocblas_fill_upper, rocblas_diagonal_non_unit, ns, T,
+                                      (rocblas_int)ld, dinfo + 1));
+      launch_zero_lower(ns, T, ld, s_);
+    }
     launch_cond1_upper(ns, R, T, ld, cond_.as<double>(), E_.as<double>(), s_);
     LOBPCG_HIP(hipMemcpyAsync(hinfo_, dinfo, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipMemcpyAsync(hcond_, cond_.get(), sizeof(double), hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipStreamSynchronize(s_));
-    out.cond = hcond_[0];
     out.potrf_info = hinfo_[0];
     out.trtri_info = hinfo_[1];
+    // a factorisation that broke down has no condition number (partial factors)
+    out.cond = (hinfo_[0] != 0 || hinfo_[1] != 0) ? HUGE_VAL : hcond_[0];
     // Line 9 (section 5.3 reading): reject when cond(R)^3 tau_skip > 1.
     const bool bad_factor = hinfo_[0] != 0 || hinfo_[1] != 0 || !std::isfinite(out.cond);
     const bool ill = tau_skip > 0.0 && out.cond * out.cond * out.cond * tau_skip > 1.0;

@@ -20,7 +20,7 @@ class KernelTimer {
   void stop(int token, int kind, double work, hipStream_t s);
   // Synchronise, fold finished records into the totals.
   void collect();
-  lobpcg_kernel_stat totals[8] = {};
+  lobpcg_kernel_stat totals[LOBPCG_KERNEL_KINDS] = {};
 
  private:
   hipEvent_t event(size_t i);

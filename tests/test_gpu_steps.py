@@ -271,6 +271,50 @@ def test_rr_step_flags_ill_conditioned(lib):
     assert got["flipped"] and got["cond"] > 1e5
 
 
+@pytest.mark.parametrize("n_s", [1, 2, 31, 32, 33, 65, 100, 330, 512])
+def test_rr_step_cholesky_and_inverse_sizes(lib, n_s):
+    """R and R^-1 of the scaled B-Gram matrix (Algorithm 7) across the one-workgroup
+    kernel's 32-row panels, ragged last panels and its largest size: the Ritz
+    values and cond_1(R) = |R|_1 |R^-1|_1 (which needs both factors) against the
+    oracle."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(1000 + n_s)
+    n, n_x = max(3 * n_s, 40), max(1, n_s // 3)
+    A = P.random_sparse_spd(9, n, min(1.0, 20.0 / n)).to_scipy()
+    S = rng.standard_normal((n, n_s)) * np.exp(rng.uniform(-2, 2, n_s))  # unequal column scales
+    GA, GB = S.T @ (A @ S), S.T @ S
+    GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+    tol = L.Tolerances()
+    ref = L.rayleigh_ritz_modified(GA, GB, n_x, 0, False, tol)
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), n_x, 0, False,
+                    tol.tau_skip)
+    assert not got["flipped"] and not ref.flipped
+    assert got["cond"] == pytest.approx(ref.cond_R, rel=1e-9)
+    th = got["theta"].cpu().numpy()
+    assert np.allclose(th, ref.theta_all, rtol=1e-10, atol=1e-12 * np.abs(th).max())
+
+
+def test_rr_step_cholesky_breakdown_in_a_late_panel(lib):
+    """A B-Gram matrix that is singular at column 40 (the second 32-row panel): the
+    factorisation must stop or report an unusable condition number, and the step
+    must ask for the orthonormalised basis (Algorithm 7's fallback)."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(41)
+    n, n_s = 500, 50
+    S = rng.standard_normal((n, n_s))
+    S[:, 40] = S[:, 3]
+    A = P.random_sparse_spd(4, n, 0.05).to_scipy()
+    GA, GB = S.T @ (A @ S), S.T @ S
+    GB[40, 40] -= 1.0  # a negative pivot in exact arithmetic
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), 10, 0, False,
+                    L.Tolerances().tau_skip)
+    assert got["flipped"]
+
+
 @pytest.mark.parametrize("n_s,use_ortho", [(330, False), (330, True), (600, False)])
 def test_rr_step_full_size_with_clustered_spectrum(lib, n_s, use_ortho):
     """The projected problem at the bench's size (n_s = 3 n_x = 330) and above.
