@@ -6,11 +6,11 @@
 // merge solves D + rho z z^T (D, Q from the halves, z = Q^T w / sqrt 2, rho = 2|b|)
 // with LAPACK-style deflation (tiny rho |z_i|, and close pairs rotated until one
 // z component vanishes), the secular equation 1 + rho sum z_i^2 / (d_i - lam) = 0
-// solved root by root by bisection in the variable shifted to the nearer pole
+// solved root by root in the variable shifted to the nearer pole
 // (so d_i - lam keeps full relative accuracy), z recomputed from the computed
 // roots (Gu and Eisenstat) so that the eigenvectors z_i / (d_i - lam_j) are
 // orthogonal to working precision, and one GEMM Q U per merge.  Leaves (at
-// most kDcLeaf rows) use cyclic Jacobi.
+// most kDcLeaf rows) use the implicit QL algorithm.
 //
 // The recursion tree depends only on n: node idx of level l (root level 0)
 // covers the range obtained by halving [0, n) l times along the bits of idx
@@ -33,7 +33,7 @@ constexpr int kWave = 64;
 constexpr int kDcLeaf = 32;
 constexpr int kDcMaxN = 512;
 constexpr int kDcThreads = 256;
-constexpr int kDcJacobiSweeps = 12;
+constexpr int kDcQlIter = 60;
 constexpr int kDcBisect = 128;
 
 __device__ __forceinline__ void dc_range(int n, int level, int idx, int& lo, int& hi) {
@@ -73,127 +73,103 @@ __global__ void dc_tear_kernel(int n, int depth, const double* __restrict__ e, d
 }
 
 // ---------------------------------------------------------------- leaves
-// One wave per leaf: threshold cyclic Jacobi with the round-robin (circle)
-// ordering, up to 16 disjoint rotations per round.  An off-diagonal entry below
-// eps sqrt(|a_pp a_qq|) or 4 eps ||A||_F (the rounding level of a rotation) is
-// set to zero instead of rotated (the relative criterion of Demmel and Veselic,
-// with an absolute floor); the sweeps stop when one performs no rotation, and
-// after kDcJacobiSweeps (cyclic Jacobi converges quadratically: 6-8 sweeps).  Writes lam[lo:hi) ascending
-// and the leaf block Z[lo:hi, lo:hi).
+// One wave per leaf: the implicit QL algorithm with Wilkinson's shift on the
+// leaf's tridiagonal block (the Bowdler-Martin-Reinsch-Wilkinson scheme).
+// Every lane runs the scalar recurrence on (d, e) in LDS with identical
+// values; lane k applies each plane rotation to row k of the eigenvector
+// block.  An off-diagonal e_i is negligible once |e_i| <= eps (|d_i| +
+// |d_{i+1}|); at most kDcQlIter sweeps per eigenvalue (convergence is cubic,
+// a few sweeps are the rule).  Writes lam[lo:hi) ascending and the leaf block
+// Z[lo:hi, lo:hi).
+// d and e stay in registers, lane k holding d_k and e_k: a uniform index is
+// read with readlane and written with a lane select, so the scalar recurrence
+// never waits on LDS.
+__device__ __forceinline__ double dc_lane_get(double v, int i) {
+  const int lo32 = __builtin_amdgcn_readlane(__double2loint(v), i);
+  const int hi32 = __builtin_amdgcn_readlane(__double2hiint(v), i);
+  return __hiloint2double(hi32, lo32);
+}
+
 __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const double* __restrict__ d,
                                                          const double* __restrict__ e,
                                                          double* __restrict__ lam,
                                                          double* __restrict__ Z, int64_t ldz) {
-  __shared__ double A[kDcLeaf][kDcLeaf + 1];
-  __shared__ double V[kDcLeaf][kDcLeaf + 1];
-  __shared__ double cs[kDcLeaf / 2][2];
-  __shared__ int pr[kDcLeaf / 2][2];
-  __shared__ double wv[kDcLeaf];
+  __shared__ double V[kDcLeaf][kDcLeaf + 1];  // V[row][col]
+  __shared__ double dl[kDcLeaf];
   __shared__ int perm[kDcLeaf];
   const int lane = threadIdx.x;
+  constexpr double eps = 2.220446049250313e-16;
   int lo, hi;
   dc_range(n, depth, blockIdx.x, lo, hi);
   const int m = hi - lo;
-  const int mp = m + (m & 1);  // players (a dummy when m is odd)
-  for (int q = lane; q < kDcLeaf * kDcLeaf; q += kWave) {
-    const int r = q % kDcLeaf, c = q / kDcLeaf;
-    double a = 0.0;
-    if (r < m && c < m) {
-      if (r == c)
-        a = d[lo + r];
-      else if (r == c + 1)
-        a = e[lo + c];
-      else if (c == r + 1)
-        a = e[lo + r];
-    }
-    A[r][c] = a;
-    V[r][c] = (r == c) ? 1.0 : 0.0;
-  }
+  for (int q = lane; q < kDcLeaf * kDcLeaf; q += kWave) V[q / kDcLeaf][q % kDcLeaf] = (q / kDcLeaf == q % kDcLeaf) ? 1.0 : 0.0;
+  double dv = lane < m ? d[lo + lane] : 0.0;
+  double ev = lane < m - 1 ? e[lo + lane] : 0.0;
+  // scale by a power of two (exact) so that every entry is below 1 in magnitude
+  double amax = fmax(fabs(dv), fabs(ev));
+  for (int off = kWave / 2; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, kWave));
+  int ex = 0;
+  if (amax > 0.0 && amax < INFINITY) frexp(amax, &ex);
+  dv = ldexp(dv, -ex);
+  ev = ldexp(ev, -ex);
   __syncthreads();
-  double fro2 = 0.0;
-  for (int q = lane; q < m * m; q += kWave) {
-    const double a = A[q % m][q / m];
-    fro2 = fma(a, a, fro2);
-  }
-  const double floor_abs = 4.0 * 2.220446049250313e-16 * sqrt(dc_wave_sum(fro2));
-  for (int sweep = 0; sweep < kDcJacobiSweeps && m > 1; ++sweep) {
-    int rotated = 0;
-    for (int round = 0; round < mp - 1; ++round) {
-      if (lane < mp / 2) {
-        // circle slots s = 0..mp-2 hold players 1 + (s + round) mod (mp - 1):
-        // pairs (0, slot 0) and (slot k, slot mp - 1 - k)
-        int p, qd;
-        if (lane == 0) {
-          p = 0;
-          qd = 1 + round % (mp - 1);
-        } else {
-          p = 1 + (lane + round) % (mp - 1);
-          qd = 1 + (mp - 1 - lane + round) % (mp - 1);
+  for (int l = 0; l < m; ++l) {
+    for (int it = 0; it < kDcQlIter; ++it) {
+      // first negligible e_mm at or after l (a wave-wide test)
+      const bool neg = !(lane >= l && lane < m - 1) ||
+                       fabs(ev) <= eps * (fabs(dv) + fabs(__shfl_down(dv, 1, kWave)));
+      const unsigned long long mask = __ballot(neg && lane >= l) | (1ull << (m - 1));
+      const int mm = __builtin_ctzll(mask >> l) + l;
+      if (mm == l) break;
+      // Wilkinson shift from the leading 2 x 2 block, as an offset g
+      const double dl0 = dc_lane_get(dv, l), el0 = dc_lane_get(ev, l);
+      double g = (dc_lane_get(dv, l + 1) - dl0) / (2.0 * el0);
+      double r = hypot(g, 1.0);
+      g = dc_lane_get(dv, mm) - dl0 + el0 / (g + copysign(r, g));
+      double sn = 1.0, cs = 1.0, p = 0.0;
+      bool split = false;
+      double di1 = dc_lane_get(dv, mm);  // d_{i+1} for i = mm - 1
+      for (int i = mm - 1; i >= l; --i) {
+        const double ei = dc_lane_get(ev, i), di = dc_lane_get(dv, i);
+        const double f = sn * ei, b = cs * ei;
+        r = hypot(f, g);
+        if (lane == i + 1) ev = r;
+        if (r == 0.0) {  // the rotation underflowed: the block splits at i + 1
+          if (lane == i + 1) dv = di1 - p;
+          if (lane == mm) ev = 0.0;
+          split = true;
+          break;
         }
-        if (p > qd) {
-          const int tmp = p;
-          p = qd;
-          qd = tmp;
+        const double rinv = 1.0 / r;
+        sn = f * rinv;
+        cs = g * rinv;
+        g = di1 - p;
+        r = (di - g) * sn + 2.0 * cs * b;
+        p = sn * r;
+        if (lane == i + 1) dv = g + p;
+        g = cs * r - b;
+        di1 = di;
+        if (lane < m) {
+          const double zi = V[lane][i], zi1 = V[lane][i + 1];
+          V[lane][i + 1] = sn * zi + cs * zi1;
+          V[lane][i] = cs * zi - sn * zi1;
         }
-        double c = 1.0, s = 0.0;
-        bool rot = false;
-        if (qd < m) {
-          const double apq = A[p][qd];
-          if (fabs(apq) <= 2.220446049250313e-16 * sqrt(fabs(A[p][p] * A[qd][qd])) ||
-              fabs(apq) <= floor_abs) {
-            A[p][qd] = 0.0;
-            A[qd][p] = 0.0;
-          } else {
-            const double th = (A[qd][qd] - A[p][p]) / (2.0 * apq);
-            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
-            c = 1.0 / sqrt(fma(t, t, 1.0));
-            s = t * c;
-            rot = true;
-          }
-        }
-        rotated |= rot ? 1 : 0;
-        pr[lane][0] = p;
-        pr[lane][1] = rot ? qd : p;
-        cs[lane][0] = c;
-        cs[lane][1] = s;
       }
-      __syncthreads();
-      // rows: A <- G^T A
-      for (int q = lane; q < (mp / 2) * m; q += kWave) {
-        const int k = q / m, col = q % m;
-        const int p = pr[k][0], qq = pr[k][1];
-        if (p == qq) continue;
-        const double c = cs[k][0], s = cs[k][1];
-        const double ap = A[p][col], aq = A[qq][col];
-        A[p][col] = c * ap - s * aq;
-        A[qq][col] = s * ap + c * aq;
+      if (split) continue;
+      if (lane == l) {
+        dv -= p;
+        ev = g;
       }
-      __syncthreads();
-      // columns: A <- A G, V <- V G
-      for (int q = lane; q < (mp / 2) * m; q += kWave) {
-        const int k = q / m, row = q % m;
-        const int p = pr[k][0], qq = pr[k][1];
-        if (p == qq) continue;
-        const double c = cs[k][0], s = cs[k][1];
-        const double ap = A[row][p], aq = A[row][qq];
-        A[row][p] = c * ap - s * aq;
-        A[row][qq] = s * ap + c * aq;
-        const double vp = V[row][p], vq = V[row][qq];
-        V[row][p] = c * vp - s * vq;
-        V[row][qq] = s * vp + c * vq;
-      }
-      __syncthreads();
+      if (lane == mm) ev = 0.0;
     }
-    // the wave agrees on whether any rotation happened in the sweep
-    if (__ballot(rotated) == 0) break;
   }
+  if (lane < m) dl[lane] = ldexp(dv, ex);
+  __syncthreads();
   // ascending order (rank sort, ties by index)
-  if (lane < m) wv[lane] = A[lane][lane];
-  __syncthreads();
   if (lane < m) {
+    const double w = dl[lane];
     int rank = 0;
-    for (int j = 0; j < m; ++j)
-      rank += (wv[j] < wv[lane] || (wv[j] == wv[lane] && j < lane)) ? 1 : 0;
+    for (int j = 0; j < m; ++j) rank += (dl[j] < w || (dl[j] == w && j < lane)) ? 1 : 0;
     perm[rank] = lane;
   }
   __syncthreads();
@@ -201,7 +177,7 @@ __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const 
     const int r = q % m, k = q / m;
     Z[(int64_t)(lo + k) * ldz + lo + r] = V[r][perm[k]];
   }
-  if (lane < m) lam[lo + lane] = wv[perm[lane]];
+  if (lane < m) lam[lo + lane] = dl[perm[lane]];
 }
 
 // Per-node bookkeeping in the int workspace (offsets from the base):
@@ -224,10 +200,11 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
     const double* __restrict__ Z, int64_t ldz, double* __restrict__ dsort,
     double* __restrict__ zsort, int* __restrict__ iw, double* __restrict__ rw,
     double* __restrict__ rhoK) {
-  __shared__ double ds[kDcMaxN], zs[kDcMaxN];
+  __shared__ double ds[kDcMaxN], zs[kDcMaxN], lm[kDcMaxN];
   __shared__ int src[kDcMaxN], defl[kDcMaxN];
   __shared__ int K_s;
   __shared__ double rho_s, znorm_s;
+  __shared__ double wmax[2][kDcThreads / kWave];
   const int t = threadIdx.x;
   const int node = blockIdx.x;
   int lo, hi;
@@ -238,27 +215,29 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
   const double rho = 2.0 * fabs(b);
   const double sg = b < 0.0 ? -1.0 : 1.0;
   const double rs2 = 0.70710678118654752440;
+  for (int i = t; i < m; i += kDcThreads) lm[i] = lam[lo + i];
+  __syncthreads();
   // merge the two ascending eigenvalue lists (ties: left half first)
   for (int i = t; i < m; i += kDcThreads) {
     double di, zi;
     int rank;
     if (i < n1) {
-      di = lam[lo + i];
+      di = lm[i];
       zi = Z[(int64_t)(lo + i) * ldz + (mid - 1)] * rs2;
       int a = 0, c = n2;  // number of right entries < di
       while (a < c) {
         const int h = (a + c) / 2;
-        if (lam[mid + h] < di) a = h + 1; else c = h;
+        if (lm[n1 + h] < di) a = h + 1; else c = h;
       }
       rank = i + a;
     } else {
       const int i2 = i - n1;
-      di = lam[mid + i2];
+      di = lm[n1 + i2];
       zi = sg * Z[(int64_t)(mid + i2) * ldz + mid] * rs2;
       int a = 0, c = n1;  // number of left entries <= di
       while (a < c) {
         const int h = (a + c) / 2;
-        if (lam[lo + h] <= di) a = h + 1; else c = h;
+        if (lm[h] <= di) a = h + 1; else c = h;
       }
       rank = i2 + a;
     }
@@ -267,11 +246,27 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
     src[rank] = i;
   }
   __syncthreads();
-  if (t == 0) {
+  {
     double dmax = 0.0, zmax = 0.0;
-    for (int i = 0; i < m; ++i) {
+    for (int i = t; i < m; i += kDcThreads) {
       dmax = fmax(dmax, fabs(ds[i]));
       zmax = fmax(zmax, fabs(zs[i]));
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      dmax = fmax(dmax, __shfl_xor(dmax, off, kWave));
+      zmax = fmax(zmax, __shfl_xor(zmax, off, kWave));
+    }
+    if (t % kWave == 0) {
+      wmax[0][t / kWave] = dmax;
+      wmax[1][t / kWave] = zmax;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    double dmax = 0.0, zmax = 0.0;
+    for (int w = 0; w < kDcThreads / kWave; ++w) {
+      dmax = fmax(dmax, wmax[0][w]);
+      zmax = fmax(zmax, wmax[1][w]);
     }
     const double tol = 8.0 * 2.220446049250313e-16 * fmax(dmax, zmax);
     int nrot = 0, prev = -1;
@@ -280,10 +275,12 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
       if (defl[i]) continue;
       if (prev >= 0) {
         const double s = zs[prev], c = zs[i];
-        const double tau = hypot(c, s);
-        const double cc = c / tau, ss = -s / tau;
         const double dt = ds[i] - ds[prev];
-        if (fabs(dt * cc * ss) <= tol) {
+        // |dt c s| / (c^2 + s^2) <= tol, tested without the square root and
+        // divisions (a close pair is rare); the rotation is formed only then
+        if (fabs(dt * c * s) <= tol * fma(c, c, s * s)) {
+          const double tau = hypot(c, s);
+          const double cc = c / tau, ss = -s / tau;
           zs[i] = tau;
           zs[prev] = 0.0;
           const double dp = ds[prev], di = ds[i];
