@@ -9,6 +9,7 @@
 //  residual  R = AX - BX Theta fused with the Jacobi preconditioner, the
 //            reversed W store and FP64 column norms for criterion (9).
 //  small     FP64 helpers for the projected (n_s x n_s) problem.
+#include "wave.hpp"
 #include "kernels.hpp"
 
 #include <hip/hip_runtime.h>
@@ -906,10 +907,7 @@ constexpr int kTrdMaxN = 512;
 constexpr int kTrdNb = 16;
 static_assert(kTrdMaxN <= kTrdThreads, "one row per thread in the column steps");
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave64_sum(v); }
 
 // Workgroup sum with one barrier: wave sums into red[wave], then every thread
 // adds the partials in the same fixed order.  Callers alternate between two
@@ -1187,8 +1185,7 @@ __global__ __launch_bounds__(kOrmThreads) void ormtr_lower_kernel(int n, const d
       double sdot = 0.0;
 #pragma unroll
       for (int q = 0; q < kOrmRows; ++q) sdot = fma(v[32 * q], z[q], sdot);
-#pragma unroll
-      for (int off = 16; off > 0; off >>= 1) sdot += __shfl_xor(sdot, off, 32);
+      sdot = half32_sum(sdot);
       const double f = tb[b] * sdot;
 #pragma unroll
       for (int q = 0; q < kOrmRows; ++q) z[q] = fma(-f, v[32 * q], z[q]);
@@ -1221,11 +1218,16 @@ constexpr int kQrMaxM = kQrGroups * kQrRows;
 __global__ __launch_bounds__(kQrThreads) void geqrf_orgqr_kernel(int m, int k,
                                                                  double* __restrict__ M,
                                                                  int64_t ldm) {
-  __shared__ double vbuf[2][kQrMaxM];
-  __shared__ double wpart[kQrGroups][kQrCols];
+  constexpr int kWaves = kQrThreads / kWave;
+  __shared__ double colb[2][kQrMaxM];           // column j of the step, double-buffered
+  __shared__ double vw[kWaves][kQrRows];        // per wave: the reflector on its rows
+  __shared__ double fw[kWaves][kQrRows];        // per wave: column j's final entries
+  __shared__ double vbuf[3][kQrMaxM];           // reflectors while Q is formed
+  __shared__ double wpart[2][kQrGroups][kQrCols];
   __shared__ double taus[kQrCols];
   const int t = threadIdx.x;
-  const int c = t % kQrCols, g = t / kQrCols;
+  const int lane = t % kWave, wave = t / kWave;
+  const int c = t % kQrCols, g = t / kQrCols;  // a wave lies in one row group
   const int r0 = g * kQrRows;
   double a[kQrRows];
 #pragma unroll
@@ -1233,59 +1235,67 @@ __global__ __launch_bounds__(kQrThreads) void geqrf_orgqr_kernel(int m, int k,
     const int r = r0 + q;
     a[q] = (c < k && r < m) ? M[(int64_t)c * ldm + r] : 0.0;
   }
-  for (int r = t; r < kQrMaxM; r += kQrThreads) vbuf[0][r] = vbuf[1][r] = 0.0;
-  __syncthreads();  // the first step stages column 0 into vbuf[1]
-  // ---- factorisation
+  for (int r = t; r < kQrMaxM; r += kQrThreads) colb[0][r] = colb[1][r] = 0.0;
+  __syncthreads();
+  if (c == 0) {
+#pragma unroll
+    for (int q = 0; q < kQrRows; ++q) colb[0][r0 + q] = a[q];
+  }
+  __syncthreads();
+  // ---- factorisation, two barriers per column: every wave forms the
+  // reflector of column j from the staged column (identical values in all
+  // waves) and writes it for its own rows to its LDS slice, where lane q
+  // handles row r0 + q (so the masks are per lane); the slice is read back by
+  // the same wave only, after a wave-level fence.
   for (int j = 0; j < k; ++j) {
-    // column j to LDS; wave 0 forms the reflector and the stored column
-    // (R above the diagonal, beta on it, v below) there, so the register
-    // loops below need no tests against the diagonal
-    double* col = vbuf[1];
+    const double* col = colb[j & 1];
+    double sq = 0.0;
+    for (int r = j + 1 + lane; r < m; r += kWave) sq = fma(col[r], col[r], sq);
+    sq = wave_sum(sq);
+    const double alpha = col[j];
+    double tj = 0.0, beta = alpha, scal = 0.0;
+    if (sq > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + sq), alpha);
+      tj = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (t == 0) taus[j] = tj;
+    if (lane < kQrRows) {
+      const int r = r0 + lane;
+      const double x = col[r];
+      const double v = r > j ? x * scal : (r == j ? 1.0 : 0.0);
+      vw[wave][lane] = v;
+      fw[wave][lane] = r > j ? v : (r == j ? beta : x);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double* vq = vw[wave];
     if (c == j) {
 #pragma unroll
-      for (int q = 0; q < kQrRows; ++q) col[r0 + q] = a[q];
-    }
-    __syncthreads();
-    if (t < kWave) {
-      double sq = 0.0;
-      for (int r = j + 1 + t; r < m; r += kWave) sq = fma(col[r], col[r], sq);
-      sq = wave_sum(sq);
-      const double alpha = col[j];
-      double tj = 0.0, beta = alpha, scal = 0.0;
-      if (sq > 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + sq), alpha);
-        tj = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      for (int r = t; r < kQrMaxM; r += kWave) {
-        const double x = col[r];
-        const double v = r > j ? x * scal : (r == j ? 1.0 : 0.0);
-        vbuf[0][r] = v;
-        col[r] = r > j ? v : (r == j ? beta : x);
-      }
-      if (t == 0) taus[j] = tj;
-    }
-    __syncthreads();
-    if (c == j) {
-#pragma unroll
-      for (int q = 0; q < kQrRows; ++q) a[q] = col[r0 + q];
+      for (int q = 0; q < kQrRows; ++q) a[q] = fw[wave][q];
     }
     const bool act = c > j && c < k;
     if (act) {
       double sdot = 0.0;
 #pragma unroll
-      for (int q = 0; q < kQrRows; ++q) sdot = fma(vbuf[0][r0 + q], a[q], sdot);
-      wpart[g][c] = sdot;
+      for (int q = 0; q < kQrRows; ++q) sdot = fma(vq[q], a[q], sdot);
+      wpart[j & 1][g][c] = sdot;
     }
     __syncthreads();
     if (act) {
       double w = 0.0;
 #pragma unroll
-      for (int q = 0; q < kQrGroups; ++q) w += wpart[q][c];
-      const double f = taus[j] * w;
+      for (int q = 0; q < kQrGroups; ++q) w += wpart[j & 1][q][c];
+      const double f = tj * w;
 #pragma unroll
-      for (int q = 0; q < kQrRows; ++q) a[q] = fma(-f, vbuf[0][r0 + q], a[q]);
+      for (int q = 0; q < kQrRows; ++q) a[q] = fma(-f, vq[q], a[q]);
+      if (c == j + 1) {
+#pragma unroll
+        for (int q = 0; q < kQrRows; ++q) colb[(j + 1) & 1][r0 + q] = a[q];
+      }
     }
+    __syncthreads();
   }
   // reflectors (below the diagonal) back to M; Q is built from them below
 #pragma unroll
@@ -1294,32 +1304,36 @@ __global__ __launch_bounds__(kQrThreads) void geqrf_orgqr_kernel(int m, int k,
     if (c < k && r < m) M[(int64_t)c * ldm + r] = a[q];
   }
   __syncthreads();
-  // ---- Q = H(0) ... H(k-1) I(:, 0:k), last reflector first
+  // ---- Q = H(0) ... H(k-1) I(:, 0:k), last reflector first, one barrier per
+  // reflector: reflector j - 1 is staged (third buffer) while j is applied,
+  // the partial sums alternate between two buffers
   auto vval = [&](int j, int r) -> double {
     if (j < 0 || r < j || r >= m) return 0.0;
     return r == j ? 1.0 : M[(int64_t)j * ldm + r];
   };
-  double pre = t < kQrMaxM ? vval(k - 1, t) : 0.0;
+  if (t < kQrMaxM) vbuf[(k - 1) % 3][t] = vval(k - 1, t);
+  double pre = t < kQrMaxM ? vval(k - 2, t) : 0.0;
 #pragma unroll
   for (int q = 0; q < kQrRows; ++q) a[q] = (c < k && r0 + q == c) ? 1.0 : 0.0;
+  __syncthreads();
   for (int j = k - 1; j >= 0; --j) {
-    double* vb = vbuf[j & 1];
-    if (t < kQrMaxM) vb[t] = pre;
-    __syncthreads();
-    if (t < kQrMaxM) pre = vval(j - 1, t);
-    const double tj = taus[j];
+    const double* vb = vbuf[j % 3];
     if (c < k) {
       double sdot = 0.0;
 #pragma unroll
       for (int q = 0; q < kQrRows; ++q) sdot = fma(vb[r0 + q], a[q], sdot);
-      wpart[g][c] = sdot;
+      wpart[j & 1][g][c] = sdot;
+    }
+    if (j >= 1 && t < kQrMaxM) {
+      vbuf[(j - 1) % 3][t] = pre;
+      pre = vval(j - 2, t);
     }
     __syncthreads();
     if (c < k) {
       double w = 0.0;
 #pragma unroll
-      for (int q = 0; q < kQrGroups; ++q) w += wpart[q][c];
-      const double f = tj * w;
+      for (int q = 0; q < kQrGroups; ++q) w += wpart[j & 1][q][c];
+      const double f = taus[j] * w;
 #pragma unroll
       for (int q = 0; q < kQrRows; ++q) a[q] = fma(-f, vb[r0 + q], a[q]);
     }

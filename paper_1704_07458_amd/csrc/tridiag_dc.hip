@@ -23,6 +23,7 @@
 #include <string>
 
 #include "tridiag_dc.hpp"
+#include "wave.hpp"
 
 #include "common.hpp"
 
@@ -48,10 +49,7 @@ __device__ __forceinline__ void dc_range(int n, int level, int idx, int& lo, int
   }
 }
 
-__device__ __forceinline__ double dc_wave_sum(double v) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
+__device__ __forceinline__ double dc_wave_sum(double v) { return wave64_sum(v); }
 
 // ---------------------------------------------------------------- tear
 // d[mid - 1] and d[mid] lose |e[mid - 1]| for every internal node (distinct
