@@ -194,15 +194,16 @@ def main():
         }
 
     # Roofline of the dominant HIP kernel class (by time inside the timed region).
-    # The tridiagonalisation of the projected matrix is one workgroup of FP64
-    # vector arithmetic: "alu" against the chip's FP64 vector peak (256 CU x 4
-    # SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s); one CU's share is
-    # reported beside it.
+    # The tridiagonalisation and the Cholesky factor + inverse of the projected
+    # matrices are one workgroup each of FP64 vector arithmetic: "alu" against
+    # the chip's FP64 vector peak (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+    # = 78.6 TFLOP/s); one CU's share is reported beside it.
     classes = {"spmm": ("hbm", "GB/s", HBM_PEAK_GBS, 1e-9),
                "gram": ("mfma", "TFLOP/s", PEAK_TFLOPS["f64"], 1e-12),
                "update": ("mfma", "TFLOP/s", PEAK_TFLOPS["f64"], 1e-12),
                "residual": ("hbm", "GB/s", HBM_PEAK_GBS, 1e-9),
-               "tridiagonalise": ("alu", "TFLOP/s", PEAK_TFLOPS["f64"], 1e-12)}
+               "tridiagonalise": ("alu", "TFLOP/s", PEAK_TFLOPS["f64"], 1e-12),
+               "cholesky_inverse": ("alu", "TFLOP/s", PEAK_TFLOPS["f64"], 1e-12)}
     per_kernel = {}
     for name, (bound, unit, peak, scale) in classes.items():
         st = st64[name]
@@ -212,7 +213,7 @@ def main():
                                 "frac": ach / peak, "seconds": st["seconds"],
                                 "launches": st["launches"],
                                 "avg_launch_us": 1e6 * st["seconds"] / st["launches"]}
-            if name == "tridiagonalise":
+            if bound == "alu":  # one-workgroup kernels: one CU's share of the peak
                 per_kernel[name]["frac_of_one_cu"] = ach / (peak / 256)
     dom = max(per_kernel, key=lambda k: per_kernel[k]["seconds"])
     roof = dict(per_kernel[dom])
