@@ -35,6 +35,14 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s)
   // Reproducible results: no split-K GEMM kernels that accumulate with
   // atomics (run-to-run rounding differences would change the iteration).
   LOBPCG_ROCBLAS(rocblas_set_atomics_mode(h_, rocblas_atomics_not_allowed));
+  // The second stream keeps the default priority; it never blocks on the
+  // main stream implicitly (events order the two).
+  LOBPCG_HIP(hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking));
+  LOBPCG_ROCBLAS(rocblas_create_handle(&h2_));
+  LOBPCG_ROCBLAS(rocblas_set_stream(h2_, s2_));
+  LOBPCG_ROCBLAS(rocblas_set_atomics_mode(h2_, rocblas_atomics_not_allowed));
+  for (hipEvent_t* e : {&ev_z_, &ev_p_})
+    LOBPCG_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   const size_t sq = sizeof(double) * (size_t)nsmax_ * nsmax_;
   H_.alloc(sq);
   R_.alloc(sq);
@@ -61,17 +69,28 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s)
 }
 
 Dense::~Dense() {
+  if (s2_) (void)hipStreamSynchronize(s2_);
+  for (hipEvent_t e : {ev_z_, ev_p_})
+    if (e) (void)hipEventDestroy(e);
+  if (h2_) rocblas_destroy_handle(h2_);
+  if (s2_) (void)hipStreamDestroy(s2_);
   if (h_) rocblas_destroy_handle(h_);
   if (hinfo_) (void)hipHostFree(hinfo_);
   if (hcond_) (void)hipHostFree(hcond_);
 }
 
+static void dgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n,
+                  int k, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double beta, double* C, int64_t ldc) {
+  if (m == 0 || n == 0) return;
+  LOBPCG_ROCBLAS(rocblas_dgemm(h, ta, tb, m, n, k, &alpha, A, (rocblas_int)lda, B,
+                               (rocblas_int)ldb, &beta, C, (rocblas_int)ldc));
+}
+
 void Dense::gemm(rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double alpha,
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                  double* C, int64_t ldc) {
-  if (m == 0 || n == 0) return;
-  LOBPCG_ROCBLAS(rocblas_dgemm(h_, ta, tb, m, n, k, &alpha, A, (rocblas_int)lda, B,
-                               (rocblas_int)ldb, &beta, C, (rocblas_int)ldc));
+  dgemm(h_, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 static void copy_cm(int m, int n, const double* src, int64_t lds, double* dst, int64_t ldd,
@@ -128,10 +147,73 @@ static void copy_cm(int m, int n, const double* src, int64_t lds, double* dst, i
                               sizeof(double) * m, n, hipMemcpyDeviceToDevice, s));
 }
 
+void Dense::join_p() {
+  if (!p_pending_) return;
+  LOBPCG_HIP(hipStreamWaitEvent(s_, ev_p_, 0));
+  p_pending_ = false;
+}
+
+// Mt = (Z_1(:, nc:nx)^T Z_1perp)^T = Z_1perp^T Z_1(:, nc:nx)   (m x na), or its
+// literal reading (the first n_x - n_c rows of Z_1perp, transposed).
+static void p_operand(const double* Z, int64_t ld, int ns, int nx, int nc, bool literal_lq,
+                      double* Mt, int64_t ldm, rocblas_handle h) {
+  const int m = ns - nx;
+  const int na = nx - nc;
+  if (literal_lq) {
+    // Q_1perp rows from the LQ of Z_1perp; the first n_x - n_c of them span
+    // the first n_x - n_c rows of Z_1perp: factor those rows only.
+    const double one = 1.0, zero = 0.0;
+    LOBPCG_ROCBLAS(rocblas_dgeam(h, rocblas_operation_transpose, rocblas_operation_none, m, na,
+                                 &one, Z + nx * ld, (rocblas_int)ld, &zero, Mt, (rocblas_int)ldm,
+                                 Mt, (rocblas_int)ldm));
+  } else {
+    dgemm(h, rocblas_operation_transpose, rocblas_operation_none, m, na, nx, 1.0, Z + nx * ld, ld,
+          Z + nc * ld, ld, 0.0, Mt, ldm);
+  }
+}
+
+void Dense::rr_p_block(const double* Z, int ns, int nx, int nc, bool literal_lq,
+                       const double* theta, double* C, int64_t ldc, double* theta_p, int64_t ldtp,
+                       hipStream_t s, rocblas_handle h) {
+  const int64_t ld = nsmax_;
+  const int m = ns - nx;
+  const int na = nx - nc;
+  const int np = std::min(na, m);
+  const double* T = Ri_.as<double>();
+  double* Mt = Mt_.as<double>();
+  const int64_t ldm = ld;
+  (void)literal_lq;
+  // LQ of Mt^T == QR of Mt (Householder): Q (m x np) orthonormal columns.
+  // Only the first np columns enter Q (np = min(na, m)).
+  if (geqrf_orgqr_fits(m, np)) {
+    const int tok = timer_ ? timer_->start(s) : -1;
+    launch_geqrf_orgqr(m, np, Mt, ldm, s);
+    if (timer_) timer_->stop(tok, 7, 0.0, s);
+  } else {
+    LOBPCG_ROCBLAS(rocsolver_dgeqrf(h, m, na, Mt, (rocblas_int)ldm, tau_.as<double>()));
+    LOBPCG_ROCBLAS(rocsolver_dorgqr(h, m, np, np, Mt, (rocblas_int)ldm, tau_.as<double>()));
+  }
+  // C_p = T Z_perp Q.
+  double* ZQ = ZQ_.as<double>();
+  dgemm(h, rocblas_operation_none, rocblas_operation_none, ns, np, m, 1.0, Z + nx * ld, ld, Mt, ldm,
+        0.0, ZQ, ld);
+  dgemm(h, rocblas_operation_none, rocblas_operation_none, ns, np, ns, 1.0, T, ld, ZQ, ld, 0.0,
+        C + nx * ldc, ldc);
+  // Line 14: Theta_p = Q^T Theta_perp Q.
+  double* Qs = Qs_.as<double>();
+  copy_cm(m, np, Mt, ldm, Qs, ld, s);
+  launch_row_scale(m, np, theta + nx, Qs, ld, s);
+  dgemm(h, rocblas_operation_transpose, rocblas_operation_none, np, np, m, 1.0, Mt, ldm, Qs, ld, 0.0,
+        theta_p, ldtp);
+  launch_symmetrize(np, theta_p, ldtp, s);
+}
+
 RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int ns, int nx,
                             int nc, bool use_ortho, bool literal_lq, double tau_skip, double* C,
-                            int64_t ldc, double* theta, double* theta_p, int64_t ldtp) {
+                            int64_t ldc, double* theta, double* theta_p, int64_t ldtp,
+                            bool defer_p) {
   LOBPCG_CHECK(ns <= nsmax_ && nx <= ns && nc <= nx, LOBPCG_ERR_ARG, "rr_modified: bad sizes");
+  join_p();
   RROutput out;
   const int64_t ld = nsmax_;
   double* H = H_.as<double>();
@@ -189,55 +271,31 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
     launch_set_identity(ns, ns, T, ld, s_);
   }
   const double* Z = H;
-  // C_x = T [Z_1; Z_2].
-  gemm(rocblas_operation_none, rocblas_operation_none, ns, nx, ns, 1.0, T, ld, Z, ld, 0.0, C, ldc);
   const int m = ns - nx;
   const int na = nx - nc;
   const int np = std::min(na, m);
   out.np = np;
-  if (np > 0) {
-    double* Mt = Mt_.as<double>();
-    const int64_t ldm = ld;
-    if (literal_lq) {
-      // Q_1perp rows from the LQ of Z_1perp; the first n_x - n_c of them span
-      // the first n_x - n_c rows of Z_1perp: factor those rows only.
-      const double one = 1.0, zero = 0.0;
-      LOBPCG_ROCBLAS(rocblas_dgeam(h_, rocblas_operation_transpose, rocblas_operation_none, m, na,
-                                   &one, Z + nx * ld, (rocblas_int)ld, &zero, Mt, (rocblas_int)ldm,
-                                   Mt, (rocblas_int)ldm));
-    } else {
-      // Mt = (Z_1(:, nc:nx)^T Z_1perp)^T = Z_1perp^T Z_1(:, nc:nx)   (m x na)
-      gemm(rocblas_operation_transpose, rocblas_operation_none, m, na, nx, 1.0, Z + nx * ld, ld,
-           Z + nc * ld, ld, 0.0, Mt, ldm);
-    }
-    // LQ of Mt^T == QR of Mt (Householder): Q (m x np) orthonormal columns.
-    // Only the first np columns enter Q (np = min(na, m)).
-    if (geqrf_orgqr_fits(m, np)) {
-      const int tok = timer_ ? timer_->start(s_) : -1;
-      launch_geqrf_orgqr(m, np, Mt, ldm, s_);
-      if (timer_) timer_->stop(tok, 7, 0.0, s_);
-    } else {
-      LOBPCG_ROCBLAS(rocsolver_dgeqrf(h_, m, na, Mt, (rocblas_int)ldm, tau_.as<double>()));
-      LOBPCG_ROCBLAS(rocsolver_dorgqr(h_, m, np, np, Mt, (rocblas_int)ldm, tau_.as<double>()));
-    }
-    // C_p = T Z_perp Q.
-    double* ZQ = ZQ_.as<double>();
-    gemm(rocblas_operation_none, rocblas_operation_none, ns, np, m, 1.0, Z + nx * ld, ld, Mt, ldm,
-         0.0, ZQ, ld);
-    gemm(rocblas_operation_none, rocblas_operation_none, ns, np, ns, 1.0, T, ld, ZQ, ld, 0.0,
-         C + nx * ldc, ldc);
-    // Line 14: Theta_p = Q^T Theta_perp Q.
-    double* Qs = Qs_.as<double>();
-    copy_cm(m, np, Mt, ldm, Qs, ld, s_);
-    launch_row_scale(m, np, theta + nx, Qs, ld, s_);
-    gemm(rocblas_operation_transpose, rocblas_operation_none, np, np, m, 1.0, Mt, ldm, Qs, ld, 0.0,
-         theta_p, ldtp);
-    launch_symmetrize(np, theta_p, ldtp, s_);
+  if (np > 0 && defer_p) {
+    // Lines 13-14 on the second stream: the LQ operand is formed first, so that
+    // the one-workgroup QR is queued before the main stream's next all-CU work.
+    p_operand(Z, ld, ns, nx, nc, literal_lq, Mt_.as<double>(), ld, h_);
+    LOBPCG_HIP(hipEventRecord(ev_z_, s_));
+    LOBPCG_HIP(hipStreamWaitEvent(s2_, ev_z_, 0));
+    rr_p_block(Z, ns, nx, nc, literal_lq, theta, C, ldc, theta_p, ldtp, s2_, h2_);
+    LOBPCG_HIP(hipEventRecord(ev_p_, s2_));
+    p_pending_ = true;
+  }
+  // C_x = T [Z_1; Z_2].
+  gemm(rocblas_operation_none, rocblas_operation_none, ns, nx, ns, 1.0, T, ld, Z, ld, 0.0, C, ldc);
+  if (np > 0 && !defer_p) {
+    p_operand(Z, ld, ns, nx, nc, literal_lq, Mt_.as<double>(), ld, h_);
+    rr_p_block(Z, ns, nx, nc, literal_lq, theta, C, ldc, theta_p, ldtp, s_, h_);
   }
   return out;
 }
 
 int Dense::svqb_transform(double* G, int64_t ldg, int nu, double tau, bool drop, double* Tu) {
+  join_p();
   if (nu == 0) return 0;
   double* d = d_.as<double>();
   double* th = th2_.as<double>();

@@ -34,9 +34,16 @@ class Dense {
   // (np x np, column-major, ld ldtp).  GB is unused when use_ortho.  tau_skip <= 0
   // disables the conditioning test (Algorithm 2).  Synchronises the stream once
   // (to read the Cholesky status and cond) unless use_ortho.
+  //
+  // defer_p: the P block (the QR of Alg. 7's LQ operand, C_p, Theta_p) is left
+  // running on the second stream; C_x is complete on the main stream when the
+  // call returns, C_p and Theta_p only after join_p().
   RROutput rr_modified(const double* GA, const double* GB, int64_t ldg, int ns, int nx, int nc,
                        bool use_ortho, bool literal_lq, double tau_skip, double* C, int64_t ldc,
-                       double* theta, double* theta_p, int64_t ldtp);
+                       double* theta, double* theta_p, int64_t ldtp, bool defer_p = false);
+
+  // Orders the main stream after the deferred P block (no-op when none).
+  void join_p();
 
   // SVQB transform of Algorithms 4 / 6 from the Gram matrix G = U^T M U (nu x nu,
   // column-major, ldg; overwritten): Tu = D Z(:, J) Theta(J)^-1/2 written to Tu
@@ -63,10 +70,21 @@ class Dense {
             const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
             int64_t ldc);
   void syev(int n, double* A, int64_t lda, double* w);
+  // Algorithm 7's P block (from Z and T = D R^-1 in place) on stream s with handle h.
+  void rr_p_block(const double* Z, int ns, int nx, int nc, bool literal_lq, const double* theta,
+                  double* C, int64_t ldc, double* theta_p, int64_t ldtp, hipStream_t s,
+                  rocblas_handle h);
 
   int nsmax_, nxmax_;
   hipStream_t s_;
   rocblas_handle h_ = nullptr;
+  // second stream (default priority) for Algorithm 7's P block (a
+  // one-workgroup QR and small products) beside the main stream's all-CU
+  // work, with its own rocBLAS handle
+  hipStream_t s2_ = nullptr;
+  rocblas_handle h2_ = nullptr;
+  hipEvent_t ev_z_ = nullptr, ev_p_ = nullptr;
+  bool p_pending_ = false;
   int eig_ = 0;
   KernelTimer* timer_ = nullptr;
   int kTridiagMaxN = 512;

@@ -315,7 +315,9 @@ struct GramPlan {
   int64_t rows_per_split;
 };
 
-constexpr int kGramTargetBlocks = 512;
+// Two workgroups on each of 255 CUs: every workgroup of the split-K grid is
+// resident at once even while a one-workgroup kernel holds a CU beside it.
+constexpr int kGramTargetBlocks = 510;
 
 GramPlan gram_plan(int64_t n, int m, int p) {
   GramPlan g;
@@ -697,7 +699,7 @@ __global__ void fill_implicit_kernel(int nx, int np, const double* __restrict__ 
   double a = 0.0, b = (i == j) ? 1.0 : 0.0;
   if (i < nx && j < nx) a = (i == j) ? theta[i] : 0.0;
   else if (i >= nx && j >= nx) a = theta_p[(i - nx) + (int64_t)(j - nx) * ldtp];
-  GA[i + (int64_t)j * ldg] = a;
+  if (GA) GA[i + (int64_t)j * ldg] = a;
   if (GB) GB[i + (int64_t)j * ldg] = b;
 }
 

@@ -71,7 +71,7 @@ void launch_gaussian(int64_t n, int ncols, double* dst, int64_t ldd, uint64_t se
 
 // Implicit Gram blocks of eqs. (12)-(14): in the leading (nx+np) x (nx+np) block of
 // GA set diag(theta) / 0 / theta_p (np x np, column-major, ld ldtp); in GB set I.
-// GB may be null.
+// GA and GB may each be null (that matrix is left untouched).
 void launch_fill_implicit(int nx, int np, const double* theta, const double* theta_p,
                           int64_t ldtp, double* GA, double* GB, int64_t ldg, hipStream_t s);
 

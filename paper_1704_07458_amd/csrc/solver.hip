@@ -170,10 +170,12 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   dense_->set_timer(&timer_);
   LOBPCG_HIP(hipHostMalloc((void**)&hbuf_, sizeof(int32_t) * 8, hipHostMallocDefault));
   LOBPCG_HIP(hipHostMalloc((void**)&hdbl_, sizeof(double) * 8, hipHostMallocDefault));
+  LOBPCG_HIP(hipEventCreateWithFlags(&ev_nc_, hipEventDisableTiming));
   LOBPCG_HIP(hipStreamSynchronize(s_));
 }
 
 Solver::~Solver() {
+  if (ev_nc_) (void)hipEventDestroy(ev_nc_);
   if (hbuf_) (void)hipHostFree(hbuf_);
   if (hdbl_) (void)hipHostFree(hdbl_);
 }
@@ -220,7 +222,8 @@ void KernelTimer::collect() {
     used_ = 0;
     return;
   }
-  LOBPCG_HIP(hipEventSynchronize(pool_[recs_.back().e1]));
+  // records can sit on two streams: wait for each of them
+  for (const Rec& r : recs_) LOBPCG_HIP(hipEventSynchronize(pool_[r.e1]));
   for (const Rec& r : recs_) {
     float ms = 0.f;
     LOBPCG_HIP(hipEventElapsedTime(&ms, pool_[r.e0], pool_[r.e1]));
@@ -435,6 +438,8 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     RROutput o;
     for (int attempt = 0; attempt < 2; ++attempt) {
       const int ns = nv + nw;
+      // Gram columns of W in S^T A S and S^T B S (explicit: every block involving
+      // W is computed, section 5.2); the rest from eqs. (12)-(14).
       // A W and B W (explicit: every block involving W is computed, section 5.2).
       phase_mark(0);
       spmm<T>(A, W, ldS, AW, ldX, nw);
@@ -442,14 +447,15 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       // Gram columns of W in S^T A S and S^T B S; the rest from eqs. (12)-(14).
       phase_mark(3);
       gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AW, ldX, B ? BW : W,
-                     B ? ldX : ldS, GA, nv, GB, nv, ldg, nv);
+              B ? ldX : ldS, GA, nv, GB, nv, ldg, nv);
       launch_fill_implicit(nx, np, theta, theta_p, nx, GA, use_ortho ? nullptr : GB, ldg, s_);
-      // Line 11: RayleighRitzModified.
+      // Line 11: RayleighRitzModified; its P block is left running on the second
+      // stream beside the X update, A X and the residual, which do not touch P.
       phase_mark(4);
       {
         const int tok = timer_.start(s_);
         o = dense_->rr_modified(GA, GB, ldg, ns, nx, nc, use_ortho, lq_literal, tau_skip, C, ldc,
-                                theta, theta_p, nx);
+                                theta, theta_p, nx, true);
         timer_.stop(tok, 4, 0.0, s_);
       }
       if (!o.flipped) break;
@@ -465,29 +471,34 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     if (o.flipped) throw Error(LOBPCG_ERR_BREAKDOWN, "Rayleigh-Ritz failed after orthoDrop");
     const int ns = nv + nw;
     const int npn = o.np;
-    // Line 16: [X, P] = S [C_x, C_p].
+    // Line 16: [X, P] = S [C_x, C_p]: X now, P once the P block is done.
     phase_mark(5);
-    update<T>(n, ns, nx + npn, Sc, ldS, C, ldc, 1.0, 0.0, Sn, ldS);
+    update<T>(n, ns, nx, Sc, ldS, C, ldc, 1.0, 0.0, Sn, ldS);
     cur ^= 1;
-    np = npn;
     // Line 17: R = AX - BX Theta with A X recomputed (explicit products).
     phase_mark(0);
     spmm<T>(A, Sn, ldS, AX, ldX, nx);
-    if (B) {
-      spmm<T>(*B, Sn, ldS, BXP, ldBXP, nx);
-      if (np > 0) spmm<T>(*B, Sn + nx, ldS, BXP + nx, ldBXP, np);
-    }
+    if (B) spmm<T>(*B, Sn, ldS, BXP, ldBXP, nx);
     phase_mark(6);
     {
       const int tok = timer_.start(s_);
       launch_residual<T>(n, nx, AX, ldX, B ? BXP : nullptr, ldBXP, Sn, ldS, theta, dinv,
-                         use_cb ? Rb : Sn + nx + np, use_cb ? ldX : ldS, normA_, normB_, tol,
+                         use_cb ? Rb : Sn + nx + npn, use_cb ? ldX : ldS, normA_, normB_, tol,
                          rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
       timer_.stop(tok, 3, (double)n * nx * sizeof(T) * (B ? 4 : 3) + (dinv ? 8.0 * n : 0.0), s_);
     }
-    // Line 18: number of converged pairs (leading run meeting criterion 9).
+    // Line 18: number of converged pairs (leading run meeting criterion 9); the
+    // host waits for this copy only, the P update runs on meanwhile.
     LOBPCG_HIP(hipMemcpyAsync(hbuf_, nc_.get(), sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
-    sync();
+    LOBPCG_HIP(hipEventRecord(ev_nc_, s_));
+    dense_->join_p();
+    phase_mark(5);
+    if (npn > 0) {
+      update<T>(n, ns, npn, Sc, ldS, C + (int64_t)nx * ldc, ldc, 1.0, 0.0, Sn + nx, ldS);
+      if (B) spmm<T>(*B, Sn + nx, ldS, BXP + nx, ldBXP, npn);
+    }
+    np = npn;
+    LOBPCG_HIP(hipEventSynchronize(ev_nc_));
     if (hbuf_[1]) throw Error(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
     nc = hbuf_[0];
     if (nc >= k_) {

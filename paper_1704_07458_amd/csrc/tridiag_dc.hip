@@ -260,52 +260,86 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
     }
   }
   __syncthreads();
+  double dmax = 0.0, zmax = 0.0;
+  for (int w = 0; w < kDcThreads / kWave; ++w) {
+    dmax = fmax(dmax, wmax[0][w]);
+    zmax = fmax(zmax, wmax[1][w]);
+  }
+  const double tol = 8.0 * 2.220446049250313e-16 * fmax(dmax, zmax);
+  // deflation of tiny rho |z_i|, in parallel
+  for (int i = t; i < m; i += kDcThreads) defl[i] = (rho * fabs(zs[i]) <= tol) ? 1 : 0;
+  __syncthreads();
   if (t == 0) {
-    double dmax = 0.0, zmax = 0.0;
-    for (int w = 0; w < kDcThreads / kWave; ++w) {
-      dmax = fmax(dmax, wmax[0][w]);
-      zmax = fmax(zmax, wmax[1][w]);
-    }
-    const double tol = 8.0 * 2.220446049250313e-16 * fmax(dmax, zmax);
+    // close pairs, in order over the survivors: |dt c s| <= tol (c^2 + s^2) is
+    // |dt c s| / (c^2 + s^2) <= tol without the square root and divisions (a
+    // close pair is rare, the rotation is formed only then); the next entry is
+    // loaded before the current one is tested
     int nrot = 0, prev = -1;
+    double pd = 0.0, pz = 0.0;
+    double nd = ds[0], nz = zs[0];
+    int ndf = defl[0];
     for (int i = 0; i < m; ++i) {
-      defl[i] = (rho * fabs(zs[i]) <= tol) ? 1 : 0;
-      if (defl[i]) continue;
-      if (prev >= 0) {
-        const double s = zs[prev], c = zs[i];
-        const double dt = ds[i] - ds[prev];
-        // |dt c s| / (c^2 + s^2) <= tol, tested without the square root and
-        // divisions (a close pair is rare); the rotation is formed only then
-        if (fabs(dt * c * s) <= tol * fma(c, c, s * s)) {
-          const double tau = hypot(c, s);
-          const double cc = c / tau, ss = -s / tau;
-          zs[i] = tau;
-          zs[prev] = 0.0;
-          const double dp = ds[prev], di = ds[i];
-          ds[prev] = dp * cc * cc + di * ss * ss;
-          ds[i] = dp * ss * ss + di * cc * cc;
-          defl[prev] = 1;
-          iw[kRp + lo + nrot] = prev;
-          iw[kRi + lo + nrot] = i;
-          rw[lo + nrot] = cc;
-          rw[kDcMaxN + lo + nrot] = ss;
-          ++nrot;
-        }
+      const double di = nd, zi = nz;
+      const int dfi = ndf;
+      if (i + 1 < m) {
+        nd = ds[i + 1];
+        nz = zs[i + 1];
+        ndf = defl[i + 1];
+      }
+      if (dfi) continue;
+      if (prev >= 0 && fabs((di - pd) * zi * pz) <= tol * fma(zi, zi, pz * pz)) {
+        const double tau = hypot(zi, pz);
+        const double cc = zi / tau, ss = -pz / tau;
+        const double dnew = pd * ss * ss + di * cc * cc;
+        zs[i] = tau;
+        zs[prev] = 0.0;
+        ds[prev] = pd * cc * cc + di * ss * ss;
+        ds[i] = dnew;
+        defl[prev] = 1;
+        iw[kRp + lo + nrot] = prev;
+        iw[kRi + lo + nrot] = i;
+        rw[lo + nrot] = cc;
+        rw[kDcMaxN + lo + nrot] = ss;
+        ++nrot;
+        pd = dnew;
+        pz = tau;
+      } else {
+        pd = di;
+        pz = zi;
       }
       prev = i;
     }
-    int K = 0;
-    double zn = 0.0;
-    for (int i = 0; i < m; ++i)
+    iw[kNrot + node] = nrot;
+  }
+  __syncthreads();
+  // K and |z_kept|^2: per-thread partials, wave sums, then the waves in order
+  {
+    double zp = 0.0;
+    int kc = 0;
+    for (int i = t; i < m; i += kDcThreads)
       if (!defl[i]) {
-        ++K;
-        zn = fma(zs[i], zs[i], zn);
+        ++kc;
+        zp = fma(zs[i], zs[i], zp);
       }
+    zp = wave64_sum(zp);
+    for (int off = kWave / 2; off > 0; off >>= 1) kc += __shfl_xor(kc, off, kWave);
+    if (t % kWave == 0) {
+      wmax[0][t / kWave] = zp;
+      wmax[1][t / kWave] = (double)kc;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    double zn = 0.0;
+    int K = 0;
+    for (int w = 0; w < kDcThreads / kWave; ++w) {
+      zn += wmax[0][w];
+      K += (int)wmax[1][w];
+    }
     K_s = K;
     znorm_s = sqrt(zn);
     rho_s = rho * zn;
     iw[node] = K;
-    iw[kNrot + node] = nrot;
     rhoK[node] = rho * zn;
   }
   __syncthreads();
