@@ -11,6 +11,7 @@
 
 #include "kernels.hpp"
 #include "cholinv.hpp"
+#include "small_gemm.hpp"
 #include "tridiag_dc.hpp"
 
 namespace lobpcg {
@@ -79,10 +80,20 @@ Dense::~Dense() {
   if (hcond_) (void)hipHostFree(hcond_);
 }
 
+// Products of the projected-problem sizes go to the MFMA small-product kernel on
+// the handle's stream (a library GEMM uses a handful of workgroups there);
+// larger ones to rocBLAS.
 static void dgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n,
                   int k, double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                   double beta, double* C, int64_t ldc) {
   if (m == 0 || n == 0) return;
+  if (small_dgemm_fits(m, n, k)) {
+    hipStream_t s = nullptr;
+    LOBPCG_ROCBLAS(rocblas_get_stream(h, &s));
+    small_dgemm(ta == rocblas_operation_transpose, tb == rocblas_operation_transpose, m, n, k,
+                alpha, A, lda, B, ldb, beta, C, ldc, s);
+    return;
+  }
   LOBPCG_ROCBLAS(rocblas_dgemm(h, ta, tb, m, n, k, &alpha, A, (rocblas_int)lda, B,
                                (rocblas_int)ldb, &beta, C, (rocblas_int)ldc));
 }
@@ -201,8 +212,7 @@ void Dense::rr_p_block(const double* Z, int ns, int nx, int nc, bool literal_lq,
         C + nx * ldc, ldc);
   // Line 14: Theta_p = Q^T Theta_perp Q.
   double* Qs = Qs_.as<double>();
-  copy_cm(m, np, Mt, ldm, Qs, ld, s);
-  launch_row_scale(m, np, theta + nx, Qs, ld, s);
+  launch_row_scale_copy(m, np, theta + nx, Mt, ldm, Qs, ld, s);
   dgemm(h, rocblas_operation_transpose, rocblas_operation_none, np, np, m, 1.0, Mt, ldm, Qs, ld, 0.0,
         theta_p, ldtp);
   launch_symmetrize(np, theta_p, ldtp, s);

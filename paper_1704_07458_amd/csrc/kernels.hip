@@ -781,6 +781,15 @@ __global__ void row_scale_kernel(int m, int n, const double* __restrict__ d, dou
   A[i + (int64_t)j * lda] *= d[i];
 }
 
+__global__ void row_scale_copy_kernel(int m, int n, const double* __restrict__ d,
+                                      const double* __restrict__ A, int64_t lda,
+                                      double* __restrict__ B, int64_t ldb) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * n) return;
+  const int i = (int)(idx % m), j = (int)(idx / m);
+  B[i + (int64_t)j * ldb] = d[i] * A[i + (int64_t)j * lda];
+}
+
 __global__ void col_scale_kernel(int m, int n, const double* __restrict__ A, int64_t lda,
                                  const double* __restrict__ theta, int mode,
                                  double* __restrict__ B, int64_t ldb) {
@@ -791,14 +800,30 @@ __global__ void col_scale_kernel(int m, int n, const double* __restrict__ A, int
   B[i + (int64_t)j * ldb] = A[i + (int64_t)j * lda] * f;
 }
 
-__global__ void symmetrize_kernel(int n, double* A, int64_t lda) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * n) return;
-  const int i = (int)(idx % n), j = (int)(idx / n);
-  if (i < j) {
-    const double v = 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]);
-    A[i + (int64_t)j * lda] = v;
-    A[j + (int64_t)i * lda] = v;
+// A <- (A + A^T) / 2 by pairs of 32 x 32 tiles (I, J), I <= J, one workgroup per
+// pair: both tiles are read and written with lanes along columns (coalesced),
+// the transposed tile through LDS.
+constexpr int kSymTile = 32;
+__global__ __launch_bounds__(256) void symmetrize_kernel(int n, double* A, int64_t lda) {
+  __shared__ double tI[kSymTile][kSymTile + 1], tJ[kSymTile][kSymTile + 1];
+  // pair index -> (I, J), J >= I, column by column of the upper tile triangle
+  const int q = blockIdx.x;
+  int J = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+  while (J * (J + 1) / 2 > q) --J;
+  while ((J + 1) * (J + 2) / 2 <= q) ++J;
+  const int I = q - J * (J + 1) / 2;
+  const int r = threadIdx.x % kSymTile, c0 = threadIdx.x / kSymTile;
+  const int i0 = I * kSymTile, j0 = J * kSymTile;
+  for (int c = c0; c < kSymTile; c += 256 / kSymTile) {
+    // tI = A(i0 + r, j0 + c), tJ = A(j0 + r, i0 + c)
+    tI[r][c] = (i0 + r < n && j0 + c < n) ? A[(i0 + r) + (int64_t)(j0 + c) * lda] : 0.0;
+    tJ[r][c] = (j0 + r < n && i0 + c < n) ? A[(j0 + r) + (int64_t)(i0 + c) * lda] : 0.0;
+  }
+  __syncthreads();
+  for (int c = c0; c < kSymTile; c += 256 / kSymTile) {
+    // A(i0 + r, j0 + c) and its mirror A(j0 + c, i0 + r) both become the mean
+    if (i0 + r < n && j0 + c < n) A[(i0 + r) + (int64_t)(j0 + c) * lda] = 0.5 * (tI[r][c] + tJ[c][r]);
+    if (j0 + r < n && i0 + c < n) A[(j0 + r) + (int64_t)(i0 + c) * lda] = 0.5 * (tJ[r][c] + tI[c][r]);
   }
 }
 
@@ -1548,6 +1573,14 @@ void launch_row_scale(int m, int n, const double* d, double* A, int64_t lda, hip
   LOBPCG_HIP(hipGetLastError());
 }
 
+void launch_row_scale_copy(int m, int n, const double* d, const double* A, int64_t lda, double* B,
+                           int64_t ldb, hipStream_t s) {
+  if (m == 0 || n == 0) return;
+  hipLaunchKernelGGL(row_scale_copy_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, s, m, n,
+                     d, A, lda, B, ldb);
+  LOBPCG_HIP(hipGetLastError());
+}
+
 void launch_col_scale(int m, int n, const double* A, int64_t lda, const double* theta, int mode,
                       double* B, int64_t ldb, hipStream_t s) {
   if (m == 0 || n == 0) return;
@@ -1558,7 +1591,8 @@ void launch_col_scale(int m, int n, const double* A, int64_t lda, const double* 
 
 void launch_symmetrize(int n, double* A, int64_t lda, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, s, n, A,
+  const int nt = (n + kSymTile - 1) / kSymTile;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, n, A,
                      lda);
   LOBPCG_HIP(hipGetLastError());
 }

@@ -90,6 +90,9 @@ void launch_zero_lower(int n, double* A, int64_t ld, hipStream_t s);
 
 // Row scaling: A(i, j) = d_i A(i, j) for an m x n column-major block.
 void launch_row_scale(int m, int n, const double* d, double* A, int64_t lda, hipStream_t s);
+// B = diag(d) A (m x n, column-major).
+void launch_row_scale_copy(int m, int n, const double* d, const double* A, int64_t lda, double* B,
+                           int64_t ldb, hipStream_t s);
 
 // Column scaling: B(i, j) = A(i, j) * f(theta_j) for an m x n column-major block,
 // mode 0: f = theta_j, mode 1: f = theta_j^-1/2.

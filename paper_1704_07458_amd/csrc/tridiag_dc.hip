@@ -22,6 +22,7 @@
 #include <cmath>
 #include <string>
 
+#include "small_gemm.hpp"
 #include "tridiag_dc.hpp"
 #include "wave.hpp"
 
@@ -654,21 +655,19 @@ void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64
                        iw, zh, Qs, Dl, G, ldz);
     LOBPCG_HIP(hipGetLastError());
     // Y = G U over each node's full block: G is zero beyond the kept columns
-    // and U zero below the kept rows (the kept count is known on the device only)
+    // and U zero below the kept rows (the kept count is known on the device
+    // only); all nodes of the level in one launch
+    int offs[kSmallGemmBatch], dims[kSmallGemmBatch];
     for (int node = 0; node < nodes; ++node) {
       int lo = 0, hi = n;
       for (int l = level - 1; l >= 0; --l) {
         const int mid = (lo + hi) / 2;
         if ((node >> l) & 1) lo = mid; else hi = mid;
       }
-      const int m = hi - lo;
-      const double one = 1.0, zero = 0.0;
-      dc_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, m, m, &one,
-                             G + (int64_t)lo * ldz + lo, (rocblas_int)ldz,
-                             Dl + (int64_t)lo * ldz + lo, (rocblas_int)ldz, &zero,
-                             Y + (int64_t)lo * ldz + lo, (rocblas_int)ldz),
-               "tridiag_dc gemm");
+      offs[node] = lo;
+      dims[node] = hi - lo;
     }
+    small_dgemm_diag_batch(nodes, offs, dims, G, ldz, Dl, ldz, Y, ldz, s);
     hipLaunchKernelGGL(dc_order_kernel, dim3(nodes), dim3(kDcThreads), 0, s, n, level, iw, lamk,
                        dsort, lam);
     hipLaunchKernelGGL(dc_scatter_kernel, dim3(nodes * mmax), dim3(kDcThreads), 0, s, n, level,
