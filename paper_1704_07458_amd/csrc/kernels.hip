@@ -164,24 +164,27 @@ struct Mfma<float> {
 };
 
 // ------------------------------------------------------------------ Gram
-// Workgroup tile 128 (m) x 128 (p): 2 x 2 waves, each wave a 64 x 64 register
-// tile of 4 x 4 MFMA 16x16x4 blocks.  The row range is consumed in stages of
-// kKB rows: each stage's L and R tiles are loaded with coalesced global loads
-// into registers while the previous stage is multiplied out of LDS, then
-// stored to the other LDS buffer (double buffering, one barrier per stage).
+// Workgroup tile TM (m) x TP (p), TM, TP in {128, 64}: 2 x 2 waves, each wave a
+// (TM/2) x (TP/2) register tile of MFMA 16x16x4 blocks.  The row range is
+// consumed in stages of kKB rows: each stage's L and R tiles are loaded with
+// coalesced global loads into registers while the previous stage is
+// multiplied out of LDS, then stored to the other LDS buffer (double
+// buffering, one barrier per stage).  The tile size is chosen per launch to
+// pad m and p least: the kernel is MFMA-bound, so padding is lost time.
 // Grid: x = nsplit * tiles (tile index fastest, so workgroups that share a row
 // range land together on one XCD).  Each workgroup sums its row range [k0, k1)
 // and writes a partial tile to part[split][i][j].
 constexpr int kGramTM = 128, kGramTP = 128, kKB = 16, kLdsPad = 2;
 
-template <typename T>
+template <typename T, int TM, int TP>
 __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
     int64_t n, int m, int p, int p1, const T* __restrict__ L, int64_t ldl,
     const T* __restrict__ R1, int64_t ldr1, const T* __restrict__ R2, int64_t ldr2,
     double* __restrict__ part, int tiles_m, int tiles_p, int64_t rows_per_split) {
   using acc_t = typename Mfma<T>::acc_t;
-  __shared__ T Ls[2][kKB][kGramTM + kLdsPad];
-  __shared__ T Rs[2][kKB][kGramTP + kLdsPad];
+  constexpr int FA = TM / 32, FB = TP / 32;  // 16 x 16 blocks per wave and dimension
+  __shared__ T Ls[2][kKB][TM + kLdsPad];
+  __shared__ T Rs[2][kKB][TP + kLdsPad];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int ntiles = tiles_m * tiles_p;
   const int split = lb / ntiles;
@@ -196,47 +199,51 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
   const int64_t k0 = (int64_t)split * rows_per_split;
   const int64_t k1 = k0 + rows_per_split < n ? k0 + rows_per_split : n;
 
-  // Global-load assignment: thread owns column c of the tile and rows r0 + 2i.
-  const int c = tid % kGramTM;
-  const int r0 = tid / kGramTM;
-  const int ca = tm * kGramTM + c;
-  const bool okA = ca < m;
-  const T* colA = L + (okA ? ca : 0);
-  const int cb = tp * kGramTP + c;
-  const bool okB = cb < p;
+  // Global-load assignment: thread owns column ca of the L tile and rows
+  // ra + RA i, and column cb of the R tile and rows rb + RB i.
+  constexpr int RA = 256 / TM, RB = 256 / TP;
+  constexpr int KA = kKB / RA, KBr = kKB / RB;  // rows per thread per stage
+  const int ca = tid % TM, ra = tid / TM;
+  const int cbt = tid % TP, rb = tid / TP;
+  const int gca = tm * TM + ca;
+  const bool okA = gca < m;
+  const T* colA = L + (okA ? gca : 0);
+  const int gcb = tp * TP + cbt;
+  const bool okB = gcb < p;
   const T* colB;
   int64_t ldB;
-  if (cb < p1) {
-    colB = R1 + cb;
+  if (gcb < p1) {
+    colB = R1 + gcb;
     ldB = ldr1;
   } else {
-    colB = R2 + (okB ? cb - p1 : 0);
+    colB = R2 + (okB ? gcb - p1 : 0);
     ldB = ldr2;
   }
-  constexpr int kPer = kKB / 2;  // rows per thread per stage
-  T ga[kPer], gb[kPer];
+  T ga[KA], gb[KBr];
   auto gload = [&](int64_t kb) {
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const int64_t row = kb + r0 + 2 * i;
-      const bool rok = row < k1;
-      ga[i] = (rok && okA) ? colA[row * ldl] : T(0);
-      gb[i] = (rok && okB) ? colB[row * ldB] : T(0);
+    for (int i = 0; i < KA; ++i) {
+      const int64_t row = kb + ra + RA * i;
+      ga[i] = (row < k1 && okA) ? colA[row * ldl] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < KBr; ++i) {
+      const int64_t row = kb + rb + RB * i;
+      gb[i] = (row < k1 && okB) ? colB[row * ldB] : T(0);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      Ls[buf][r0 + 2 * i][c] = ga[i];
-      Rs[buf][r0 + 2 * i][c] = gb[i];
-    }
+    for (int i = 0; i < KA; ++i) Ls[buf][ra + RA * i][ca] = ga[i];
+#pragma unroll
+    for (int i = 0; i < KBr; ++i) Rs[buf][rb + RB * i][cbt] = gb[i];
   };
 
-  acc_t acc[4][4];
+  acc_t acc[FA][FB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    for (int b = 0; b < FB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
   const int64_t nst = (k1 - k0 + kKB - 1) / kKB;
   if (nst > 0) {
@@ -250,16 +257,15 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
     if (more) gload(k0 + (st + 1) * kKB);
 #pragma unroll
     for (int s = 0; s < kKB / 4; ++s) {
-      T a[4], b[4];
+      T a[FA], b[FB];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        a[f] = Ls[buf][4 * s + lk][wm * 64 + f * 16 + li];
-        b[f] = Rs[buf][4 * s + lk][wp * 64 + f * 16 + li];
-      }
+      for (int f = 0; f < FA; ++f) a[f] = Ls[buf][4 * s + lk][wm * (TM / 2) + f * 16 + li];
 #pragma unroll
-      for (int fa = 0; fa < 4; ++fa)
+      for (int f = 0; f < FB; ++f) b[f] = Rs[buf][4 * s + lk][wp * (TP / 2) + f * 16 + li];
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
+      for (int fa = 0; fa < FA; ++fa)
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
@@ -268,22 +274,19 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
   // Store the partial tile (FP64).
   double* out = part + (int64_t)split * m * p;
 #pragma unroll
-  for (int fa = 0; fa < 4; ++fa)
+  for (int fa = 0; fa < FA; ++fa)
 #pragma unroll
-    for (int fb = 0; fb < 4; ++fb) {
-      const int j = tp * kGramTP + wp * 64 + fb * 16 + li;
+    for (int fb = 0; fb < FB; ++fb) {
+      const int j = tp * TP + wp * (TP / 2) + fb * 16 + li;
       if (j >= p) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = tm * kGramTM + wm * 64 + fa * 16 + Mfma<T>::row(lk, q);
+        const int i = tm * TM + wm * (TM / 2) + fa * 16 + Mfma<T>::row(lk, q);
         if (i < m) out[(int64_t)i * p + j] = (double)acc[fa][fb][q];
       }
     }
 }
 
-// Second stage: G(i, j) = sum over splits in fixed order (column-major output).
-// Column j < p1 goes to column c1 + j of G1, the rest to column c2 + j - p1 of G2.
-// Rows i < mirror_rows are also written transposed (symmetric completion).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int p1, int nsplit,
                                                           const double* __restrict__ part,
                                                           double* __restrict__ G1, int c1,
@@ -311,6 +314,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int p1, 
 }
 
 struct GramPlan {
+  int tm, tp;  // tile sizes (128 or 64)
   int tiles_m, tiles_p, nsplit;
   int64_t rows_per_split;
 };
@@ -321,8 +325,20 @@ constexpr int kGramTargetBlocks = 510;
 
 GramPlan gram_plan(int64_t n, int m, int p) {
   GramPlan g;
-  g.tiles_m = (m + kGramTM - 1) / kGramTM;
-  g.tiles_p = (p + kGramTP - 1) / kGramTP;
+  // the tile pair that pads m x p least (ties: the larger tiles)
+  auto padded = [](int x, int t) { return (int64_t)((x + t - 1) / t) * t; };
+  int64_t best = -1;
+  for (int tm : {kGramTM, kGramTM / 2})
+    for (int tp : {kGramTP, kGramTP / 2}) {
+      const int64_t area = padded(m, tm) * padded(p, tp);
+      if (best < 0 || area < best) {
+        best = area;
+        g.tm = tm;
+        g.tp = tp;
+      }
+    }
+  g.tiles_m = (m + g.tm - 1) / g.tm;
+  g.tiles_p = (p + g.tp - 1) / g.tp;
   const int ntiles = g.tiles_m * g.tiles_p;
   // About kGramTargetBlocks workgroups (2 per CU) with at least 256 rows each.
   int64_t target = std::max<int64_t>(1, kGramTargetBlocks / std::max(ntiles, 1));
@@ -1415,9 +1431,17 @@ void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const
   double* part = static_cast<double*>(work);
   if (nsplit > 0) {
     const unsigned grid = (unsigned)(nsplit * g.tiles_m * g.tiles_p);
-    hipLaunchKernelGGL((gram_partial_kernel<T>), dim3(grid), dim3(256), 0, s, n, m, p, p1, L,
-                       ldl, R1, ldr1, R2 ? R2 : R1, R2 ? ldr2 : ldr1, part, g.tiles_m, g.tiles_p,
-                       g.rows_per_split);
+    const T* R2e = R2 ? R2 : R1;
+    const int64_t ldr2e = R2 ? ldr2 : ldr1;
+#define LOBPCG_GRAM_LAUNCH(TMv, TPv)                                                          \
+  hipLaunchKernelGGL((gram_partial_kernel<T, TMv, TPv>), dim3(grid), dim3(256), 0, s, n, m, p, \
+                     p1, L, ldl, R1, ldr1, R2e, ldr2e, part, g.tiles_m, g.tiles_p,           \
+                     g.rows_per_split)
+    if (g.tm == kGramTM && g.tp == kGramTP) LOBPCG_GRAM_LAUNCH(kGramTM, kGramTP);
+    else if (g.tm == kGramTM) LOBPCG_GRAM_LAUNCH(kGramTM, kGramTP / 2);
+    else if (g.tp == kGramTP) LOBPCG_GRAM_LAUNCH(kGramTM / 2, kGramTP);
+    else LOBPCG_GRAM_LAUNCH(kGramTM / 2, kGramTP / 2);
+#undef LOBPCG_GRAM_LAUNCH
     LOBPCG_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for((int64_t)m * p)), dim3(256), 0, s, m, p,
