@@ -353,15 +353,15 @@ GramPlan gram_plan(int64_t n, int m, int p) {
 }
 
 // ------------------------------------------------------------------ update
-// Y tile 128 rows x 128 cols per workgroup: 2 x 2 waves, each a 64 x 64
-// register tile of 4 x 4 MFMA blocks.  K is consumed in stages of kKB: the
-// S tile (128 rows x kKB, row segments of kKB contiguous elements) and the C
-// tile (kKB x 128, column segments of C, which is column-major) go through
-// double-buffered LDS as in the Gram kernel.
+// Y tile 128 rows x TN cols per workgroup (TN = 128, or 64 when that pads N
+// less): 2 x 2 waves, each a 64 x (TN/2) register tile of MFMA blocks.  K is
+// consumed in stages of kKB: the S tile (128 rows x kKB, row segments of kKB
+// contiguous elements) and the C tile (kKB x TN, column segments of C, which
+// is column-major) go through double-buffered LDS as in the Gram kernel.
 // Grid: x = row tiles * col tiles (col tile fastest).
 constexpr int kUpdTM = 128, kUpdTN = 128, kUpdPad = 1;
 
-template <typename T>
+template <typename T, int TN>
 __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
                                                      const T* __restrict__ S, int64_t lds,
                                                      const double* __restrict__ C, int64_t ldc,
@@ -369,7 +369,8 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
                                                      int64_t ldy, int tiles_n) {
   using acc_t = typename Mfma<T>::acc_t;
   __shared__ T Ss[2][kUpdTM][kKB + kUpdPad];
-  __shared__ T Cs[2][kUpdTN][kKB + kUpdPad];
+  constexpr int FB = TN / 32;  // 16-column blocks per wave
+  __shared__ T Cs[2][TN][kKB + kUpdPad];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t tr = lb / tiles_n;
   const int tc = lb % tiles_n;
@@ -383,35 +384,38 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
   // (or columns) q0 + 16 i, i = 0..7.
   const int kk = tid % kKB;
   const int q0 = tid / kKB;
-  constexpr int kPer = kUpdTM / 16;
+  constexpr int kPer = kUpdTM / 16, kPerC = TN / 16;
   const int rows_valid = (int)(n - tr * kUpdTM < kUpdTM ? n - tr * kUpdTM : kUpdTM);
-  const int cols_valid = N - tc * kUpdTN < kUpdTN ? N - tc * kUpdTN : kUpdTN;
+  const int cols_valid = N - tc * TN < TN ? N - tc * TN : TN;
   const T* sbase = S + (tr * kUpdTM + q0) * lds + kk;
-  const double* cbase = C + (int64_t)(tc * kUpdTN + q0) * ldc + kk;
+  const double* cbase = C + (int64_t)(tc * TN + q0) * ldc + kk;
   const int64_t sstep = 16 * lds, cstep = 16 * ldc;
-  T gs[kPer], gc[kPer];
+  T gs[kPer], gc[kPerC];
   auto gload = [&](int kb) {
     const bool kok = kb + kk < K;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int q = q0 + 16 * i;
       gs[i] = (kok && q < rows_valid) ? sbase[i * sstep + kb] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < kPerC; ++i) {
+      const int q = q0 + 16 * i;
       gc[i] = (kok && q < cols_valid) ? (T)cbase[i * cstep + kb] : T(0);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      Ss[buf][q0 + 16 * i][kk] = gs[i];
-      Cs[buf][q0 + 16 * i][kk] = gc[i];
-    }
+    for (int i = 0; i < kPer; ++i) Ss[buf][q0 + 16 * i][kk] = gs[i];
+#pragma unroll
+    for (int i = 0; i < kPerC; ++i) Cs[buf][q0 + 16 * i][kk] = gc[i];
   };
 
-  acc_t acc[4][4];
+  acc_t acc[4][FB];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    for (int b = 0; b < FB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
   const int nst = (K + kKB - 1) / kKB;
   if (nst > 0) {
@@ -425,16 +429,15 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
     if (more) gload((st + 1) * kKB);
 #pragma unroll
     for (int s = 0; s < kKB / 4; ++s) {
-      T a[4], b[4];
+      T a[4], b[FB];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        a[f] = Ss[buf][wr * 64 + f * 16 + li][4 * s + lk];
-        b[f] = Cs[buf][wc * 64 + f * 16 + li][4 * s + lk];
-      }
+      for (int f = 0; f < 4; ++f) a[f] = Ss[buf][wr * 64 + f * 16 + li][4 * s + lk];
+#pragma unroll
+      for (int f = 0; f < FB; ++f) b[f] = Cs[buf][wc * (TN / 2) + f * 16 + li][4 * s + lk];
 #pragma unroll
       for (int fa = 0; fa < 4; ++fa)
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
+        for (int fb = 0; fb < FB; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
@@ -443,8 +446,8 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
 #pragma unroll
   for (int fa = 0; fa < 4; ++fa)
 #pragma unroll
-    for (int fb = 0; fb < 4; ++fb) {
-      const int j = tc * kUpdTN + wc * 64 + fb * 16 + li;
+    for (int fb = 0; fb < FB; ++fb) {
+      const int j = tc * TN + wc * (TN / 2) + fb * 16 + li;
       if (j >= N) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -1459,12 +1462,19 @@ template <typename T>
 void launch_update(int64_t n, int K, int N, const T* S, int64_t lds, const double* C, int64_t ldc,
                    double alpha, double beta, T* Y, int64_t ldy, hipStream_t s) {
   if (n == 0 || N == 0) return;
-  const int tiles_n = (N + kUpdTN - 1) / kUpdTN;
+  // 64-wide column tiles when they pad N less than 128-wide ones
+  const bool narrow = (N + 63) / 64 * 64 < (N + kUpdTN - 1) / kUpdTN * kUpdTN;
+  const int tn = narrow ? 64 : kUpdTN;
+  const int tiles_n = (N + tn - 1) / tn;
   const int64_t tiles_r = (n + kUpdTM - 1) / kUpdTM;
   const int64_t grid = tiles_r * tiles_n;
   LOBPCG_CHECK(grid < (int64_t)1 << 31, LOBPCG_ERR_ARG, "update grid too large");
-  hipLaunchKernelGGL((update_kernel<T>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N, S, lds, C,
-                     ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);
+  if (narrow)
+    hipLaunchKernelGGL((update_kernel<T, 64>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N, S,
+                       lds, C, ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);
+  else
+    hipLaunchKernelGGL((update_kernel<T, kUpdTN>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N,
+                       S, lds, C, ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);
   LOBPCG_HIP(hipGetLastError());
 }
 
