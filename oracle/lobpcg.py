@@ -236,20 +236,24 @@ def ortho_drop(
 
 
 def ortho(Mop: Operator, U: np.ndarray, V: np.ndarray, MV: np.ndarray, tol: Tolerances,
-          itmax1: int = 3, itmax2: int = 3) -> np.ndarray:
+          stats: Optional[OrthoStats] = None, itmax1: int = 3, itmax2: int = 3) -> np.ndarray:
     """Algorithm 3 (Stathopoulos-Wu ortho with svqb only, no dropping).
 
-    Kept for the section 4.1 example, where it shows the failure that
-    orthoDrop fixes.
+    Used by the section 4.1 example, where it shows the failure that orthoDrop
+    fixes, and by the version 2 rung of the section 6 ablation (lobpcg with
+    ortho_kind="hl").
     """
+    stats = stats if stats is not None else OrthoStats()
     for _i in range(itmax1):
+        stats.outer += 1
         if V.shape[1] > 0:
             U = U - V @ (MV.T @ U)
         for _j in range(itmax2):
             U = svqb(Mop, U, tol.tau_replace(U.shape[1]))
+            stats.svqb_calls += 1
             if _rel_orth_error(U, Mop(U)) <= tol.tau_ortho:
                 break
-        if _rel_ext_error(V, MV, U) <= tol.tau_ortho:
+        if V.shape[1] == 0 or _rel_ext_error(V, MV, U) <= tol.tau_ortho:
             break
     return U
 
@@ -400,6 +404,8 @@ def lobpcg(
     Omega_T: Optional[np.ndarray] = None,
     literal_lq: bool = False,
     exact_norms: Optional[tuple] = None,
+    force_ortho: bool = False,
+    ortho_kind: str = "drop",
 ) -> LobpcgResult:
     """Algorithm 8: the robust and efficient LOBPCG of the paper, FP64.
 
@@ -408,7 +414,15 @@ def lobpcg(
     precond: W0 = precond(R) applies K^-1 column-wise (None = identity).
     Omega_T: m x k sketch for the norm estimate (default X0, reading R1).
     exact_norms: (||A||_2, ||B||_2) to use instead of the sketch.
+    force_ortho, ortho_kind: the section 6 ablation of the algorithm's
+    versions.  force_ortho orthogonalises W from the first iteration and never
+    takes the Cholesky path of Algorithm 7 (lines 12-15 never fire);
+    ortho_kind "drop" is orthoDrop (Algorithm 5), "hl" is ortho (Algorithm 3).
+    The defaults are Algorithm 8 itself.
     """
+    if ortho_kind not in ("drop", "hl"):
+        raise ValueError("ortho_kind must be 'drop' or 'hl'")
+    orth = ortho_drop if ortho_kind == "drop" else ortho
     tols = tols or Tolerances()
     Aop, Bop = Operator(_csr(A)), Operator(_csr(B))
     Kinv = precond if precond is not None else (lambda R: R.copy())
@@ -432,7 +446,7 @@ def lobpcg(
     AX, BX = Aop(X), Bop(X)
     theta_x = theta
     R = AX - BX * theta_x[None, :]
-    n_c, use_ortho = 0, False
+    n_c, use_ortho = 0, bool(force_ortho)
     P = np.zeros((n, 0))
     AP, BP = np.zeros((n, 0)), np.zeros((n, 0))
     history: List[IterRecord] = []
@@ -448,7 +462,7 @@ def lobpcg(
         W0 = Kinv(R[:, n_c:])
         V, MV = np.hstack([X, P]), np.hstack([BX, BP])
         if use_ortho:
-            W = ortho_drop(Bop, W0, V, MV, tols, ostats)
+            W = orth(Bop, W0, V, MV, tols, ostats)
         else:
             W = W0
         AW, BW = Aop(W), Bop(W)
@@ -464,7 +478,7 @@ def lobpcg(
             # Lines 12-15: switch to orthogonalised W for good.
             use_ortho = True
             switch_iter = it
-            W = ortho_drop(Bop, W0, V, MV, tols, ostats)
+            W = orth(Bop, W0, V, MV, tols, ostats)
             AW, BW = Aop(W), Bop(W)
             S = np.hstack([X, P, W])
             AS = np.hstack([AX, AP, AW])

@@ -387,6 +387,52 @@ def test_forced_ortho_switch_still_converges():
     assert res.ortho_stats.svqb_calls > 0
 
 
+# ------------------------------------- section 6: the versions of the algorithm
+def test_e1_ortho_of_algorithm_3_keeps_a_spurious_column():
+    """Algorithm 3 (svqb only) on the section 4.1 example: the dependent column
+    survives as a rounding-noise direction, the orthogonality tests are never met
+    (all three outer passes run), and [X0, U] gives the spurious Ritz value 0.
+    orthoDrop on the same input keeps one column in fewer svqb passes."""
+    g = _read_golden("e1_spurious_ritz.txt")
+    A, X0 = _e1_setup()
+    Mop = L.Operator(None)
+    theta0 = np.diag(X0.T @ (A @ X0))
+    W0 = A @ X0 - X0 * theta0
+    st = L.OrthoStats()
+    U = L.ortho(Mop, W0, X0, X0, L.Tolerances(), st)
+    assert U.shape[1] == 2 and st.outer == 3
+    S = np.hstack([X0, U])
+    assert np.linalg.matrix_rank(S, tol=1e-8) == 3
+    theta = np.linalg.eigvalsh(S.T @ (A @ S))
+    assert abs(theta[0] - g["spurious_theta1"][0]) < 1e-8
+    sd = L.OrthoStats()
+    Ud = L.ortho_drop(Mop, W0, X0, X0, L.Tolerances(), sd)
+    assert Ud.shape[1] == 1 and sd.svqb_calls < st.svqb_calls
+
+
+@pytest.mark.parametrize("force,kind", [(False, "drop"), (True, "drop"), (True, "hl")])
+def test_ablation_versions_reach_the_closed_form(force, kind):
+    """force_ortho orthogonalises W on every iteration and never switches;
+    every version converges to the Dirichlet spectrum."""
+    w = P.workload(0)
+    res = _solve(w, force_ortho=force, ortho_kind=kind)
+    assert res.converged
+    ex = cf.smallest(cf.laplacian_2d_dirichlet(32), w.k)
+    assert np.max(np.abs(res.theta[: w.k] - ex) / ex) < 1e-10
+    assert all(h.use_ortho == force for h in res.history)
+    assert res.ortho_switch_iter == -1
+    if force:
+        assert res.ortho_stats.svqb_calls >= res.iterations
+    else:
+        assert res.ortho_stats.svqb_calls == 0
+
+
+def test_ablation_rejects_unknown_ortho_kind():
+    w = P.workload(0)
+    with pytest.raises(ValueError):
+        _solve(w, ortho_kind="qr", maxit=1)
+
+
 def test_maxit_returns_not_converged():
     w = P.workload(0)
     res = _solve(w, maxit=3)
