@@ -10,6 +10,11 @@ and for the FP32-split path.
 Prints one JSON line.  Options: --steps K --warmup W (default 3 / 1),
 --gpus N (only 1 is supported), --no-cpu (skip the oracle baseline),
 --cpu-iters M (oracle iterations in the CPU sample, default 5).
+
+--ablation instead solves the same workload with the versions of the method
+that section 6 (Fig. 2) compares, built as option switches of the one
+solver, and prints one JSON line per version (iterations, time, orthogonal-
+isation counts, phase breakdown).
 """
 
 from __future__ import annotations
@@ -92,6 +97,55 @@ def cpu_baseline(w, iters, gpu_iters):
     }
 
 
+# Versions of section 6 (Fig. 2) that this solver can run: every X/P Gram block
+# explicit and W orthogonalised on every iteration with Algorithm 3 (version 2,
+# the conservative Hetmaniuk-Lehoucq type), then with orthoDrop (version 5),
+# then skipping orthogonalisation until Algorithm 7 rejects the Cholesky path
+# (version 6), then the X/P blocks from eqs. (12)-(14) (version 7, Algorithm 8).
+ABLATION = [
+    ("v2_hl_ortho", 2, {"force_ortho": 1, "ortho_mode": 1, "implicit_gram": 0}),
+    ("v5_orthodrop", 5, {"force_ortho": 1, "ortho_mode": 0, "implicit_gram": 0}),
+    ("v6_skip_ortho", 6, {"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 0}),
+    ("v7_algorithm8", 7, {"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 1}),
+]
+
+
+def run_ablation(torch, B, w, X0, exact):
+    base = None
+    for label, version, opts in ABLATION:
+        s = B.Solver(w.A, w.k, precond="jacobi", **opts)
+        # first solve: per-phase times (stream-synchronised, so not the timed one)
+        s.set_profiling(True)
+        pinfo = s.solve(w.tol, X0)
+        s.set_profiling(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve(w.tol, X0)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        lam, X, _ = s.eigpairs(w.k)
+        rho, err = check_solution(w, lam.cpu().numpy(), X.cpu().numpy(), info["norm_A_est"],
+                                  exact)
+        ph = pinfo["seconds_phase"]
+        tot = sum(ph.values())
+        base = base if base is not None else sec
+        line = {"ablation": label, "paper_version": version, "options": opts,
+                "status": info["status"], "iterations": info["iterations"], "seconds": sec,
+                "relative_time": sec / base, "flips": info["flips"],
+                "ortho_switch_iter": info["ortho_switch_iter"],
+                "ortho_calls": info["ortho_calls"], "svqb_calls": info["svqb_calls"],
+                "svqb_per_ortho": (info["svqb_calls"] / info["ortho_calls"]
+                                   if info["ortho_calls"] else None),
+                "phase_share": {k: v / tot for k, v in ph.items()} if tot > 0 else None,
+                "max_rho": rho, "eig_rel_err_vs_closed_form": err,
+                "workload": "3D 7-point Dirichlet Laplacian 64^3, k=100, n_x=110, Jacobi, "
+                            "tol 1e-8"}
+        _log(f"[bench] ablation {label}: {info['iterations']} iters {sec:.3f}s "
+             f"svqb/ortho {line['svqb_per_ortho']}")
+        print(json.dumps(line), flush=True)
+        s.close()
+
+
 def kernel_source_hash() -> str:
     import hashlib
 
@@ -127,6 +181,8 @@ def main():
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="solve with each version of section 6 instead (one line each)")
     ap.add_argument("--phases", action="store_true",
                     help="one extra untimed FP64 solve with per-phase timing (stream syncs)")
     args = ap.parse_args()
@@ -158,6 +214,9 @@ def main():
     w = P.workload(1)
     exact = cf.smallest(cf.laplacian_3d_dirichlet(64), w.k)
     X0 = torch.from_numpy(w.X0).cuda()  # resident in HBM before timing
+    if args.ablation:
+        run_ablation(torch, B, w, X0, exact)
+        return
 
     s64 = B.Solver(w.A, w.k, precond="jacobi")
     t64, infos64, st64 = timed_solves(torch, s64, X0, w.tol, args.steps, args.warmup, "fp64")

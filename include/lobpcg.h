@@ -81,9 +81,11 @@ typedef struct {
                                 converges at fp32_tol, then FP64 iterations to tol */
   int32_t precond;           /* 0 = none (K = I); 1 = Jacobi (diagonal of A, shifted to be
                                 positive when it is not); 2 = the solve's callback */
-  int32_t implicit_products; /* -1 = automatic cost model; 0 = recompute A X (and B X) with the
-                                sparse product; 1 = implicit updates A X = (A S) C_x
-                                (section 5.2, B = I only) */
+  int32_t implicit_products; /* -1 (automatic) or 0: A X (and B X) are recomputed with the
+                                sparse product after each update; on this GPU that costs less
+                                than the implicit update A X = (A S) C_x of section 5.2.  1 (the
+                                implicit update) is not provided and is rejected with
+                                LOBPCG_ERR_ARG */
   int32_t lq_literal;        /* 0 = P built from the LQ of Z_1(:, n_c:n_x)^T Z_1perp; 1 = the first
                                 n_x - n_c rows of the LQ of Z_1perp (Algorithm 7, line 14) */
   double tau_ortho;          /* relative orthogonality tolerance of Algorithm 5; <= 0: 1e-12
@@ -95,6 +97,16 @@ typedef struct {
   double fp32_tol;           /* criterion (9) threshold ending the FP32 phase; <= 0: 1e-5 */
   uint64_t seed;             /* seed of the Gaussian initial block when X0 is NULL */
   void* stream;              /* hipStream_t for all work; NULL = default stream */
+  /* Switches for the version ladder of section 6 (Figure 2); the defaults give
+   * Algorithm 8. */
+  int32_t ortho_mode;        /* 0 = orthoDrop (Algorithm 5, with basis truncation); 1 = ortho
+                                (Algorithm 3, the Hetmaniuk-Lehoucq scheme: svqb on every inner
+                                pass, no columns dropped) */
+  int32_t force_ortho;       /* 1 = orthogonalise W from the first iteration and solve the
+                                projected problem as a standard one (never the Cholesky path of
+                                Algorithm 7), as the versions without skipped orthogonalisation */
+  int32_t implicit_gram;     /* 1 = the X and P blocks of S^T A S and S^T B S from eqs. (12)-(14)
+                                (default); 0 = computed explicitly (with A P and B P) */
 } lobpcg_options;
 
 /* Per-solve statistics. seconds_phase: 0 sparse products, 1 preconditioner,
@@ -107,8 +119,8 @@ typedef struct {
   int32_t ortho_switch_iter;  /* iteration at which useOrtho became true; -1 if never */
   int32_t fp32_iterations;    /* iterations of the FP32 phase (split mode) */
   int32_t fp64_iterations;    /* FP64 iterations */
-  int32_t svqb_calls;         /* svqb + svqbDrop calls inside orthoDrop */
-  int32_t ortho_calls;        /* orthoDrop calls */
+  int32_t svqb_calls;         /* svqb + svqbDrop passes inside orthogonalisation */
+  int32_t ortho_calls;        /* orthoDrop (or ortho, ortho_mode 1) calls */
   int32_t flips;              /* Cholesky rejections (0 or 1 per phase) */
   double norm_A_est;          /* ||A||_2 lower bound from the Gaussian sketch (section 4.3) */
   double norm_B_est;          /* same for B (1 when B = I) */

@@ -64,6 +64,9 @@ class lobpcg_options(C.Structure):
         ("fp32_tol", C.c_double),
         ("seed", C.c_uint64),
         ("stream", C.c_void_p),
+        ("ortho_mode", C.c_int32),
+        ("force_ortho", C.c_int32),
+        ("implicit_gram", C.c_int32),
     ]
 
 

@@ -65,6 +65,9 @@ void lobpcg_default_options(lobpcg_options* opt) {
   opt->fp32_tol = 1e-5;
   opt->seed = 0;
   opt->stream = nullptr;
+  opt->ortho_mode = 0;
+  opt->force_ortho = 0;
+  opt->implicit_gram = 1;
 }
 
 int lobpcg_create(lobpcg_t* out, const lobpcg_csr* A, const lobpcg_csr* B, int32_t k,

@@ -128,6 +128,11 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   nx_ = opt.block_size > 0 ? opt.block_size : k + (k + 9) / 10;
   LOBPCG_CHECK(nx_ >= k, LOBPCG_ERR_ARG, "block_size must be >= k");
   LOBPCG_CHECK(3 * (int64_t)nx_ <= n_, LOBPCG_ERR_ARG, "need 3 * block_size <= n");
+  LOBPCG_CHECK(opt.implicit_products <= 0, LOBPCG_ERR_ARG,
+               "implicit product updates (implicit_products = 1) are not provided: A X is "
+               "recomputed with the sparse product");
+  LOBPCG_CHECK(opt.ortho_mode == 0 || opt.ortho_mode == 1, LOBPCG_ERR_ARG,
+               "ortho_mode must be 0 (orthoDrop) or 1 (ortho)");
   LOBPCG_CHECK(opt.precision == 0 || opt.precision == 1, LOBPCG_ERR_ARG, "precision must be 0/1");
   LOBPCG_CHECK(opt.precond >= 0 && opt.precond <= 2, LOBPCG_ERR_ARG, "precond must be 0/1/2");
   const bool split = opt.precision == 1;
@@ -321,8 +326,9 @@ int Solver::ortho_drop(Blocks<T>& b, const DevCsr* B, T* U, int64_t ldu, int nu,
     }
     gram_u();
     for (int j = 0; j < 3 && nu > 0; ++j) {
-      // Lines 6-10: svqb on the first pass, svqbDrop afterwards.
-      const bool drop = j > 0;
+      // Lines 6-10: svqb on the first pass, svqbDrop afterwards (Algorithm 3,
+      // ortho_mode 1: svqb on every pass, nothing dropped).
+      const bool drop = j > 0 && opt_.ortho_mode == 0;
       const double factor = drop ? (opt_.drop_factor > 0 ? opt_.drop_factor : 10.0)
                                  : (opt_.replace_factor > 0 ? opt_.replace_factor : 10.0);
       const double tau = factor * nu * eps;
@@ -414,7 +420,9 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   launch_residual<T>(n, nx, AX, ldX, B ? BXP : nullptr, ldBXP, S1, ldS, theta, dinv,
                      use_cb ? Rb : S1 + nx, use_cb ? ldX : ldS, normA_, normB_, tol,
                      rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
-  bool use_ortho = false;  // line 6
+  // line 6 (useOrtho = false), or true from the start in the versions of
+  // section 6 that orthogonalise every iteration
+  bool use_ortho = opt_.force_ortho != 0;
   int rc = LOBPCG_NOT_CONVERGED;
   int it = 0;
   for (it = 1; it <= maxit; ++it) {
@@ -438,8 +446,6 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     RROutput o;
     for (int attempt = 0; attempt < 2; ++attempt) {
       const int ns = nv + nw;
-      // Gram columns of W in S^T A S and S^T B S (explicit: every block involving
-      // W is computed, section 5.2); the rest from eqs. (12)-(14).
       // A W and B W (explicit: every block involving W is computed, section 5.2).
       phase_mark(0);
       spmm<T>(A, W, ldS, AW, ldX, nw);
@@ -448,7 +454,20 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       phase_mark(3);
       gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AW, ldX, B ? BW : W,
               B ? ldX : ldS, GA, nv, GB, nv, ldg, nv);
-      launch_fill_implicit(nx, np, theta, theta_p, nx, GA, use_ortho ? nullptr : GB, ldg, s_);
+      if (opt_.implicit_gram) {
+        launch_fill_implicit(nx, np, theta, theta_p, nx, GA, use_ortho ? nullptr : GB, ldg, s_);
+      } else {
+        // The X and P blocks computed explicitly: [X P]^T [AX AP] and
+        // [X P]^T [BX BP] (or [X P]^T [X P]); A P goes through the ortho buffer.
+        T* AP = b.U2.template as<T>();
+        phase_mark(0);
+        if (np > 0) spmm<T>(A, Sc + nx, ldS, AP, ldX, np);
+        phase_mark(3);
+        gram<T>(n, nv, nv, nx, Sc, ldS, AX, ldX, AP, ldX, GA, 0, GA, nx, ldg, 0);
+        if (!use_ortho)
+          gram<T>(n, nv, nv, nv, Sc, ldS, B ? BXP : Sc, B ? ldBXP : ldS, nullptr, 0, GB, 0,
+                  nullptr, 0, ldg, 0);
+      }
       // Line 11: RayleighRitzModified; its P block is left running on the second
       // stream beside the X update, A X and the residual, which do not touch P.
       phase_mark(4);

@@ -163,6 +163,44 @@ def test_forced_ortho_switch_generalized_pencil(lib):
     assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
 
 
+# Versions of section 6 (Fig. 2) as option switches, each against the oracle run
+# the same way: Algorithm 3 ortho on every iteration with explicit X/P Gram
+# blocks (version 2), orthoDrop instead (version 5), orthogonalisation skipped
+# until Algorithm 7 asks for it (version 6), and forced orthoDrop with the
+# implicit Gram blocks of eqs. (12)-(14).
+LADDER = [
+    ({"force_ortho": 1, "ortho_mode": 1, "implicit_gram": 0},
+     {"force_ortho": True, "ortho_kind": "hl"}),
+    ({"force_ortho": 1, "ortho_mode": 0, "implicit_gram": 0},
+     {"force_ortho": True, "ortho_kind": "drop"}),
+    ({"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 0}, {}),
+    ({"force_ortho": 1, "ortho_mode": 0, "implicit_gram": 1}, {"force_ortho": True}),
+]
+
+
+@pytest.mark.parametrize("idx", [0, 2])
+@pytest.mark.parametrize("gpu_opts,ref_opts", LADDER)
+def test_section6_versions_match_oracle(lib, idx, gpu_opts, ref_opts):
+    w = P.workload(idx, small=idx != 0)
+    s, info = _gpu_solve(w, **gpu_opts)
+    assert info["converged"], info
+    ref = _oracle(w, **ref_opts)
+    assert ref.converged
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    th = ref.theta[: w.k]
+    assert np.max(np.abs(lam - th) / np.abs(th)) <= EIG_RTOL
+    assert abs(info["iterations"] - ref.iterations) <= max(2, 0.1 * ref.iterations)
+    if gpu_opts["force_ortho"]:
+        assert info["flips"] == 0 and info["ortho_switch_iter"] == -1
+        assert info["ortho_calls"] == info["iterations"]
+        ref_svqb = ref.ortho_stats.svqb_calls
+        assert abs(info["svqb_calls"] - ref_svqb) <= 0.25 * ref_svqb + 2
+    Bm = None if w.B is None else w.B.to_scipy()
+    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], info["norm_B_est"]) <= RESID_TOL)
+    if Bm is not None:
+        assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
+
+
 def test_literal_lq_reading_also_converges(lib):
     w = P.workload(0)
     s, info = _gpu_solve(w, lq_literal=1)
