@@ -406,6 +406,7 @@ def lobpcg(
     exact_norms: Optional[tuple] = None,
     force_ortho: bool = False,
     ortho_kind: str = "drop",
+    largest: bool = False,
 ) -> LobpcgResult:
     """Algorithm 8: the robust and efficient LOBPCG of the paper, FP64.
 
@@ -419,11 +420,18 @@ def lobpcg(
     takes the Cholesky path of Algorithm 7 (lines 12-15 never fire);
     ortho_kind "drop" is orthoDrop (Algorithm 5), "hl" is ortho (Algorithm 3).
     The defaults are Algorithm 8 itself.
+    largest: the k largest eigenpairs instead (section 2: the Ritz values are
+    ordered the other way).  Taking them in descending order for A is taking
+    them in ascending order for -A, so the iteration runs on (-A, B) and the
+    Ritz values are negated on return; precond must then approximate the
+    inverse of (-A) shifted, as for any pencil.
     """
     if ortho_kind not in ("drop", "hl"):
         raise ValueError("ortho_kind must be 'drop' or 'hl'")
     orth = ortho_drop if ortho_kind == "drop" else ortho
     tols = tols or Tolerances()
+    if largest:
+        A = -_csr(A)
     Aop, Bop = Operator(_csr(A)), Operator(_csr(B))
     Kinv = precond if precond is not None else (lambda R: R.copy())
     X0 = np.asarray(X0, dtype=np.float64)
@@ -504,7 +512,8 @@ def lobpcg(
             break
         if W.shape[1] == 0 and P.shape[1] == 0:
             break  # the search space cannot grow any more
-    return LobpcgResult(converged, it, theta_x.copy(), X, rho, n_c, normA, normB, history,
+    theta_out = -theta_x if largest else theta_x.copy()
+    return LobpcgResult(converged, it, theta_out, X, rho, n_c, normA, normB, history,
                         switch_iter, ostats)
 
 

@@ -433,6 +433,32 @@ def test_ablation_rejects_unknown_ortho_kind():
         _solve(w, ortho_kind="qr", maxit=1)
 
 
+# ------------------------------------- section 2: the largest eigenpairs instead
+def test_largest_eigenpairs_closed_form():
+    w = P.workload(0)
+    res = _solve(w, largest=True)
+    assert res.converged
+    ex = np.sort(cf.laplacian_2d_dirichlet(32))[::-1][: w.k]
+    assert np.max(np.abs(res.theta[: w.k] - ex) / ex) < 1e-10
+    X, th = res.X[:, : w.k], res.theta[: w.k]
+    A = w.A.to_scipy()
+    rho = L.criterion9(A @ X - X * th, X, th, cf.norm2_laplacian_2d(32), 1.0)
+    assert np.all(rho <= w.tol)
+    assert np.all(np.diff(th) <= 0)  # descending
+
+
+def test_largest_eigenpairs_of_random_pencil_brute_force():
+    n = 150
+    Am = P.random_sparse_spd(21, n, 0.05, shift=-0.5).to_scipy()
+    Bm = P.random_sparse_spd(22, n, 0.03, shift=2.0).to_scipy()
+    X0 = P.initial_block(3, n, 8)
+    res = L.lobpcg(Am, X0, 6, 1e-10, B=Bm, largest=True)
+    assert res.converged
+    w, _ = brute.jacobi_eigh_pencil(Am.toarray(), Bm.toarray())
+    top = w[::-1][:6]
+    assert np.max(np.abs(res.theta[:6] - top) / np.abs(top)) < 1e-9
+
+
 def test_maxit_returns_not_converged():
     w = P.workload(0)
     res = _solve(w, maxit=3)
