@@ -15,6 +15,9 @@ Prints one JSON line.  Options: --steps K --warmup W (default 3 / 1),
 that section 6 (Fig. 2) compares, built as option switches of the one
 solver, and prints one JSON line per version (iterations, time, orthogonal-
 isation counts, phase breakdown).
+
+--ksweep solves the 64^3 Laplacian for k = 25, 50, 100, 150, 200 (the analog of
+Fig. 4's time against the number of eigenpairs) and prints one line per k.
 """
 
 from __future__ import annotations
@@ -146,6 +149,36 @@ def run_ablation(torch, B, w, X0, exact):
         s.close()
 
 
+KSWEEP = (25, 50, 100, 150, 200)
+
+
+def run_ksweep(torch, B, P, cf):
+    w = P.workload(1)
+    ev = cf.laplacian_3d_dirichlet(64)
+    for i, k in enumerate(KSWEEP):
+        n_x = P.block_size(k)
+        X0 = torch.from_numpy(P.initial_block(0, w.A.n, n_x)).cuda()
+        s = B.Solver(w.A, k, precond="jacobi")
+        if i == 0:
+            s.solve(w.tol, X0)  # one-time library set-up outside the timed solves
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve(w.tol, X0)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        lam, X, _ = s.eigpairs(k)
+        rho, err = check_solution(w, lam.cpu().numpy(), X.cpu().numpy(), info["norm_A_est"],
+                                  cf.smallest(ev, k))
+        line = {"ksweep_k": k, "n_x": n_x, "status": info["status"],
+                "iterations": info["iterations"], "seconds": sec,
+                "ms_per_iteration": 1e3 * sec / max(1, info["iterations"]),
+                "max_rho": rho, "eig_rel_err_vs_closed_form": err,
+                "workload": "3D 7-point Dirichlet Laplacian 64^3, Jacobi, tol 1e-8"}
+        _log(f"[bench] ksweep k={k}: {info['iterations']} iters {sec:.3f}s")
+        print(json.dumps(line), flush=True)
+        s.close()
+
+
 def kernel_source_hash() -> str:
     import hashlib
 
@@ -183,6 +216,8 @@ def main():
                     help="only run 4 plain device copies of MIB MiB (HBM counter calibration)")
     ap.add_argument("--ablation", action="store_true",
                     help="solve with each version of section 6 instead (one line each)")
+    ap.add_argument("--ksweep", action="store_true",
+                    help="time to k eigenpairs for several k instead (one line each)")
     ap.add_argument("--phases", action="store_true",
                     help="one extra untimed FP64 solve with per-phase timing (stream syncs)")
     args = ap.parse_args()
@@ -216,6 +251,9 @@ def main():
     X0 = torch.from_numpy(w.X0).cuda()  # resident in HBM before timing
     if args.ablation:
         run_ablation(torch, B, w, X0, exact)
+        return
+    if args.ksweep:
+        run_ksweep(torch, B, P, cf)
         return
 
     s64 = B.Solver(w.A, w.k, precond="jacobi")

@@ -107,6 +107,11 @@ typedef struct {
                                 Algorithm 7), as the versions without skipped orthogonalisation */
   int32_t implicit_gram;     /* 1 = the X and P blocks of S^T A S and S^T B S from eqs. (12)-(14)
                                 (default); 0 = computed explicitly (with A P and B P) */
+  int32_t largest;           /* 1 = the k largest eigenpairs instead (section 2: the Ritz values
+                                ordered the other way round), computed as the k smallest of
+                                (-A, B); lobpcg_eigpairs then returns descending values.  The
+                                Jacobi preconditioner is built from -A (its diagonal shifted
+                                positive).  lobpcg_adjoint rejects this mode (LOBPCG_ERR_ARG) */
 } lobpcg_options;
 
 /* Per-solve statistics. seconds_phase: 0 sparse products, 1 preconditioner,
@@ -151,7 +156,7 @@ int lobpcg_solve(lobpcg_t h, double tol, const double* X0, int32_t x0_on_device,
                  lobpcg_precond_fn K, void* K_user, lobpcg_info* info);
 
 /* Copy out the leading `count` Ritz pairs (count <= n_x) of the last solve:
- * lambda (count values, ascending), X (row-major n x count, leading dimension
+ * lambda (count values, ascending; descending with opt.largest), X (row-major n x count, leading dimension
  * ldx >= count, B-orthonormal columns) and rel_resid (criterion (9) per pair);
  * any output pointer may be NULL.  on_device = 0: host buffers; 1: device.
  * Errors: LOBPCG_ERR_STATE before a solve, LOBPCG_ERR_ARG. */

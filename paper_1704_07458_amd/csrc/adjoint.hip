@@ -194,6 +194,8 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
                     double* grad, double cg_tol, int cg_maxit, int32_t* cg_iters) {
   LOBPCG_CHECK(solved_, LOBPCG_ERR_STATE, "adjoint called before a solve");
   LOBPCG_CHECK(!haveB_, LOBPCG_ERR_ARG, "adjoint supports B = I only");
+  LOBPCG_CHECK(opt_.largest == 0, LOBPCG_ERR_ARG,
+               "adjoint is not provided for the largest-eigenpair mode");
   LOBPCG_CHECK(count >= 1 && count <= nx_, LOBPCG_ERR_ARG, "count must be in [1, n_x]");
   LOBPCG_CHECK(grad != nullptr, LOBPCG_ERR_ARG, "grad is NULL");
   LOBPCG_CHECK(X_bar == nullptr || ld_xbar >= count, LOBPCG_ERR_ARG, "ld_xbar < count");

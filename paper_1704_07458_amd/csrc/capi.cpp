@@ -68,6 +68,7 @@ void lobpcg_default_options(lobpcg_options* opt) {
   opt->ortho_mode = 0;
   opt->force_ortho = 0;
   opt->implicit_gram = 1;
+  opt->largest = 0;
 }
 
 int lobpcg_create(lobpcg_t* out, const lobpcg_csr* A, const lobpcg_csr* B, int32_t k,

@@ -853,6 +853,11 @@ __global__ void set_identity_kernel(int m, int n, double* A, int64_t lda) {
   A[i + (int64_t)j * lda] = (i == j) ? 1.0 : 0.0;
 }
 
+__global__ void negate_kernel(int n, const double* __restrict__ x, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = -x[i];
+}
+
 // theta ascending.  The eigenvalues above the threshold form a trailing run.
 __global__ __launch_bounds__(256) void svqb_theta_kernel(int n, double* theta, double tau, int drop,
                                                          double* scale, int32_t* info) {
@@ -1635,6 +1640,12 @@ void launch_set_identity(int m, int n, double* A, int64_t lda, hipStream_t s) {
   if (m == 0 || n == 0) return;
   hipLaunchKernelGGL(set_identity_kernel, dim3(blocks_for((int64_t)m * n)), dim3(256), 0, s, m, n,
                      A, lda);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+void launch_negate(int n, const double* x, double* y, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(negate_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, x, y);
   LOBPCG_HIP(hipGetLastError());
 }
 

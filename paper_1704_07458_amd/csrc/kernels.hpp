@@ -104,6 +104,8 @@ void launch_symmetrize(int n, double* A, int64_t lda, hipStream_t s);
 
 // Set A to the m x n identity-like pattern (1 on the diagonal).
 void launch_set_identity(int m, int n, double* A, int64_t lda, hipStream_t s);
+// y = -x (n values; y may be x).
+void launch_negate(int n, const double* x, double* y, hipStream_t s);
 
 // SVQB post-processing (Algorithms 4 and 6): theta ascending (n values).
 // replace mode: theta_j <- max(theta_j, tau * max|theta|), keep all (keep = n).

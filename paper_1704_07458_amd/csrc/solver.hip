@@ -133,6 +133,10 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
                "recomputed with the sparse product");
   LOBPCG_CHECK(opt.ortho_mode == 0 || opt.ortho_mode == 1, LOBPCG_ERR_ARG,
                "ortho_mode must be 0 (orthoDrop) or 1 (ortho)");
+  LOBPCG_CHECK(opt.largest == 0 || opt.largest == 1, LOBPCG_ERR_ARG, "largest must be 0/1");
+  // The k largest pairs of (A, B) are the k smallest of (-A, B).
+  if (opt.largest)
+    for (double& v : va) v = -v;
   LOBPCG_CHECK(opt.precision == 0 || opt.precision == 1, LOBPCG_ERR_ARG, "precision must be 0/1");
   LOBPCG_CHECK(opt.precond >= 0 && opt.precond <= 2, LOBPCG_ERR_ARG, "precond must be 0/1/2");
   const bool split = opt.precision == 1;
@@ -623,8 +627,12 @@ int Solver::eigpairs(int count, double* lambda, double* X, int64_t ldx, double* 
   LOBPCG_CHECK(count >= 0 && count <= nx_, LOBPCG_ERR_ARG, "count must be in [0, n_x]");
   if (count == 0) return LOBPCG_OK;
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  if (lambda)
+  const bool neg = opt_.largest != 0;
+  if (lambda && neg && on_device) {
+    launch_negate(count, theta_.as<double>(), lambda, s_);
+  } else if (lambda) {
     LOBPCG_HIP(hipMemcpyAsync(lambda, theta_.get(), sizeof(double) * count, kind, s_));
+  }
   if (rho) LOBPCG_HIP(hipMemcpyAsync(rho, rho_.get(), sizeof(double) * count, kind, s_));
   if (X) {
     LOBPCG_CHECK(ldx >= count, LOBPCG_ERR_ARG, "ldx < count");
@@ -632,6 +640,8 @@ int Solver::eigpairs(int count, double* lambda, double* X, int64_t ldx, double* 
                                 sizeof(double) * count, n_, kind, s_));
   }
   sync();
+  if (lambda && neg && !on_device)
+    for (int i = 0; i < count; ++i) lambda[i] = -lambda[i];
   return LOBPCG_OK;
 }
 

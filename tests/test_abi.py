@@ -43,7 +43,7 @@ def test_default_options_values():
     o = B.default_options()
     assert o.maxit == 2000 and o.precision == 0 and o.tau_ortho == 1e-12
     assert o.drop_factor == 10.0 and o.skip_factor == 10.0 and o.implicit_products == -1
-    assert o.ortho_mode == 0 and o.force_ortho == 0 and o.implicit_gram == 1
+    assert o.ortho_mode == 0 and o.force_ortho == 0 and o.implicit_gram == 1 and o.largest == 0
 
 
 def _create(A, k, B_=None, **kw):
@@ -101,6 +101,8 @@ def test_rejects_unprovided_implicit_products_and_bad_ortho_mode():
     assert code == -1 and "implicit" in msg
     code, msg = _create(A, 2, ortho_mode=2)
     assert code == -1 and "ortho_mode" in msg
+    code, msg = _create(A, 2, largest=2)
+    assert code == -1 and "largest" in msg
 
 
 def test_rejects_mismatched_B_and_nonfinite_values():

@@ -201,6 +201,73 @@ def test_section6_versions_match_oracle(lib, idx, gpu_opts, ref_opts):
         assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
 
 
+def _golden(name):
+    import os
+
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                key, *nums = line.split()
+                vals[key] = np.array([float(x) for x in nums])
+    return vals
+
+
+@pytest.mark.parametrize("ortho_mode", [0, 1])
+def test_e1_first_iteration_orthodrop_against_ortho(lib, ortho_mode):
+    """The section 4.1 example on the GPU (n = 256: the example holds for any n >= 4),
+    one iteration with W orthogonalised.  orthoDrop keeps one column of
+    W0 = [-e3, e3]/sqrt(2) and gives the Ritz values of span(e1, e2, e3);
+    Algorithm 3 keeps both, so the four columns of S span a 3D space and the
+    Rayleigh-Ritz step that assumes S^T S = I returns the spurious value 0."""
+    from paper_1704_07458_amd import binding as B
+
+    g = _golden("e1_spurious_ritz.txt")
+    n = 256
+    A = P.tridiag_1d(n, 1.0, 3.0, 1.0)
+    X0 = np.zeros((n, 2))
+    X0[0] = [1.0, 1.0]
+    X0[1] = [-1.0, 1.0]
+    X0 /= np.sqrt(2.0)
+    s = B.Solver(A, 2, block_size=2, maxit=1, force_ortho=1, ortho_mode=ortho_mode)
+    info = s.solve(1e-14, X0)
+    assert info["iterations"] == 1 and info["ortho_calls"] == 1
+    lam = s.eigpairs(2)[0].cpu().numpy()
+    if ortho_mode == 0:
+        assert np.allclose(lam, g["rr_values"][:2], rtol=0, atol=1e-12)
+    else:
+        assert abs(lam[0] - g["spurious_theta1"][0]) < 1e-8
+
+
+def test_largest_eigenpairs_closed_form_and_oracle(lib):
+    """Section 2's reversed ordering: the 10 largest pairs of the 32^2 Laplacian."""
+    w = P.workload(0)
+    s, info = _gpu_solve(w, largest=1)
+    assert info["converged"], info
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    ex = np.sort(cf.laplacian_2d_dirichlet(32))[::-1][: w.k]
+    assert np.max(np.abs(lam - ex) / ex) <= EIG_RTOL
+    ref = _oracle(w, largest=True)
+    assert np.max(np.abs(lam - ref.theta[: w.k]) / ref.theta[: w.k]) <= EIG_RTOL
+    assert abs(info["iterations"] - ref.iterations) <= max(2, 0.1 * ref.iterations)
+    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], 1.0) <= RESID_TOL)
+    with pytest.raises(RuntimeError, match="largest"):
+        s.adjoint(1, np.ones(1), None)
+
+
+def test_largest_eigenpairs_generalized_pencil(lib):
+    w = P.workload(2, small=True)
+    Am, Bm = w.A.to_scipy(), w.B.to_scipy()
+    s, info = _gpu_solve(w, largest=1)
+    assert info["converged"], info
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    ex = sla.eigh(Am.toarray(), Bm.toarray(), eigvals_only=True)[::-1][: w.k]
+    assert np.max(np.abs(lam - ex) / np.abs(ex)) <= EIG_RTOL
+    assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
+    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], info["norm_B_est"]) <= RESID_TOL)
+
+
 def test_literal_lq_reading_also_converges(lib):
     w = P.workload(0)
     s, info = _gpu_solve(w, lq_literal=1)
