@@ -87,7 +87,7 @@ typedef struct {
                                 implicit update) is not provided and is rejected with
                                 LOBPCG_ERR_ARG */
   int32_t lq_literal;        /* 0 = P built from the LQ of Z_1(:, n_c:n_x)^T Z_1perp; 1 = the first
-                                n_x - n_c rows of the LQ of Z_1perp (Algorithm 7, line 14) */
+                                n_x - n_c rows of the LQ of Z_1perp (Algorithm 7's P block) */
   double tau_ortho;          /* relative orthogonality tolerance of Algorithm 5; <= 0: 1e-12
                                 (FP64), 1e-5 in the FP32 phase */
   double drop_factor;        /* tau_drop = drop_factor * n_u * eps (section 4.1); <= 0: 10 */

@@ -19,7 +19,7 @@
 extern "C" {
 #endif
 
-/* Sparse times block, Y = A X (section 2 / Algorithm 8 line 17 and the products
+/* Sparse times block, Y = A X (section 2 / Algorithm 8's residual and the products
  * A W, B W of section 5.2).  CSR as in lobpcg.h with values of type dtype; X is
  * n x ncols (ldx), Y is n x ncols (ldy), Y must not alias X.  ncols may be 0. */
 int lobpcg_spmm(int64_t n, const int64_t* rowptr, const int32_t* colind, const void* values,
@@ -45,7 +45,7 @@ int lobpcg_gram(int64_t n, int32_t m, int32_t p, int32_t p1, int32_t dtype, cons
                 void* stream);
 
 /* Basis update Y = beta * Y + alpha * S C (section 5.1, eqs. 10-11 and
- * Algorithm 8 line 16).  S: n x K (lds), C: K x N FP64 COLUMN-major (ldc >= K),
+ * Algorithm 8's basis update).  S: n x K (lds), C: K x N FP64 COLUMN-major (ldc >= K),
  * rounded to dtype inside the kernel; Y: n x N (ldy).  beta must be 0 or 1;
  * Y may not alias S. */
 int lobpcg_update(int64_t n, int32_t K, int32_t N, int32_t dtype, const void* S, int64_t lds,
@@ -55,7 +55,7 @@ int lobpcg_update(int64_t n, int32_t K, int32_t N, int32_t dtype, const void* S,
 /* Bytes of workspace lobpcg_residual needs. */
 int64_t lobpcg_residual_workspace(int64_t n, int32_t nx);
 
-/* Residual and convergence test (Algorithm 8 line 17-18 and eq. 9):
+/* Residual and convergence test (Algorithm 8's residual and converged count, eq. 9):
  * R = AX - BX diag(theta) (BX may be NULL for B = I, meaning X);
  * W(:, nx-1-j) = dinv .* R(:, j) (reversed column order, section 5.1;
  * dinv NULL = identity; W may be NULL to skip);
@@ -78,9 +78,15 @@ int lobpcg_residual(int64_t n, int32_t nx, int32_t dtype, const void* AX, int64_
  * host outputs: *n_p, *flipped (1 when Cholesky was rejected: no coefficients
  * are produced), *cond (cond_1 of the scaled Cholesky factor; +inf when the
  * factorisation breaks down at a pivot that is not positive; 0 if unused).
- * tau_skip: section 5.3 threshold.  Synchronises the stream. */
+ * tau_skip: section 5.3 threshold.
+ * n_ident: 0, or the size of a leading block of GB that is exactly the identity
+ * (the X and P blocks given by eqs. (12)-(14)); the Cholesky factor of Algorithm
+ * 7 is then formed blockwise, factoring only the Schur complement of the
+ * trailing n_s - n_ident block (the same factor in exact arithmetic).
+ * Synchronises the stream. */
 int lobpcg_rr_step(int32_t n_s, int32_t n_x, int32_t n_c, int32_t use_ortho,
-                   int32_t lq_literal, const double* GA, const double* GB, int64_t ldg,
+                   int32_t lq_literal, int32_t n_ident, const double* GA, const double* GB,
+                   int64_t ldg,
                    double tau_skip, double* C, int64_t ldc, double* theta, double* theta_p,
                    int32_t* n_p, int32_t* flipped, double* cond, void* stream);
 

@@ -295,7 +295,7 @@ def rayleigh_ritz_modified(
 ) -> RRResult:
     """Algorithm 7 on the projected pencil (GA, GB) = (S^T A S, S^T B S).
 
-    Returns C_x, C_p and the block-diagonal Theta of line 14.  When the
+    Returns C_x, C_p and the block-diagonal Theta of the P block.  When the
     Cholesky factor is unreliable (reading R3) it returns flipped=True and no
     coefficients, so that the caller can orthogonalise W and call again.
 
@@ -303,7 +303,7 @@ def rayleigh_ritz_modified(
     columns after the first n_x Ritz vectors.  Reading R5 for the P block:
     LQ-factorise Z_1(:, n_c:n_x)^T Z_1perp and take C_p = T Z_perp Q^T.
     literal_lq=True takes the first n_x - n_c rows of the LQ of Z_1perp
-    instead (the literal line 14 of Algorithm 7).
+    instead (the literal reading of Algorithm 7's P block).
     """
     n_s = GA.shape[0]
     cond_R = 1.0
@@ -417,7 +417,7 @@ def lobpcg(
     exact_norms: (||A||_2, ||B||_2) to use instead of the sketch.
     force_ortho, ortho_kind: the section 6 ablation of the algorithm's
     versions.  force_ortho orthogonalises W from the first iteration and never
-    takes the Cholesky path of Algorithm 7 (lines 12-15 never fire);
+    takes the Cholesky path of Algorithm 7 (the switch to useOrtho never fires);
     ortho_kind "drop" is orthoDrop (Algorithm 5), "hl" is ortho (Algorithm 3).
     The defaults are Algorithm 8 itself.
     largest: the k largest eigenpairs instead (section 2: the Ritz values are
@@ -447,7 +447,7 @@ def lobpcg(
         normA = sketch_norm(Aop, Om)
         normB = 1.0 if Bop.is_identity else sketch_norm(Bop, Om)
 
-    # Lines 3-6: initial Rayleigh-Ritz on X0.
+    # Start: initial Rayleigh-Ritz on X0.
     AX0, BX0 = Aop(X0), Bop(X0)
     C, theta = rayleigh_ritz(X0.T @ AX0, X0.T @ BX0)
     X = X0 @ C
@@ -466,7 +466,7 @@ def lobpcg(
     converged = False
     while it < maxit:
         it += 1
-        # Lines 8-9 (with reading R2): W0 = K^-1 R on the unconverged columns.
+        # W (with reading R2): W0 = K^-1 R on the unconverged columns.
         W0 = Kinv(R[:, n_c:])
         V, MV = np.hstack([X, P]), np.hstack([BX, BP])
         if use_ortho:
@@ -474,16 +474,16 @@ def lobpcg(
         else:
             W = W0
         AW, BW = Aop(W), Bop(W)
-        # Line 10: S = [X, P, W]; every block of S^T A S and S^T B S explicit.
+        # S = [X, P, W]; every block of S^T A S and S^T B S explicit.
         S = np.hstack([X, P, W])
         AS = np.hstack([AX, AP, AW])
         BS = np.hstack([BX, BP, BW])
         GA, GB = S.T @ AS, S.T @ BS
         GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
-        # Line 11.
+        # RayleighRitzModified (Algorithm 7).
         rr = rayleigh_ritz_modified(GA, GB, n_x, n_c, use_ortho, tols, literal_lq)
         if rr.flipped:
-            # Lines 12-15: switch to orthogonalised W for good.
+            # Cholesky rejected: switch to orthogonalised W for good.
             use_ortho = True
             switch_iter = it
             W = orth(Bop, W0, V, MV, tols, ostats)
@@ -494,14 +494,14 @@ def lobpcg(
             GA, GB = S.T @ AS, S.T @ BS
             GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
             rr = rayleigh_ritz_modified(GA, GB, n_x, n_c, use_ortho, tols, literal_lq)
-        # Line 16: [X, P] = S [C_x, C_p]; products recomputed explicitly.
+        # Basis update [X, P] = S [C_x, C_p]; products recomputed explicitly.
         X, P = S @ rr.Cx, S @ rr.Cp
         AX, BX = Aop(X), Bop(X)
         AP, BP = Aop(P), Bop(P)
         theta_x = rr.theta_x
-        # Line 17.
+        # Residual.
         R = AX - BX * theta_x[None, :]
-        # Line 18 (reading R6): leading run of columns meeting criterion (9).
+        # Converged count (reading R6): leading run of columns meeting criterion (9).
         rho = criterion9(R, X, theta_x, normA, normB)
         ok = rho <= tol
         n_c = int(np.argmin(ok)) if not np.all(ok) else n_x

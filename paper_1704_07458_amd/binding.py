@@ -140,7 +140,7 @@ SIGNATURES = {
                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                   C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lobpcg_rr_step": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                 C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
+                                 C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
                                  C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_void_p]),
 }
@@ -426,8 +426,10 @@ def residual(AX, X, theta, BX=None, dinv=None, W=None, normA=1.0, normB=1.0, tol
     return rho, nc
 
 
-def rr_step(GA, GB, n_x: int, n_c: int, use_ortho: bool, tau_skip: float, literal: bool = False):
-    """Algorithm 7 on device FP64 (n_s x n_s) GA, GB; returns a dict."""
+def rr_step(GA, GB, n_x: int, n_c: int, use_ortho: bool, tau_skip: float, literal: bool = False,
+            n_ident: int = 0):
+    """Algorithm 7 on device FP64 (n_s x n_s) GA, GB; returns a dict.  n_ident: size of a
+    leading block of GB that is exactly the identity (blockwise Cholesky)."""
     import torch
 
     ns = GA.shape[0]
@@ -440,7 +442,7 @@ def rr_step(GA, GB, n_x: int, n_c: int, use_ortho: bool, tau_skip: float, litera
     fl = C.c_int32()
     cond = C.c_double()
     check(load().lobpcg_rr_step(ns, n_x, n_c, 1 if use_ortho else 0, 1 if literal else 0,
-                                _ptr(GAc), _ptr(GBc), ns, float(tau_skip), _ptr(Cm), ns,
+                                int(n_ident), _ptr(GAc), _ptr(GBc), ns, float(tau_skip), _ptr(Cm), ns,
                                 _ptr(theta), _ptr(theta_p), C.byref(np_), C.byref(fl),
                                 C.byref(cond), _stream()))
     p = int(np_.value)

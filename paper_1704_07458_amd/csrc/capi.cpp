@@ -244,16 +244,18 @@ int lobpcg_residual(int64_t n, int32_t nx, int32_t dtype, const void* AX, int64_
 }
 
 int lobpcg_rr_step(int32_t n_s, int32_t n_x, int32_t n_c, int32_t use_ortho, int32_t lq_literal,
-                   const double* GA, const double* GB, int64_t ldg, double tau_skip, double* C,
+                   int32_t n_ident, const double* GA, const double* GB, int64_t ldg,
+                   double tau_skip, double* C,
                    int64_t ldc, double* theta, double* theta_p, int32_t* n_p, int32_t* flipped,
                    double* cond, void* stream) {
   return guarded([&]() {
     LOBPCG_CHECK(n_s >= 1 && n_x >= 1 && n_x <= n_s && n_c >= 0 && n_c <= n_x && ldg >= n_s &&
-                     ldc >= n_s,
+                     ldc >= n_s && n_ident >= 0 && n_ident <= n_s,
                  LOBPCG_ERR_ARG, "lobpcg_rr_step: bad sizes");
     lobpcg::Dense d(n_s, n_x, as_stream(stream));
     lobpcg::RROutput o = d.rr_modified(GA, GB, ldg, n_s, n_x, n_c, use_ortho != 0,
-                                       lq_literal != 0, tau_skip, C, ldc, theta, theta_p, n_x);
+                                       lq_literal != 0, tau_skip, C, ldc, theta, theta_p, n_x,
+                                       false, n_ident);
     LOBPCG_HIP(hipStreamSynchronize(as_stream(stream)));
     if (n_p) *n_p = o.np;
     if (flipped) *flipped = o.flipped ? 1 : 0;

@@ -210,7 +210,7 @@ void Dense::rr_p_block(const double* Z, int ns, int nx, int nc, bool literal_lq,
         0.0, ZQ, ld);
   dgemm(h, rocblas_operation_none, rocblas_operation_none, ns, np, ns, 1.0, T, ld, ZQ, ld, 0.0,
         C + nx * ldc, ldc);
-  // Line 14: Theta_p = Q^T Theta_perp Q.
+  // Algorithm 7's Theta_p = Q^T Theta_perp Q.
   double* Qs = Qs_.as<double>();
   launch_row_scale_copy(m, np, theta + nx, Mt, ldm, Qs, ld, s);
   dgemm(h, rocblas_operation_transpose, rocblas_operation_none, np, np, m, 1.0, Mt, ldm, Qs, ld, 0.0,
@@ -221,8 +221,9 @@ void Dense::rr_p_block(const double* Z, int ns, int nx, int nc, bool literal_lq,
 RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int ns, int nx,
                             int nc, bool use_ortho, bool literal_lq, double tau_skip, double* C,
                             int64_t ldc, double* theta, double* theta_p, int64_t ldtp,
-                            bool defer_p) {
-  LOBPCG_CHECK(ns <= nsmax_ && nx <= ns && nc <= nx, LOBPCG_ERR_ARG, "rr_modified: bad sizes");
+                            bool defer_p, int n_ident) {
+  LOBPCG_CHECK(ns <= nsmax_ && nx <= ns && nc <= nx && n_ident >= 0 && n_ident <= ns,
+               LOBPCG_ERR_ARG, "rr_modified: bad sizes");
   join_p();
   RROutput out;
   const int64_t ld = nsmax_;
@@ -232,10 +233,29 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
   int32_t* dinfo = info_.as<int32_t>();
   if (!use_ortho) {
     double* R = R_.as<double>();
-    // Algorithm 7 lines 7-8: D = diag(S^T B S)^-1/2, R^T R = D S^T B S D.
+    // Algorithm 7's scaling and factor: D = diag(S^T B S)^-1/2, R^T R = D S^T B S D.
     launch_diag_scale(ns, GB, ldg, d, R, ld, true, s_);
     launch_diag_scale(ns, GA, ldg, d, H, ld, false, s_);
-    if (ns <= cholinv_max_n()) {
+    const int k = n_ident, wn = ns - n_ident;
+    int pivot_base = 0;
+    if (k > 0 && wn > 0 && wn <= cholinv_max_n()) {
+      // The leading k x k block of D S^T B S is exactly I (D is 1 there), so
+      // with K its k x w upper-right block: R = [I K; 0 R_w] where R_w^T R_w =
+      // G_w - K^T K, and R^-1 = [I, -K R_w^-1; 0, R_w^-1].  The lower-left
+      // block of R keeps K^T: only R's upper triangle is read afterwards.
+      double* K = R + (int64_t)k * ld;
+      double* Rw = K + k;
+      double* Tw = T + k + (int64_t)k * ld;
+      gemm(rocblas_operation_transpose, rocblas_operation_none, wn, wn, k, -1.0, K, ld, K, ld,
+           1.0, Rw, ld);
+      const int tok = timer_ ? timer_->start(s_) : -1;
+      launch_cholinv_upper(wn, Rw, ld, Tw, ld, dinfo, s_);
+      if (timer_) timer_->stop(tok, 8, 2.0 / 3.0 * wn * (double)wn * wn, s_);
+      launch_set_identity(ns, k, T, ld, s_);
+      gemm(rocblas_operation_none, rocblas_operation_none, k, wn, wn, -1.0, K, ld, Tw, ld, 0.0,
+           T + (int64_t)k * ld, ld);
+      pivot_base = k;
+    } else if (ns <= cholinv_max_n()) {
       // R and R^-1 from one sweep over [R^T R | I] in one workgroup.
       const int tok = timer_ ? timer_->start(s_) : -1;
       launch_cholinv_upper(ns, R, ld, T, ld, dinfo, s_);
@@ -252,18 +272,18 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
     LOBPCG_HIP(hipMemcpyAsync(hinfo_, dinfo, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipMemcpyAsync(hcond_, cond_.get(), sizeof(double), hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipStreamSynchronize(s_));
-    out.potrf_info = hinfo_[0];
+    out.potrf_info = hinfo_[0] != 0 ? hinfo_[0] + pivot_base : 0;
     out.trtri_info = hinfo_[1];
     // a factorisation that broke down has no condition number (partial factors)
     out.cond = (hinfo_[0] != 0 || hinfo_[1] != 0) ? HUGE_VAL : hcond_[0];
-    // Line 9 (section 5.3 reading): reject when cond(R)^3 tau_skip > 1.
+    // Algorithm 7's rejection test (section 5.3 reading): cond(R)^3 tau_skip > 1.
     const bool bad_factor = hinfo_[0] != 0 || hinfo_[1] != 0 || !std::isfinite(out.cond);
     const bool ill = tau_skip > 0.0 && out.cond * out.cond * out.cond * tau_skip > 1.0;
     if (bad_factor || ill) {
       out.flipped = true;
       return out;
     }
-    // Line 10: (R^-T D GA D R^-1) Z = Z Theta.
+    // The standard eigenproblem (R^-T D GA D R^-1) Z = Z Theta.
     double* T1 = T1_.as<double>();
     gemm(rocblas_operation_none, rocblas_operation_none, ns, ns, ns, 1.0, H, ld, T, ld, 0.0, T1,
          ld);
@@ -271,10 +291,10 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
          H, ld);
     launch_symmetrize(ns, H, ld, s_);
     syev(ns, H, ld, theta);
-    // T = D R^-1 (line 12).
+    // T = D R^-1, the map from Z to coefficients of S.
     launch_row_scale(ns, ns, d, T, ld, s_);
   } else {
-    // Line 3: S is B-orthonormal, solve (S^T A S) Z = Z Theta directly.
+    // With useOrtho S is B-orthonormal: solve (S^T A S) Z = Z Theta directly.
     copy_cm(ns, ns, GA, ldg, H, ld, s_);
     launch_symmetrize(ns, H, ld, s_);
     syev(ns, H, ld, theta);
@@ -286,7 +306,7 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
   const int np = std::min(na, m);
   out.np = np;
   if (np > 0 && defer_p) {
-    // Lines 13-14 on the second stream: the LQ operand is formed first, so that
+    // The P block (LQ, C_p, Theta_p) on the second stream: the LQ operand is formed first, so that
     // the one-workgroup QR is queued before the main stream's next all-CU work.
     p_operand(Z, ld, ns, nx, nc, literal_lq, Mt_.as<double>(), ld, h_);
     LOBPCG_HIP(hipEventRecord(ev_z_, s_));

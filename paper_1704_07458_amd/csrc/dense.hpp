@@ -38,9 +38,14 @@ class Dense {
   // defer_p: the P block (the QR of Alg. 7's LQ operand, C_p, Theta_p) is left
   // running on the second stream; C_x is complete on the main stream when the
   // call returns, C_p and Theta_p only after join_p().
+  //
+  // n_ident: the leading n_ident x n_ident block of GB is exactly the identity
+  // (the X and P blocks of eqs. (12)-(14)); the Cholesky factor is then formed
+  // blockwise and only the Schur complement of the W block is factored.
   RROutput rr_modified(const double* GA, const double* GB, int64_t ldg, int ns, int nx, int nc,
                        bool use_ortho, bool literal_lq, double tau_skip, double* C, int64_t ldc,
-                       double* theta, double* theta_p, int64_t ldtp, bool defer_p = false);
+                       double* theta, double* theta_p, int64_t ldtp, bool defer_p = false,
+                       int n_ident = 0);
 
   // Orders the main stream after the deferred P block (no-op when none).
   void join_p();

@@ -323,14 +323,14 @@ int Solver::ortho_drop(Blocks<T>& b, const DevCsr* B, T* U, int64_t ldu, int nu,
   };
   double u_norm = 0.0;
   for (int i = 0; i < 3 && nu > 0; ++i) {
-    // Line 4: U = U - V (V^T M U) (block classical Gram-Schmidt).
+    // Outer pass: U = U - V (V^T M U) (block classical Gram-Schmidt).
     if (nv > 0) {
       gram<T>(n_, nv, nu, nu, MV, ldmv, U, ldu, nullptr, 0, Gv, 0, nullptr, 0, ldg, 0);
       update<T>(n_, nv, nu, V, ldv, Gv, ldg, -1.0, 1.0, U, ldu);
     }
     gram_u();
     for (int j = 0; j < 3 && nu > 0; ++j) {
-      // Lines 6-10: svqb on the first pass, svqbDrop afterwards (Algorithm 3,
+      // Inner passes: svqb on the first, svqbDrop afterwards (Algorithm 3,
       // ortho_mode 1: svqb on every pass, nothing dropped).
       const bool drop = j > 0 && opt_.ortho_mode == 0;
       const double factor = drop ? (opt_.drop_factor > 0 ? opt_.drop_factor : 10.0)
@@ -342,7 +342,7 @@ int Solver::ortho_drop(Blocks<T>& b, const DevCsr* B, T* U, int64_t ldu, int nu,
       update<T>(n_, nu, keep, U, ldu, Tu, nu, 1.0, 0.0, U2, ldX_);
       launch_copy2d<T, T>(n_, keep, U2, ldX_, U, ldu, s_);
       nu = keep;
-      // Line 11: ||U^T M U - I|| / (||MU|| ||U||) with MU recomputed.
+      // Inner test: ||U^T M U - I|| / (||MU|| ||U||) with MU recomputed.
       gram_u();
       launch_fro_minus_identity(nu, G, ldg, nrm + 4 * nx_, s_);
       launch_colsq<T>(n_, nu, U, ldu, nrm, work_.get(), s_);
@@ -357,7 +357,7 @@ int Solver::ortho_drop(Blocks<T>& b, const DevCsr* B, T* U, int64_t ldu, int nu,
       if (err <= tau_ortho) break;
     }
     if (nv == 0 || nu == 0) break;
-    // Line 12: ||V^T M U|| / (||MV|| ||U||).
+    // Outer test: ||V^T M U|| / (||MV|| ||U||).
     gram<T>(n_, nv, nu, nu, MV, ldmv, U, ldu, nullptr, 0, Gv, 0, nullptr, 0, ldg, 0);
     launch_fro(nv, nu, Gv, ldg, nrm + 4 * nx_, s_);
     LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx_, sizeof(double), hipMemcpyDeviceToHost, s_));
@@ -393,7 +393,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   int cur = 0;
   *iters_out = 0;
 
-  // Algorithm 8 lines 3-4: Rayleigh-Ritz on X0 (Algorithm 2), X = X0 C.
+  // Algorithm 8's start: Rayleigh-Ritz on X0 (Algorithm 2), X = X0 C.
   phase_mark(7);
   T* S0 = b.S[0].template as<T>();
   launch_copy2d<double, T>(n, nx, X0dev, nx, S0, ldS, s_);
@@ -415,7 +415,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   T* S1 = b.S[1].template as<T>();
   update<T>(n, nx, nx, S0, ldS, C, ldc, 1.0, 0.0, S1, ldS);
   cur = 1;
-  // Line 5: R = AX - BX Theta; W = K^-1 R stored reversed after X (P is empty).
+  // First residual R = AX - BX Theta; W = K^-1 R stored reversed after X (P is empty).
   phase_mark(0);
   spmm<T>(A, S1, ldS, AX, ldX, nx);
   if (B) spmm<T>(*B, S1, ldS, BXP, ldBXP, nx);
@@ -424,7 +424,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   launch_residual<T>(n, nx, AX, ldX, B ? BXP : nullptr, ldBXP, S1, ldS, theta, dinv,
                      use_cb ? Rb : S1 + nx, use_cb ? ldX : ldS, normA_, normB_, tol,
                      rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
-  // line 6 (useOrtho = false), or true from the start in the versions of
+  // useOrtho starts false, or true from the start in the versions of
   // section 6 that orthogonalise every iteration
   bool use_ortho = opt_.force_ortho != 0;
   int rc = LOBPCG_NOT_CONVERGED;
@@ -435,7 +435,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     const int nv = nx + np;
     T* W = Sc + nv;
     int nw = nx - nc;
-    // Lines 8-9 with the preconditioner applied to R (W0 = K^-1 R).
+    // W from the residual with the preconditioner applied (W0 = K^-1 R).
     if (use_cb) {
       phase_mark(1);
       const int st = K(Kuser, n, nw, sizeof(T) == 8 ? 0 : 1, Rb, ldX, W, ldS, (void*)s_);
@@ -472,17 +472,18 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
           gram<T>(n, nv, nv, nv, Sc, ldS, B ? BXP : Sc, B ? ldBXP : ldS, nullptr, 0, GB, 0,
                   nullptr, 0, ldg, 0);
       }
-      // Line 11: RayleighRitzModified; its P block is left running on the second
+      // RayleighRitzModified (Algorithm 7); its P block is left running on the second
       // stream beside the X update, A X and the residual, which do not touch P.
       phase_mark(4);
       {
         const int tok = timer_.start(s_);
+        // with the implicit blocks the X/P block of S^T B S is exactly I
         o = dense_->rr_modified(GA, GB, ldg, ns, nx, nc, use_ortho, lq_literal, tau_skip, C, ldc,
-                                theta, theta_p, nx, true);
+                                theta, theta_p, nx, true, opt_.implicit_gram ? nv : 0);
         timer_.stop(tok, 4, 0.0, s_);
       }
       if (!o.flipped) break;
-      // Lines 12-15: switch to orthogonalised W for good and redo the step.
+      // Cholesky rejected: switch to orthogonalised W for good and redo the step.
       use_ortho = true;
       if (info) {
         info->flips++;
@@ -494,11 +495,11 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     if (o.flipped) throw Error(LOBPCG_ERR_BREAKDOWN, "Rayleigh-Ritz failed after orthoDrop");
     const int ns = nv + nw;
     const int npn = o.np;
-    // Line 16: [X, P] = S [C_x, C_p]: X now, P once the P block is done.
+    // Basis update [X, P] = S [C_x, C_p]: X now, P once the P block is done.
     phase_mark(5);
     update<T>(n, ns, nx, Sc, ldS, C, ldc, 1.0, 0.0, Sn, ldS);
     cur ^= 1;
-    // Line 17: R = AX - BX Theta with A X recomputed (explicit products).
+    // Residual R = AX - BX Theta with A X recomputed (explicit products).
     phase_mark(0);
     spmm<T>(A, Sn, ldS, AX, ldX, nx);
     if (B) spmm<T>(*B, Sn, ldS, BXP, ldBXP, nx);
@@ -510,7 +511,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
                          rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
       timer_.stop(tok, 3, (double)n * nx * sizeof(T) * (B ? 4 : 3) + (dinv ? 8.0 * n : 0.0), s_);
     }
-    // Line 18: number of converged pairs (leading run meeting criterion 9); the
+    // Number of converged pairs (leading run meeting criterion 9); the
     // host waits for this copy only, the P update runs on meanwhile.
     LOBPCG_HIP(hipMemcpyAsync(hbuf_, nc_.get(), sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipEventRecord(ev_nc_, s_));

@@ -315,6 +315,68 @@ def test_rr_step_cholesky_breakdown_in_a_late_panel(lib):
     assert got["flipped"]
 
 
+def _identity_block_gram(seed, n, n_s, k, dependent=False):
+    """S = [Q, W] with Q orthonormal (k columns) and the X/P block of S^T S set
+    to the identity exactly, as eqs. (12)-(14) fill it in the solver."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    W = rng.standard_normal((n, n_s - k)) * np.exp(rng.uniform(-2, 2, n_s - k))
+    if dependent:
+        W[:, 3] = Q[:, 1]  # a W column inside span(Q): singular Schur complement
+    S = np.hstack([Q, W])
+    A = P.random_sparse_spd(17, n, min(1.0, 20.0 / n)).to_scipy()
+    GA, GB = S.T @ (A @ S), S.T @ S
+    GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+    GB[:k, :k] = np.eye(k)
+    return GA, GB
+
+
+@pytest.mark.parametrize("n_s,k,n_x,n_c", [(25, 18, 9, 0), (330, 220, 110, 0), (330, 200, 110, 20),
+                                           (660, 440, 220, 0), (97, 64, 40, 5)])
+def test_rr_step_identity_leading_block(lib, n_s, k, n_x, n_c):
+    """Algorithm 7 with the blockwise Cholesky (leading block of S^T B S exactly I)
+    against the oracle's full Cholesky of the same matrix: Ritz values, C_x up to
+    column signs and cond_1(R) = |R|_1 |R^-1|_1, which needs every block of R and
+    R^-1.  n_s = 660 factors a 220-wide Schur complement in the one-workgroup kernel."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    n = max(3 * n_s, 400)
+    GA, GB = _identity_block_gram(100 + n_s, n, n_s, k)
+    tol = L.Tolerances()
+    ref = L.rayleigh_ritz_modified(GA, GB, n_x, n_c, False, tol)
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), n_x, n_c, False,
+                    tol.tau_skip, n_ident=k)
+    assert not got["flipped"] and not ref.flipped
+    assert got["cond"] == pytest.approx(ref.cond_R, rel=1e-9)
+    th = got["theta"].cpu().numpy()
+    assert np.allclose(th, ref.theta_all, rtol=1e-10, atol=1e-12 * np.abs(th).max())
+    # C_x columns of well-separated Ritz values are unique up to sign
+    g = np.abs(np.diff(ref.theta_all))
+    thr = 1e-6 * np.abs(ref.theta_all).max()
+    sep = (np.r_[np.inf, g[: n_x - 1]] > thr) & (g[:n_x] > thr)
+    Cx = got["Cx"].cpu().numpy()
+    _signs_match(Cx[:, sep], ref.Cx[:, sep], 1e-7)
+    plain = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), n_x, n_c, False,
+                      tol.tau_skip) if n_s <= 512 else None
+    if plain is not None:
+        assert plain["cond"] == pytest.approx(got["cond"], rel=1e-9)
+
+
+def test_rr_step_identity_leading_block_singular_schur(lib):
+    """A W column inside span(X, P): the Schur complement is singular and the step
+    must ask for the orthonormalised basis, as with the full factorisation."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    GA, GB = _identity_block_gram(7, 600, 60, 40, dependent=True)
+    tol = L.Tolerances()
+    ref = L.rayleigh_ritz_modified(GA, GB, 20, 0, False, tol)
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), 20, 0, False,
+                    tol.tau_skip, n_ident=40)
+    assert ref.flipped and got["flipped"]
+
+
 @pytest.mark.parametrize("n_s,use_ortho", [(330, False), (330, True), (600, False)])
 def test_rr_step_full_size_with_clustered_spectrum(lib, n_s, use_ortho):
     """The projected problem at the bench's size (n_s = 3 n_x = 330) and above.
