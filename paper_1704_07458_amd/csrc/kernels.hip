@@ -985,6 +985,7 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
   __shared__ double pp[2 * kTrdThreads];   // partial products per column group
   __shared__ double yv[2 * kTrdNb];        // W^T v, V^T v
   __shared__ double redA[kTrdThreads / kWave], redB[kTrdThreads / kWave];
+  __shared__ double pdet[3][kTrdNb];       // the panel's d, e (beta), tau, stored at its end
   const int t = threadIdx.x;
   const int lane = t % kWave, wave = t / kWave;
   constexpr int nwaves = kTrdThreads / kWave;
@@ -1004,6 +1005,8 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
         const int r = i + t;
         if (r < n) {
           double a = have_pre ? pre : col[r];
+          // unrolled so that the LDS loads of several reflectors are in flight
+#pragma unroll 4
           for (int k = 0; k < j; ++k)
             a -= V[k * kTrdMaxN + r] * W[k * kTrdMaxN + i] + W[k * kTrdMaxN + r] * V[k * kTrdMaxN + i];
           cv[r] = a;
@@ -1019,21 +1022,23 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
         taui = (beta - alpha) / beta;
         scal = 1.0 / (alpha - beta);
       }
-      if (t == 0) {
-        d[i] = cv[i];
-        e[i] = beta;
-        tau[i] = taui;
-      }
-      for (int r = i0 + t; r < n; r += kTrdThreads) {
-        double vr = 0.0;
-        if (r == i + 1) {
-          vr = 1.0;
-          col[r] = beta;
-        } else if (r >= i + 2) {
-          vr = cv[r] * scal;
-          col[r] = vr;
+      // n <= kTrdThreads: thread t owns row i0 + t of the reflector.  The
+      // reflector and d, e, tau reach global memory only at the panel's end (a
+      // barrier waits for outstanding stores; there they overlap the update).
+      const int rv = i0 + t;
+      double vst = 0.0;
+      if (rv < n) {
+        if (rv == i + 1) {
+          vst = 1.0;
+        } else if (rv >= i + 2) {
+          vst = cv[rv] * scal;
         }
-        V[j * kTrdMaxN + r] = vr;
+        V[j * kTrdMaxN + rv] = vst;
+      }
+      if (t == 0) {
+        pdet[0][j] = cv[i];
+        pdet[1][j] = beta;
+        pdet[2][j] = taui;
       }
       __syncthreads();
       // (c) y1 = W^T v, y2 = V^T v over the panel's earlier columns (one wave
@@ -1113,7 +1118,9 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
       for (int r = i + 1 + t; r < n; r += kTrdThreads) {
         const int rr = r - rb;
         double pr = 0.0;
+#pragma unroll 4
         for (int q = 0; q < groups; ++q) pr += pp[q * rows_pass + rr];
+#pragma unroll 4
         for (int k = 0; k < j; ++k)
           pr -= V[k * kTrdMaxN + r] * yv[k] + W[k * kTrdMaxN + r] * yv[j + k];
         pr *= taui;
@@ -1126,41 +1133,60 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
         W[j * kTrdMaxN + r] = r >= i + 1 ? fma(alpha2, vj[r], W[j * kTrdMaxN + r]) : 0.0;
       __syncthreads();
     }
-    // (e) A(c0:n, c0:n) -= V W^T + W V^T, both triangles, 4 x 4 tiles per thread.
-    const int c0 = i0 + nbp;
-    const int mt = n - c0;
-    const int ntr = (mt + 3) / 4;
-    for (int q = t; q < ntr * ntr; q += kTrdThreads) {
-      const int r0 = c0 + 4 * (q % ntr), cc0 = c0 + 4 * (q / ntr);
-      // the tile's entries are loaded first; their latency hides behind the sums
-      double acc[4][4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-          acc[a][b] = (cc0 + b < n && r0 + a < n) ? A[(int64_t)(cc0 + b) * lda + r0 + a] : 0.0;
+    // (e) A(c0:n, c0:n) -= V W^T + W V^T = -[V W] [W V]^T on MFMA
+    // (v_mfma_f64_16x16x4f64, K = 2 nbp in 4-deep slices): one wave per 16 x 16
+    // tile of the lower triangle; an off-diagonal tile is stored at both of its
+    // symmetric positions, so the matrix stays exactly symmetric there.
+    {
+      // the panel's reflectors (v below the subdiagonal, beta on it) and d, e, tau
+      if (t < nbp) {
+        d[i0 + t] = pdet[0][t];
+        e[i0 + t] = pdet[1][t];
+        tau[i0 + t] = pdet[2][t];
+      }
       for (int k = 0; k < nbp; ++k) {
-        double vr[4], wr[4], vc[4], wc[4];
+        const int r = i0 + t;  // rows i0 + k + 1 .. n - 1 of column i0 + k
+        if (r >= i0 + k + 1 && r < n)
+          A[(int64_t)(i0 + k) * lda + r] = r == i0 + k + 1 ? pdet[1][k] : V[k * kTrdMaxN + r];
+      }
+      const int c0 = i0 + nbp;
+      const int ntl = (n - c0 + 15) / 16;
+      const int kk = 2 * nbp;
+      const int li = lane % 16, lq = lane / 16;
+      for (int tix = wave; tix < ntl * (ntl + 1) / 2; tix += nwaves) {
+        // tile (tr, tc), tr >= tc, from its index in the packed lower triangle
+        int tr = (int)((sqrtf(8.0f * (float)tix + 1.0f) - 1.0f) * 0.5f);
+        while ((tr + 1) * (tr + 2) / 2 <= tix) ++tr;
+        while (tr * (tr + 1) / 2 > tix) --tr;
+        const int tc = tix - tr * (tr + 1) / 2;
+        const int R0 = c0 + 16 * tr, C0 = c0 + 16 * tc;
+        // accumulator layout: element q of lane l is (R0 + l/16 + 4q, C0 + l%16)
+        const int cd = C0 + li;
+        v4d acc;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const bool okr = r0 + a < n, okc = cc0 + a < n;
-          vr[a] = okr ? V[k * kTrdMaxN + r0 + a] : 0.0;
-          wr[a] = okr ? W[k * kTrdMaxN + r0 + a] : 0.0;
-          vc[a] = okc ? V[k * kTrdMaxN + cc0 + a] : 0.0;
-          wc[a] = okc ? W[k * kTrdMaxN + cc0 + a] : 0.0;
+        for (int q = 0; q < 4; ++q) {
+          const int rd = R0 + lq + 4 * q;
+          acc[q] = (rd < n && cd < n) ? A[(int64_t)cd * lda + rd] : 0.0;
+        }
+        // operands: A(row R0 + l%16, k = 4s + l/16), B(k = 4s + l/16, column C0 + l%16)
+        const int ra = R0 + li;
+        for (int s4 = 0; s4 < (kk + 3) / 4; ++s4) {  // wave-uniform trip count
+          const int k = 4 * s4 + lq;
+          double a = 0.0, b = 0.0;
+          if (k < kk) {
+            if (ra < n) a = -(k < nbp ? V[k * kTrdMaxN + ra] : W[(k - nbp) * kTrdMaxN + ra]);
+            if (cd < n) b = k < nbp ? W[k * kTrdMaxN + cd] : V[(k - nbp) * kTrdMaxN + cd];
+          }
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = fma(-vr[a], wc[b], fma(-wr[a], vc[b], acc[a][b]));
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if (cc0 + b >= n) continue;
-        double* ac = A + (int64_t)(cc0 + b) * lda;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-          if (r0 + a < n) ac[r0 + a] = acc[a][b];
+        for (int q = 0; q < 4; ++q) {
+          const int rd = R0 + lq + 4 * q;
+          if (rd < n && cd < n) {
+            A[(int64_t)cd * lda + rd] = acc[q];
+            if (tr != tc) A[(int64_t)rd * lda + cd] = acc[q];
+          }
+        }
       }
     }
     __syncthreads();
