@@ -407,6 +407,7 @@ def lobpcg(
     force_ortho: bool = False,
     ortho_kind: str = "drop",
     largest: bool = False,
+    implicit_products: bool = False,
 ) -> LobpcgResult:
     """Algorithm 8: the robust and efficient LOBPCG of the paper, FP64.
 
@@ -425,7 +426,12 @@ def lobpcg(
     them in ascending order for -A, so the iteration runs on (-A, B) and the
     Ritz values are negated on return; precond must then approximate the
     inverse of (-A) shifted, as for any pencil.
+    implicit_products: section 5.2's implicit updates A X = (A S) C_x and
+    A P = (A S) C_p after the basis update instead of recomputing the products
+    (B = I only: the paper restricts them to that case).
     """
+    if implicit_products and B is not None:
+        raise ValueError("implicit product updates need B = I")
     if ortho_kind not in ("drop", "hl"):
         raise ValueError("ortho_kind must be 'drop' or 'hl'")
     orth = ortho_drop if ortho_kind == "drop" else ortho
@@ -494,10 +500,15 @@ def lobpcg(
             GA, GB = S.T @ AS, S.T @ BS
             GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
             rr = rayleigh_ritz_modified(GA, GB, n_x, n_c, use_ortho, tols, literal_lq)
-        # Basis update [X, P] = S [C_x, C_p]; products recomputed explicitly.
+        # Basis update [X, P] = S [C_x, C_p]; products recomputed explicitly, or
+        # updated implicitly from A S (section 5.2).
         X, P = S @ rr.Cx, S @ rr.Cp
-        AX, BX = Aop(X), Bop(X)
-        AP, BP = Aop(P), Bop(P)
+        if implicit_products:
+            AX, AP = AS @ rr.Cx, AS @ rr.Cp
+            BX, BP = X, P
+        else:
+            AX, BX = Aop(X), Bop(X)
+            AP, BP = Aop(P), Bop(P)
         theta_x = rr.theta_x
         # Residual.
         R = AX - BX * theta_x[None, :]

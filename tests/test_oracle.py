@@ -459,6 +459,34 @@ def test_largest_eigenpairs_of_random_pencil_brute_force():
     assert np.max(np.abs(res.theta[:6] - top) / np.abs(top)) < 1e-9
 
 
+# ------------------------------------- section 5.2: implicit product updates
+@pytest.mark.parametrize("idx", [0, 1])
+def test_implicit_product_updates_reach_closed_form(idx):
+    """A X = (A S) C_x and A P = (A S) C_p instead of sparse products: the
+    iteration still meets criterion (9) with the true residual, and the drift of
+    the implicit products (section 5.2: of order eps ||A|| ||X|| ||C||) leaves the
+    computed and the true criterion equal to well below the tolerance."""
+    w = P.workload(idx, small=idx != 0)
+    res = _solve(w, implicit_products=True)
+    assert res.converged
+    if idx == 0:
+        ex = cf.smallest(cf.laplacian_2d_dirichlet(32), w.k)
+    else:
+        ex = cf.smallest(cf.laplacian_3d_dirichlet(12), w.k)
+    assert np.max(np.abs(res.theta[: w.k] - ex) / ex) < 1e-10
+    A = w.A.to_scipy()
+    X, th = res.X, res.theta
+    rho_true = L.criterion9(A @ X - X * th, X, th, res.normA, 1.0)
+    assert np.all(rho_true[: w.k] <= w.tol)
+    assert np.max(np.abs(rho_true - res.rho)) < 1e-11
+
+
+def test_implicit_product_updates_need_identity_B():
+    w = P.workload(2, small=True)
+    with pytest.raises(ValueError):
+        _solve(w, implicit_products=True, maxit=1)
+
+
 def test_maxit_returns_not_converged():
     w = P.workload(0)
     res = _solve(w, maxit=3)
