@@ -102,14 +102,25 @@ def cpu_baseline(w, iters, gpu_iters):
 
 # Versions of section 6 (Fig. 2) that this solver can run: every X/P Gram block
 # explicit and W orthogonalised on every iteration with Algorithm 3 (version 2,
-# the conservative Hetmaniuk-Lehoucq type), then with orthoDrop (version 5),
-# then skipping orthogonalisation until Algorithm 7 rejects the Cholesky path
-# (version 6), then the X/P blocks from eqs. (12)-(14) (version 7, Algorithm 8).
+# the conservative Hetmaniuk-Lehoucq type); plus the implicit product updates of
+# section 5.2 (version 4, the aggressive type); then orthoDrop (version 5), then
+# skipping orthogonalisation until Algorithm 7 rejects the Cholesky path
+# (version 6), then the X/P blocks from eqs. (12)-(14) (version 7, Algorithm 8
+# as printed); and Algorithm 8 with A X recomputed by the sparse product, this
+# solver's default.
 ABLATION = [
-    ("v2_hl_ortho", 2, {"force_ortho": 1, "ortho_mode": 1, "implicit_gram": 0}),
-    ("v5_orthodrop", 5, {"force_ortho": 1, "ortho_mode": 0, "implicit_gram": 0}),
-    ("v6_skip_ortho", 6, {"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 0}),
-    ("v7_algorithm8", 7, {"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 1}),
+    ("v2_hl_ortho", 2, {"force_ortho": 1, "ortho_mode": 1, "implicit_gram": 0,
+                        "implicit_products": 0}),
+    ("v4_hl_ortho_implicit_products", 4, {"force_ortho": 1, "ortho_mode": 1, "implicit_gram": 0,
+                                          "implicit_products": 1}),
+    ("v5_orthodrop", 5, {"force_ortho": 1, "ortho_mode": 0, "implicit_gram": 0,
+                         "implicit_products": 1}),
+    ("v6_skip_ortho", 6, {"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 0,
+                          "implicit_products": 1}),
+    ("v7_algorithm8", 7, {"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 1,
+                          "implicit_products": 1}),
+    ("v7_algorithm8_spmm_products", 7, {"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 1,
+                                        "implicit_products": 0}),
 ]
 
 

@@ -82,10 +82,12 @@ typedef struct {
   int32_t precond;           /* 0 = none (K = I); 1 = Jacobi (diagonal of A, shifted to be
                                 positive when it is not); 2 = the solve's callback */
   int32_t implicit_products; /* -1 (automatic) or 0: A X (and B X) are recomputed with the
-                                sparse product after each update; on this GPU that costs less
-                                than the implicit update A X = (A S) C_x of section 5.2.  1 (the
-                                implicit update) is not provided and is rejected with
-                                LOBPCG_ERR_ARG */
+                                sparse product after each update (on this GPU one SpMM costs
+                                about half of an n x n_s by n_s x n_x product); 1: the implicit
+                                updates A X = (A S) C_x, A P = (A S) C_p of section 5.2, which
+                                keep A S = [A X, A P, A W] (two more n x n_s blocks of memory).
+                                1 needs B = I (section 5.2: with B != I the updates are not
+                                safe), else LOBPCG_ERR_ARG */
   int32_t lq_literal;        /* 0 = P built from the LQ of Z_1(:, n_c:n_x)^T Z_1perp; 1 = the first
                                 n_x - n_c rows of the LQ of Z_1perp (Algorithm 7's P block) */
   double tau_ortho;          /* relative orthogonality tolerance of Algorithm 5; <= 0: 1e-12

@@ -100,7 +100,7 @@ void upload_csr(DevCsr& D, const std::vector<int64_t>& rp, const std::vector<int
 }  // namespace
 
 template <typename T>
-void Blocks<T>::alloc(int64_t n, int64_t ldS, int64_t ldX, bool haveB) {
+void Blocks<T>::alloc(int64_t n, int64_t ldS, int64_t ldX, bool haveB, bool implicit_products) {
   const size_t e = sizeof(T);
   S[0].alloc(e * n * ldS);
   S[1].alloc(e * n * ldS);
@@ -112,6 +112,10 @@ void Blocks<T>::alloc(int64_t n, int64_t ldS, int64_t ldX, bool haveB) {
     BXP.alloc(e * n * 2 * ldX);
     BW.alloc(e * n * ldX);
     MU.alloc(e * n * ldX);
+  }
+  if (implicit_products) {
+    AS[0].alloc(e * n * ldS);
+    AS[1].alloc(e * n * ldS);
   }
 }
 
@@ -128,9 +132,11 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   nx_ = opt.block_size > 0 ? opt.block_size : k + (k + 9) / 10;
   LOBPCG_CHECK(nx_ >= k, LOBPCG_ERR_ARG, "block_size must be >= k");
   LOBPCG_CHECK(3 * (int64_t)nx_ <= n_, LOBPCG_ERR_ARG, "need 3 * block_size <= n");
-  LOBPCG_CHECK(opt.implicit_products <= 0, LOBPCG_ERR_ARG,
-               "implicit product updates (implicit_products = 1) are not provided: A X is "
-               "recomputed with the sparse product");
+  LOBPCG_CHECK(opt.implicit_products >= -1 && opt.implicit_products <= 1, LOBPCG_ERR_ARG,
+               "implicit_products must be -1, 0 or 1");
+  LOBPCG_CHECK(opt.implicit_products != 1 || B == nullptr, LOBPCG_ERR_ARG,
+               "implicit product updates need B = I (section 5.2: with B != I the updates "
+               "are not safe)");
   LOBPCG_CHECK(opt.ortho_mode == 0 || opt.ortho_mode == 1, LOBPCG_ERR_ARG,
                "ortho_mode must be 0 (orthoDrop) or 1 (ortho)");
   LOBPCG_CHECK(opt.largest == 0 || opt.largest == 1, LOBPCG_ERR_ARG, "largest must be 0/1");
@@ -153,8 +159,9 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   nsmax_ = 3 * nx_;
   ldS_ = round_up(nsmax_, 16);
   ldX_ = round_up(nx_, 16);
-  b64_.alloc(n_, ldS_, ldX_, haveB_);
-  if (split) b32_.alloc(n_, ldS_, ldX_, haveB_);
+  const bool impl = opt.implicit_products == 1;
+  b64_.alloc(n_, ldS_, ldX_, haveB_, impl);
+  if (split) b32_.alloc(n_, ldS_, ldX_, haveB_, impl);
   const size_t sq = sizeof(double) * (size_t)nsmax_ * nsmax_;
   GA_.alloc(sq);
   GB_.alloc(sq);
@@ -385,7 +392,13 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   double* C = C_.as<double>();
   double* theta = theta_.as<double>();
   double* theta_p = theta_p_.as<double>();
+  // With implicit product updates (section 5.2, B = I) A X, A P and A W live in
+  // AS[cur] with the column layout of S and A X, A P follow the basis update
+  // (A S C); otherwise A X is recomputed with the sparse product.
+  const bool impl = opt_.implicit_products == 1;
+  auto ASp = [&](int which) -> T* { return b.AS[which].template as<T>(); };
   T* AX = b.AX.template as<T>();
+  int64_t ldAX = ldX;
   T* AW = b.AW.template as<T>();
   T* BXP = B ? b.BXP.template as<T>() : nullptr;
   T* BW = B ? b.BW.template as<T>() : nullptr;
@@ -417,11 +430,15 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   cur = 1;
   // First residual R = AX - BX Theta; W = K^-1 R stored reversed after X (P is empty).
   phase_mark(0);
-  spmm<T>(A, S1, ldS, AX, ldX, nx);
+  if (impl) {
+    AX = ASp(cur);
+    ldAX = ldS;
+  }
+  spmm<T>(A, S1, ldS, AX, ldAX, nx);
   if (B) spmm<T>(*B, S1, ldS, BXP, ldBXP, nx);
   phase_mark(6);
   int np = 0, nc = 0;
-  launch_residual<T>(n, nx, AX, ldX, B ? BXP : nullptr, ldBXP, S1, ldS, theta, dinv,
+  launch_residual<T>(n, nx, AX, ldAX, B ? BXP : nullptr, ldBXP, S1, ldS, theta, dinv,
                      use_cb ? Rb : S1 + nx, use_cb ? ldX : ldS, normA_, normB_, tol,
                      rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
   // useOrtho starts false, or true from the start in the versions of
@@ -435,6 +452,8 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     const int nv = nx + np;
     T* W = Sc + nv;
     int nw = nx - nc;
+    T* AWc = impl ? ASp(cur) + nv : AW;
+    const int64_t ldAW = impl ? ldS : ldX;
     // W from the residual with the preconditioner applied (W0 = K^-1 R).
     if (use_cb) {
       phase_mark(1);
@@ -452,22 +471,24 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       const int ns = nv + nw;
       // A W and B W (explicit: every block involving W is computed, section 5.2).
       phase_mark(0);
-      spmm<T>(A, W, ldS, AW, ldX, nw);
+      spmm<T>(A, W, ldS, AWc, ldAW, nw);
       if (B) spmm<T>(*B, W, ldS, BW, ldX, nw);
       // Gram columns of W in S^T A S and S^T B S; the rest from eqs. (12)-(14).
       phase_mark(3);
-      gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AW, ldX, B ? BW : W,
+      gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AWc, ldAW, B ? BW : W,
               B ? ldX : ldS, GA, nv, GB, nv, ldg, nv);
       if (opt_.implicit_gram) {
         launch_fill_implicit(nx, np, theta, theta_p, nx, GA, use_ortho ? nullptr : GB, ldg, s_);
       } else {
         // The X and P blocks computed explicitly: [X P]^T [AX AP] and
-        // [X P]^T [BX BP] (or [X P]^T [X P]); A P goes through the ortho buffer.
-        T* AP = b.U2.template as<T>();
+        // [X P]^T [BX BP] (or [X P]^T [X P]); A P from the implicit update, or
+        // by the sparse product through the ortho buffer.
+        T* AP = impl ? ASp(cur) + nx : b.U2.template as<T>();
+        const int64_t ldAP = impl ? ldS : ldX;
         phase_mark(0);
-        if (np > 0) spmm<T>(A, Sc + nx, ldS, AP, ldX, np);
+        if (np > 0 && !impl) spmm<T>(A, Sc + nx, ldS, AP, ldAP, np);
         phase_mark(3);
-        gram<T>(n, nv, nv, nx, Sc, ldS, AX, ldX, AP, ldX, GA, 0, GA, nx, ldg, 0);
+        gram<T>(n, nv, nv, nx, Sc, ldS, AX, ldAX, AP, ldAP, GA, 0, GA, nx, ldg, 0);
         if (!use_ortho)
           gram<T>(n, nv, nv, nv, Sc, ldS, B ? BXP : Sc, B ? ldBXP : ldS, nullptr, 0, GB, 0,
                   nullptr, 0, ldg, 0);
@@ -498,15 +519,22 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     // Basis update [X, P] = S [C_x, C_p]: X now, P once the P block is done.
     phase_mark(5);
     update<T>(n, ns, nx, Sc, ldS, C, ldc, 1.0, 0.0, Sn, ldS);
+    T* ASo = impl ? ASp(cur) : nullptr;
     cur ^= 1;
-    // Residual R = AX - BX Theta with A X recomputed (explicit products).
-    phase_mark(0);
-    spmm<T>(A, Sn, ldS, AX, ldX, nx);
+    // Residual R = AX - BX Theta with A X recomputed by the sparse product, or
+    // updated implicitly as A X = (A S) C_x (section 5.2).
+    if (impl) {
+      AX = ASp(cur);
+      update<T>(n, ns, nx, ASo, ldS, C, ldc, 1.0, 0.0, AX, ldS);
+    } else {
+      phase_mark(0);
+      spmm<T>(A, Sn, ldS, AX, ldX, nx);
+    }
     if (B) spmm<T>(*B, Sn, ldS, BXP, ldBXP, nx);
     phase_mark(6);
     {
       const int tok = timer_.start(s_);
-      launch_residual<T>(n, nx, AX, ldX, B ? BXP : nullptr, ldBXP, Sn, ldS, theta, dinv,
+      launch_residual<T>(n, nx, AX, ldAX, B ? BXP : nullptr, ldBXP, Sn, ldS, theta, dinv,
                          use_cb ? Rb : Sn + nx + npn, use_cb ? ldX : ldS, normA_, normB_, tol,
                          rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
       timer_.stop(tok, 3, (double)n * nx * sizeof(T) * (B ? 4 : 3) + (dinv ? 8.0 * n : 0.0), s_);
@@ -519,6 +547,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     phase_mark(5);
     if (npn > 0) {
       update<T>(n, ns, npn, Sc, ldS, C + (int64_t)nx * ldc, ldc, 1.0, 0.0, Sn + nx, ldS);
+      if (impl) update<T>(n, ns, npn, ASo, ldS, C + (int64_t)nx * ldc, ldc, 1.0, 0.0, AX + nx, ldS);
       if (B) spmm<T>(*B, Sn + nx, ldS, BXP + nx, ldBXP, npn);
     }
     np = npn;

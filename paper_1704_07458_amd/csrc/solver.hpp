@@ -24,7 +24,8 @@ template <typename T>
 struct Blocks {
   DevBuf S[2];  // [X | P | W], ping-pong
   DevBuf AX, AW, BXP, BW, MU, U2, R;
-  void alloc(int64_t n, int64_t ldS, int64_t ldX, bool haveB);
+  DevBuf AS[2];  // [A X | A P | A W] in the layout of S (implicit product updates only)
+  void alloc(int64_t n, int64_t ldS, int64_t ldX, bool haveB, bool implicit_products);
 };
 
 

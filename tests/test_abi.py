@@ -95,10 +95,13 @@ def test_rejects_block_too_wide_and_bad_k():
     assert code == -1
 
 
-def test_rejects_unprovided_implicit_products_and_bad_ortho_mode():
+def test_rejects_implicit_products_with_B_and_bad_ortho_mode():
     A = P.laplacian_2d_dirichlet(8)
-    code, msg = _create(A, 2, implicit_products=1)
-    assert code == -1 and "implicit" in msg
+    Bm = P.laplacian_2d_dirichlet(8)
+    code, msg = _create(A, 2, Bm, implicit_products=1)
+    assert code == -1 and "B = I" in msg
+    code, msg = _create(A, 2, implicit_products=2)
+    assert code == -1 and "implicit_products" in msg
     code, msg = _create(A, 2, ortho_mode=2)
     assert code == -1 and "ortho_mode" in msg
     code, msg = _create(A, 2, largest=2)

@@ -201,6 +201,43 @@ def test_section6_versions_match_oracle(lib, idx, gpu_opts, ref_opts):
         assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
 
 
+# Section 5.2's implicit product updates (B = I), alone and in the versions of
+# Fig. 2 that use them: AHL (version 4: Algorithm 3 every iteration, explicit
+# X/P Gram blocks) and Algorithm 8 with them (version 7 as printed).
+IMPLICIT = [
+    ({"implicit_products": 1}, {"implicit_products": True}),
+    ({"force_ortho": 1, "ortho_mode": 1, "implicit_gram": 0, "implicit_products": 1},
+     {"force_ortho": True, "ortho_kind": "hl", "implicit_products": True}),
+    ({"implicit_gram": 0, "implicit_products": 1}, {"implicit_products": True}),
+]
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+@pytest.mark.parametrize("gpu_opts,ref_opts", IMPLICIT)
+def test_implicit_product_updates_match_oracle(lib, idx, gpu_opts, ref_opts):
+    w = P.workload(idx, small=idx != 0)
+    s, info = _gpu_solve(w, **gpu_opts)
+    assert info["converged"], info
+    ref = _oracle(w, **ref_opts)
+    assert ref.converged
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    th = ref.theta[: w.k]
+    assert np.max(np.abs(lam - th) / np.abs(th)) <= EIG_RTOL
+    assert abs(info["iterations"] - ref.iterations) <= max(2, 0.1 * ref.iterations)
+    # the true residual, recomputed on the host, not the implicitly updated one
+    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], 1.0) <= RESID_TOL)
+
+
+def test_implicit_product_updates_fp32_split(lib):
+    w = P.workload(1, small=True)
+    s, info = _gpu_solve(w, implicit_products=1, precision="split")
+    assert info["converged"], info
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    exact = cf.smallest(cf.laplacian_3d_dirichlet(12), w.k)
+    assert np.max(np.abs(lam - exact) / exact) <= EIG_RTOL
+    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], 1.0) <= RESID_TOL)
+
+
 def _golden(name):
     import os
 
