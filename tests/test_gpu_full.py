@@ -111,6 +111,77 @@ def test_gram_and_update_full_size(lib, cfg1):
     assert np.all(np.abs(Y - refY) <= bY)
 
 
+@pytest.fixture(scope="module")
+def cfg3():
+    """The 96^3 periodic Laplacian + U[-8, 8] potential of the k = 1000 workload,
+    built without its 884,736 x 1100 host initial block."""
+    L3 = P.laplacian_3d(96, periodic=True)
+    V = P.potential(0, L3.n, -8.0, 8.0)
+    return P.add_diagonal(L3, V), float(V.min())
+
+
+def test_spmm_96cubed_1100_columns_sampled_rows(lib, cfg3):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    A, _ = cfg3
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    X = torch.randn((A.n, 1100), generator=gen, dtype=torch.float64, device="cuda")
+    rp = torch.from_numpy(A.rowptr).cuda()
+    ci = torch.from_numpy(A.colind).cuda()
+    va = torch.from_numpy(A.values).cuda()
+    Y = B.spmm(rp, ci, va, X)
+    rng = np.random.default_rng(3)
+    rows = np.sort(rng.choice(A.n, 500, replace=False))
+    As = A.to_scipy()[rows]
+    cols = np.unique(As.indices)
+    Xg = X[torch.from_numpy(cols).cuda()].cpu().numpy()
+    Asub = As[:, cols]
+    ref = Asub @ Xg
+    bound = 2 * gamma(7, U64) * (abs(Asub) @ np.abs(Xg))
+    got = Y[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_periodic_96cubed_k1000_first_iterations(lib, cfg3):
+    """The k = 1000 workload at full size (n = 884,736, n_x = 1100, n_s up to 3300,
+    the projected problems on the library's dense solvers): one and two iterations
+    from the same X0.  What holds at any size: Ritz values ascending and above
+    Gershgorin's bound min(V), non-increasing from one iteration to the next (the
+    new search space contains the old X), X orthonormal, and criterion (9) of
+    sampled pairs recomputed on the host equal to the solver's."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    A, vmin = cfg3
+    k = 1000
+    n_x = P.block_size(k)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    X0 = torch.randn((A.n, n_x), generator=gen, dtype=torch.float64, device="cuda")
+    lams = []
+    for it in (1, 2):
+        s = B.Solver(A, k, precond="jacobi", maxit=it)
+        info = s.solve(1e-8, X0)
+        assert info["status"] == "NOT_CONVERGED" and info["iterations"] == it
+        lam, X, rho = s.eigpairs(n_x)
+        lams.append(lam.cpu().numpy())
+        if it == 2:
+            Xt = X.t().contiguous()
+            G = (Xt @ X).cpu().numpy()
+            assert np.max(np.abs(G - np.eye(n_x))) <= 1e-10
+            cols = np.array([0, 1, 7, 100, 555, 999, n_x - 1])
+            xs = X[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+            ls = lams[-1][cols]
+            host = _host_rho(A.to_scipy(), ls, xs, info["norm_A_est"])
+            assert np.allclose(host, rho.cpu().numpy()[cols], rtol=1e-6, atol=1e-15)
+        del X
+        s.close()
+    lam1, lam2 = lams
+    assert np.all(np.diff(lam1) >= 0) and np.all(np.diff(lam2) >= 0)
+    assert lam2.min() >= vmin - 1e-9
+    assert np.all(lam2 <= lam1 + 1e-10 * np.abs(lam1).max())
+
+
 def test_fem_pencil_48cubed_k400(lib):
     """Generalised pencil (Q1 stiffness, mass) on 48^3, k = 400, Jacobi."""
     torch = _torch()
