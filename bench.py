@@ -18,6 +18,10 @@ isation counts, phase breakdown).
 
 --ksweep solves the 64^3 Laplacian for k = 25, 50, 100, 150, 200 (the analog of
 Fig. 4's time against the number of eigenpairs) and prints one line per k.
+
+--workloads times the other synthetic pencils: the 48^3 Q1 FEM pencil with
+k = 400 to convergence, and the first 30 iterations of the 96^3 periodic
+Laplacian + potential with k = 1000 (one line each, with phase shares).
 """
 
 from __future__ import annotations
@@ -36,6 +40,13 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-k-eigenpairs at rel. residual 1e-8; SpMM GB/s; FP64 vs FP32-split"
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+
+def dirichlet3d_smallest(N: int, k: int) -> np.ndarray:
+    """The k smallest eigenvalues of the 3D 7-point Dirichlet Laplacian on an
+    N^3 grid: sums of three 1D values 4 sin^2(pi j / (2 (N + 1))), j = 1..N."""
+    e1 = 4.0 * np.sin(np.pi * np.arange(1, N + 1) / (2.0 * (N + 1))) ** 2
+    return np.sort((e1[:, None, None] + e1[None, :, None] + e1[None, None, :]).ravel())[:k]
 
 
 def _log(msg):
@@ -163,9 +174,8 @@ def run_ablation(torch, B, w, X0, exact):
 KSWEEP = (25, 50, 100, 150, 200)
 
 
-def run_ksweep(torch, B, P, cf):
+def run_ksweep(torch, B, P):
     w = P.workload(1)
-    ev = cf.laplacian_3d_dirichlet(64)
     for i, k in enumerate(KSWEEP):
         n_x = P.block_size(k)
         X0 = torch.from_numpy(P.initial_block(0, w.A.n, n_x)).cuda()
@@ -179,7 +189,7 @@ def run_ksweep(torch, B, P, cf):
         sec = time.perf_counter() - t0
         lam, X, _ = s.eigpairs(k)
         rho, err = check_solution(w, lam.cpu().numpy(), X.cpu().numpy(), info["norm_A_est"],
-                                  cf.smallest(ev, k))
+                                  dirichlet3d_smallest(64, k))
         line = {"ksweep_k": k, "n_x": n_x, "status": info["status"],
                 "iterations": info["iterations"], "seconds": sec,
                 "ms_per_iteration": 1e3 * sec / max(1, info["iterations"]),
@@ -188,6 +198,47 @@ def run_ksweep(torch, B, P, cf):
         _log(f"[bench] ksweep k={k}: {info['iterations']} iters {sec:.3f}s")
         print(json.dumps(line), flush=True)
         s.close()
+
+
+def _timed_with_phases(torch, s, tol, X0):
+    s.solve(tol, X0)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.solve(tol, X0)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    s.set_profiling(True)
+    ph = s.solve(tol, X0)["seconds_phase"]
+    s.set_profiling(False)
+    tot = sum(ph.values())
+    return info, sec, {k: v / tot for k, v in ph.items()} if tot > 0 else None
+
+
+def run_workloads(torch, B, P):
+    w = P.workload(2)
+    X0 = torch.from_numpy(w.X0).cuda()
+    s = B.Solver(w.A, w.k, B=w.B, precond="jacobi")
+    info, sec, share = _timed_with_phases(torch, s, w.tol, X0)
+    print(json.dumps({"workload": "Q1 FEM pencil (K, M) 48^3 (n=110592), k=400, n_x=440, Jacobi, "
+                                  "tol 1e-8", "status": info["status"],
+                      "iterations": info["iterations"], "seconds": sec,
+                      "ms_per_iteration": 1e3 * sec / info["iterations"],
+                      "phase_share": share}), flush=True)
+    s.close()
+    del X0
+    L3 = P.laplacian_3d(96, periodic=True)
+    A = P.add_diagonal(L3, P.potential(0, L3.n, -8.0, 8.0))
+    n_x = P.block_size(1000)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    X0 = torch.randn((A.n, n_x), generator=gen, dtype=torch.float64, device="cuda")
+    s = B.Solver(A, 1000, precond="jacobi", maxit=30)
+    info, sec, share = _timed_with_phases(torch, s, 1e-8, X0)
+    print(json.dumps({"workload": "periodic 3D 7-point 96^3 + U[-8,8] (n=884736), k=1000, "
+                                  "n_x=1100, Jacobi; first 30 iterations (device N(0,1) X0)",
+                      "status": info["status"], "iterations": info["iterations"],
+                      "seconds": sec, "ms_per_iteration": 1e3 * sec / info["iterations"],
+                      "phase_share": share}), flush=True)
+    s.close()
 
 
 def kernel_source_hash() -> str:
@@ -229,6 +280,8 @@ def main():
                     help="solve with each version of section 6 instead (one line each)")
     ap.add_argument("--ksweep", action="store_true",
                     help="time to k eigenpairs for several k instead (one line each)")
+    ap.add_argument("--workloads", action="store_true",
+                    help="time the FEM k=400 and periodic k=1000 pencils instead")
     ap.add_argument("--phases", action="store_true",
                     help="one extra untimed FP64 solve with per-phase timing (stream syncs)")
     args = ap.parse_args()
@@ -250,21 +303,23 @@ def main():
         print(json.dumps({"calibration_copy_bytes": nbytes, "copies": 4}), flush=True)
         return
 
-    from oracle import closed_forms as cf
     from paper_1704_07458_amd import binding as B
     from paper_1704_07458_amd import problems as P
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
     B.load()
+    if args.workloads:
+        run_workloads(torch, B, P)
+        return
     w = P.workload(1)
-    exact = cf.smallest(cf.laplacian_3d_dirichlet(64), w.k)
+    exact = dirichlet3d_smallest(64, w.k)
     X0 = torch.from_numpy(w.X0).cuda()  # resident in HBM before timing
     if args.ablation:
         run_ablation(torch, B, w, X0, exact)
         return
     if args.ksweep:
-        run_ksweep(torch, B, P, cf)
+        run_ksweep(torch, B, P)
         return
 
     s64 = B.Solver(w.A, w.k, precond="jacobi")
