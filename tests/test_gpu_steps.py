@@ -90,8 +90,11 @@ def test_spmm_fp32(lib):
     assert np.all(np.abs(Y.cpu().numpy() - ref) <= bound)
 
 
+# shapes that take each of the 64/128 tile pairs, ragged tails in n, m and p, and
+# the bench's Gram (n_s = 330 rows, 2 n_w = 220 columns split at n_w)
 @pytest.mark.parametrize("n,m,p,p1", [(1000, 33, 22, 22), (5003, 130, 70, 40), (300, 7, 5, 5),
-                                      (20000, 65, 128, 64)])
+                                      (20000, 65, 128, 64), (20000, 330, 220, 110),
+                                      (3001, 100, 50, 25)])
 def test_gram_fp64(lib, n, m, p, p1):
     torch = _torch()
     from paper_1704_07458_amd import binding as B
@@ -130,12 +133,12 @@ def test_gram_mirror_and_determinism(lib):
     assert np.all(G1[:m - w, :m - w] == 0.0)
 
 
-def test_gram_fp32_accumulation(lib):
+@pytest.mark.parametrize("n,m,p", [(30000, 50, 20), (30001, 330, 110)])
+def test_gram_fp32_accumulation(lib, n, m, p):
     torch = _torch()
     from paper_1704_07458_amd import binding as B
 
     rng = np.random.default_rng(4)
-    n, m, p = 30000, 50, 20
     L32 = rng.standard_normal((n, m)).astype(np.float32)
     R32 = rng.standard_normal((n, p)).astype(np.float32)
     G = B.gram(torch.from_numpy(L32).cuda(), torch.from_numpy(R32).cuda()).cpu().numpy()
