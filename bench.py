@@ -286,8 +286,8 @@ def main():
                     help="one extra untimed FP64 solve with per-phase timing (stream syncs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the row-partitioned design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (a row "
+              "partition across GPUs with halo exchange is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
