@@ -353,15 +353,17 @@ GramPlan gram_plan(int64_t n, int m, int p) {
 }
 
 // ------------------------------------------------------------------ update
-// Y tile 128 rows x TN cols per workgroup (TN = 128, or 64 when that pads N
-// less): 2 x 2 waves, each a 64 x (TN/2) register tile of MFMA blocks.  K is
+// Y tile 128 rows x TN cols per workgroup, TN = 128, 112 or 64, whichever pads N
+// least (N = n_x = 110 pads to 112): WR waves along the rows and 4 / WR along the
+// columns (2 x 2 for 128 and 64, 4 x 1 with 32 x 112 per wave for 112), each a
+// register tile of MFMA blocks.  K is
 // consumed in stages of kKB: the S tile (128 rows x kKB, row segments of kKB
 // contiguous elements) and the C tile (kKB x TN, column segments of C, which
 // is column-major) go through double-buffered LDS as in the Gram kernel.
 // Grid: x = row tiles * col tiles (col tile fastest).
 constexpr int kUpdTM = 128, kUpdTN = 128, kUpdPad = 1;
 
-template <typename T, int TN>
+template <typename T, int TN, int WR>
 __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
                                                      const T* __restrict__ S, int64_t lds,
                                                      const double* __restrict__ C, int64_t ldc,
@@ -369,7 +371,11 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
                                                      int64_t ldy, int tiles_n) {
   using acc_t = typename Mfma<T>::acc_t;
   __shared__ T Ss[2][kUpdTM][kKB + kUpdPad];
-  constexpr int FB = TN / 32;  // 16-column blocks per wave
+  // WR waves along the rows, 4 / WR along the columns: each wave RW rows x CW
+  // columns, FA x FB MFMA blocks
+  constexpr int WC = 4 / WR, RW = kUpdTM / WR, CW = TN / WC;
+  constexpr int FA = RW / 16, FB = CW / 16;
+  static_assert(FA * 16 == RW && FB * 16 == CW, "16-row/column blocks");
   __shared__ T Cs[2][TN][kKB + kUpdPad];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t tr = lb / tiles_n;
@@ -377,7 +383,7 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
   const int tid = threadIdx.x;
   const int wave = uniform(tid / kWave);
   const int lane = tid % kWave;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WC, wc = wave % WC;
   const int li = lane & 15, lk = lane >> 4;
 
   // Global-load assignment: thread owns k offset kk of the stage and rows
@@ -411,9 +417,9 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
     for (int i = 0; i < kPerC; ++i) Cs[buf][q0 + 16 * i][kk] = gc[i];
   };
 
-  acc_t acc[4][FB];
+  acc_t acc[FA][FB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
     for (int b = 0; b < FB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
@@ -429,13 +435,13 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
     if (more) gload((st + 1) * kKB);
 #pragma unroll
     for (int s = 0; s < kKB / 4; ++s) {
-      T a[4], b[FB];
+      T a[FA], b[FB];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) a[f] = Ss[buf][wr * 64 + f * 16 + li][4 * s + lk];
+      for (int f = 0; f < FA; ++f) a[f] = Ss[buf][wr * RW + f * 16 + li][4 * s + lk];
 #pragma unroll
-      for (int f = 0; f < FB; ++f) b[f] = Cs[buf][wc * (TN / 2) + f * 16 + li][4 * s + lk];
+      for (int f = 0; f < FB; ++f) b[f] = Cs[buf][wc * CW + f * 16 + li][4 * s + lk];
 #pragma unroll
-      for (int fa = 0; fa < 4; ++fa)
+      for (int fa = 0; fa < FA; ++fa)
 #pragma unroll
         for (int fb = 0; fb < FB; ++fb) acc[fa][fb] = Mfma<T>::mma(a[fa], b[fb], acc[fa][fb]);
     }
@@ -444,14 +450,14 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
   }
 
 #pragma unroll
-  for (int fa = 0; fa < 4; ++fa)
+  for (int fa = 0; fa < FA; ++fa)
 #pragma unroll
     for (int fb = 0; fb < FB; ++fb) {
-      const int j = tc * TN + wc * (TN / 2) + fb * 16 + li;
+      const int j = tc * TN + wc * CW + fb * 16 + li;
       if (j >= N) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t r = tr * kUpdTM + wr * 64 + fa * 16 + Mfma<T>::row(lk, q);
+        const int64_t r = tr * kUpdTM + wr * RW + fa * 16 + Mfma<T>::row(lk, q);
         if (r < n) {
           T v = alpha * acc[fa][fb][q];
           if (beta1) v += Y[r * ldy + j];
@@ -1493,19 +1499,25 @@ template <typename T>
 void launch_update(int64_t n, int K, int N, const T* S, int64_t lds, const double* C, int64_t ldc,
                    double alpha, double beta, T* Y, int64_t ldy, hipStream_t s) {
   if (n == 0 || N == 0) return;
-  // 64-wide column tiles when they pad N less than 128-wide ones
-  const bool narrow = (N + 63) / 64 * 64 < (N + kUpdTN - 1) / kUpdTN * kUpdTN;
-  const int tn = narrow ? 64 : kUpdTN;
+  // the column tile (128, 112 or 64 wide) that pads N least; ties to the wider
+  auto padded = [N](int t) { return (N + t - 1) / t * t; };
+  int tn = kUpdTN;
+  if (padded(112) < padded(tn)) tn = 112;
+  if (padded(64) < padded(tn)) tn = 64;
   const int tiles_n = (N + tn - 1) / tn;
   const int64_t tiles_r = (n + kUpdTM - 1) / kUpdTM;
   const int64_t grid = tiles_r * tiles_n;
   LOBPCG_CHECK(grid < (int64_t)1 << 31, LOBPCG_ERR_ARG, "update grid too large");
-  if (narrow)
-    hipLaunchKernelGGL((update_kernel<T, 64>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N, S,
-                       lds, C, ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);
-  else
-    hipLaunchKernelGGL((update_kernel<T, kUpdTN>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N,
+  // 2 x 2 waves for 128- and 64-wide tiles; 4 x 1 (32 rows x 112 columns each) for 112
+  if (tn == 64)
+    hipLaunchKernelGGL((update_kernel<T, 64, 2>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N,
                        S, lds, C, ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);
+  else if (tn == 112)
+    hipLaunchKernelGGL((update_kernel<T, 112, 4>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N,
+                       S, lds, C, ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);
+  else
+    hipLaunchKernelGGL((update_kernel<T, kUpdTN, 2>), dim3((unsigned)grid), dim3(256), 0, s, n, K,
+                       N, S, lds, C, ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);
   LOBPCG_HIP(hipGetLastError());
 }
 

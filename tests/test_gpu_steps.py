@@ -148,7 +148,9 @@ def test_gram_fp32_accumulation(lib, n, m, p):
     assert np.all(np.abs(G - ref) <= bound)
 
 
-@pytest.mark.parametrize("n,K,N", [(1000, 33, 22), (4097, 330, 220), (70, 5, 3), (2000, 130, 65)])
+# column tiles: 64 (22, 3), 112 (220, 65, and 110 = n_x of the bench), 128 (128)
+@pytest.mark.parametrize("n,K,N", [(1000, 33, 22), (4097, 330, 220), (70, 5, 3), (2000, 130, 65),
+                                   (5001, 330, 110), (3000, 200, 128)])
 def test_update_fp64(lib, n, K, N):
     torch = _torch()
     from paper_1704_07458_amd import binding as B
@@ -169,12 +171,12 @@ def test_update_fp64(lib, n, K, N):
     assert np.all(np.abs(Y0.cpu().numpy() - ref2) <= bound + 2 * U64 * np.abs(Y0h))
 
 
-def test_update_fp32(lib):
+@pytest.mark.parametrize("n,K,N", [(3000, 96, 70), (4001, 330, 110)])
+def test_update_fp32(lib, n, K, N):
     torch = _torch()
     from paper_1704_07458_amd import binding as B
 
     rng = np.random.default_rng(9)
-    n, K, N = 3000, 96, 70
     S32 = rng.standard_normal((n, K)).astype(np.float32)
     Ch = rng.standard_normal((K, N))
     Y = B.update(torch.from_numpy(S32).cuda(), torch.from_numpy(Ch).cuda()).cpu().numpy()
