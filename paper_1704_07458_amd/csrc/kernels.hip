@@ -165,7 +165,8 @@ struct Mfma<float> {
 
 // ------------------------------------------------------------------ Gram
 // Workgroup tile TM (m) x TP (p), TM, TP in {128, 64}: 2 x 2 waves, each wave a
-// (TM/2) x (TP/2) register tile of MFMA 16x16x4 blocks.  The row range is
+// (TM/2) x (TP/2) register tile of MFMA 16x16x4 blocks; or one side 112 (seven
+// blocks) with the four waves along the other side.  The row range is
 // consumed in stages of kKB rows: each stage's L and R tiles are loaded with
 // coalesced global loads into registers while the previous stage is
 // multiplied out of LDS, then stored to the other LDS buffer (double
@@ -176,13 +177,17 @@ struct Mfma<float> {
 // and writes a partial tile to part[split][i][j].
 constexpr int kGramTM = 128, kGramTP = 128, kKB = 16, kLdsPad = 2;
 
-template <typename T, int TM, int TP>
+template <typename T, int TM, int TP, int WM>
 __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
     int64_t n, int m, int p, int p1, const T* __restrict__ L, int64_t ldl,
     const T* __restrict__ R1, int64_t ldr1, const T* __restrict__ R2, int64_t ldr2,
     double* __restrict__ part, int tiles_m, int tiles_p, int64_t rows_per_split) {
   using acc_t = typename Mfma<T>::acc_t;
-  constexpr int FA = TM / 32, FB = TP / 32;  // 16 x 16 blocks per wave and dimension
+  // WM waves along m, 4 / WM along p; each wave RM x CP of the tile in FA x FB
+  // MFMA blocks of 16 x 16
+  constexpr int WP = 4 / WM, RM = TM / WM, CP = TP / WP;
+  constexpr int FA = RM / 16, FB = CP / 16;
+  static_assert(FA * 16 == RM && FB * 16 == CP, "16-row/column blocks");
   __shared__ T Ls[2][kKB][TM + kLdsPad];
   __shared__ T Rs[2][kKB][TP + kLdsPad];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
   const int tid = threadIdx.x;
   const int wave = uniform(tid / kWave);
   const int lane = tid % kWave;
-  const int wm = wave >> 1, wp = wave & 1;
+  const int wm = wave / WP, wp = wave % WP;
   const int li = lane & 15, lk = lane >> 4;
 
   const int64_t k0 = (int64_t)split * rows_per_split;
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
 
   // Global-load assignment: thread owns column ca of the L tile and rows
   // ra + RA i, and column cb of the R tile and rows rb + RB i.
-  constexpr int RA = 256 / TM, RB = 256 / TP;
+  constexpr int RA = 256 / TM, RB = 256 / TP;  // a 112-wide tile leaves threads 224.. idle
   constexpr int KA = kKB / RA, KBr = kKB / RB;  // rows per thread per stage
   const int ca = tid % TM, ra = tid / TM;
   const int cbt = tid % TP, rb = tid / TP;
@@ -224,19 +229,21 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
 #pragma unroll
     for (int i = 0; i < KA; ++i) {
       const int64_t row = kb + ra + RA * i;
-      ga[i] = (row < k1 && okA) ? colA[row * ldl] : T(0);
+      ga[i] = (ra < RA && row < k1 && okA) ? colA[row * ldl] : T(0);
     }
 #pragma unroll
     for (int i = 0; i < KBr; ++i) {
       const int64_t row = kb + rb + RB * i;
-      gb[i] = (row < k1 && okB) ? colB[row * ldB] : T(0);
+      gb[i] = (rb < RB && row < k1 && okB) ? colB[row * ldB] : T(0);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < KA; ++i) Ls[buf][ra + RA * i][ca] = ga[i];
+    for (int i = 0; i < KA; ++i)
+      if (ra < RA) Ls[buf][ra + RA * i][ca] = ga[i];
 #pragma unroll
-    for (int i = 0; i < KBr; ++i) Rs[buf][rb + RB * i][cbt] = gb[i];
+    for (int i = 0; i < KBr; ++i)
+      if (rb < RB) Rs[buf][rb + RB * i][cbt] = gb[i];
   };
 
   acc_t acc[FA][FB];
@@ -259,9 +266,9 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
     for (int s = 0; s < kKB / 4; ++s) {
       T a[FA], b[FB];
 #pragma unroll
-      for (int f = 0; f < FA; ++f) a[f] = Ls[buf][4 * s + lk][wm * (TM / 2) + f * 16 + li];
+      for (int f = 0; f < FA; ++f) a[f] = Ls[buf][4 * s + lk][wm * RM + f * 16 + li];
 #pragma unroll
-      for (int f = 0; f < FB; ++f) b[f] = Rs[buf][4 * s + lk][wp * (TP / 2) + f * 16 + li];
+      for (int f = 0; f < FB; ++f) b[f] = Rs[buf][4 * s + lk][wp * CP + f * 16 + li];
 #pragma unroll
       for (int fa = 0; fa < FA; ++fa)
 #pragma unroll
@@ -277,11 +284,11 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
   for (int fa = 0; fa < FA; ++fa)
 #pragma unroll
     for (int fb = 0; fb < FB; ++fb) {
-      const int j = tp * TP + wp * (TP / 2) + fb * 16 + li;
+      const int j = tp * TP + wp * CP + fb * 16 + li;
       if (j >= p) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = tm * TM + wm * (TM / 2) + fa * 16 + Mfma<T>::row(lk, q);
+        const int i = tm * TM + wm * RM + fa * 16 + Mfma<T>::row(lk, q);
         if (i < m) out[(int64_t)i * p + j] = (double)acc[fa][fb][q];
       }
     }
@@ -314,7 +321,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int p1, 
 }
 
 struct GramPlan {
-  int tm, tp;  // tile sizes (128 or 64)
+  int tm, tp;  // tile sizes (128, 112 or 64; at most one of them 112)
   int tiles_m, tiles_p, nsplit;
   int64_t rows_per_split;
 };
@@ -325,18 +332,21 @@ constexpr int kGramTargetBlocks = 510;
 
 GramPlan gram_plan(int64_t n, int m, int p) {
   GramPlan g;
-  // the tile pair that pads m x p least (ties: the larger tiles)
+  // the tile pair that pads m x p least (ties: the earlier, larger tiles); a
+  // 112-wide side (seven 16-blocks, n_s = 330 -> 336, 2 n_w = 220 -> 224) takes
+  // a 4 x 1 or 1 x 4 wave layout, so the other side must be 128 or 64
   auto padded = [](int x, int t) { return (int64_t)((x + t - 1) / t) * t; };
+  static const int kPairs[8][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
+                                   {128, 112}, {112, 128}, {112, 64}, {64, 112}};
   int64_t best = -1;
-  for (int tm : {kGramTM, kGramTM / 2})
-    for (int tp : {kGramTP, kGramTP / 2}) {
-      const int64_t area = padded(m, tm) * padded(p, tp);
-      if (best < 0 || area < best) {
-        best = area;
-        g.tm = tm;
-        g.tp = tp;
-      }
+  for (const auto& tt : kPairs) {
+    const int64_t area = padded(m, tt[0]) * padded(p, tt[1]);
+    if (best < 0 || area < best) {
+      best = area;
+      g.tm = tt[0];
+      g.tp = tt[1];
     }
+  }
   g.tiles_m = (m + g.tm - 1) / g.tm;
   g.tiles_p = (p + g.tp - 1) / g.tp;
   const int ntiles = g.tiles_m * g.tiles_p;
@@ -1473,14 +1483,18 @@ void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const
     const unsigned grid = (unsigned)(nsplit * g.tiles_m * g.tiles_p);
     const T* R2e = R2 ? R2 : R1;
     const int64_t ldr2e = R2 ? ldr2 : ldr1;
-#define LOBPCG_GRAM_LAUNCH(TMv, TPv)                                                          \
-  hipLaunchKernelGGL((gram_partial_kernel<T, TMv, TPv>), dim3(grid), dim3(256), 0, s, n, m, p, \
-                     p1, L, ldl, R1, ldr1, R2e, ldr2e, part, g.tiles_m, g.tiles_p,           \
+#define LOBPCG_GRAM_LAUNCH(TMv, TPv, WMv)                                                    \
+  hipLaunchKernelGGL((gram_partial_kernel<T, TMv, TPv, WMv>), dim3(grid), dim3(256), 0, s, n, m, \
+                     p, p1, L, ldl, R1, ldr1, R2e, ldr2e, part, g.tiles_m, g.tiles_p,          \
                      g.rows_per_split)
-    if (g.tm == kGramTM && g.tp == kGramTP) LOBPCG_GRAM_LAUNCH(kGramTM, kGramTP);
-    else if (g.tm == kGramTM) LOBPCG_GRAM_LAUNCH(kGramTM, kGramTP / 2);
-    else if (g.tp == kGramTP) LOBPCG_GRAM_LAUNCH(kGramTM / 2, kGramTP);
-    else LOBPCG_GRAM_LAUNCH(kGramTM / 2, kGramTP / 2);
+    if (g.tm == 128 && g.tp == 128) LOBPCG_GRAM_LAUNCH(128, 128, 2);
+    else if (g.tm == 128 && g.tp == 64) LOBPCG_GRAM_LAUNCH(128, 64, 2);
+    else if (g.tm == 64 && g.tp == 128) LOBPCG_GRAM_LAUNCH(64, 128, 2);
+    else if (g.tm == 64 && g.tp == 64) LOBPCG_GRAM_LAUNCH(64, 64, 2);
+    else if (g.tm == 128 && g.tp == 112) LOBPCG_GRAM_LAUNCH(128, 112, 4);
+    else if (g.tm == 112 && g.tp == 128) LOBPCG_GRAM_LAUNCH(112, 128, 1);
+    else if (g.tm == 112 && g.tp == 64) LOBPCG_GRAM_LAUNCH(112, 64, 1);
+    else LOBPCG_GRAM_LAUNCH(64, 112, 4);
 #undef LOBPCG_GRAM_LAUNCH
     LOBPCG_HIP(hipGetLastError());
   }
