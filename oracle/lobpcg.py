@@ -311,7 +311,12 @@ def rayleigh_ritz_modified(
         theta, Z = np.linalg.eigh(0.5 * (GA + GA.T))
         T = np.eye(n_s)
     else:
-        d = 1.0 / np.sqrt(np.diag(GB))
+        g = np.diag(GB)
+        if not np.all(g > 0.0):
+            # a column of S with zero B-norm (an exactly converged residual):
+            # S^T B S is singular and has no Cholesky factor (reading R8)
+            return RRResult(None, None, None, None, None, True, True, np.inf)
+        d = 1.0 / np.sqrt(g)
         D = np.diag(d)
         try:
             R = np.linalg.cholesky(D @ GB @ D).T

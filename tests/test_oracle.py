@@ -487,6 +487,21 @@ def test_implicit_product_updates_need_identity_B():
         _solve(w, implicit_products=True, maxit=1)
 
 
+def test_exactly_converged_start_drops_zero_residuals():
+    """X0 spans an invariant subspace exactly (unit vectors of a diagonal A): every
+    residual, hence every W column, is exactly zero.  S^T B S is singular, the
+    Cholesky path is rejected, orthoDrop removes the zero columns (reading R8) and
+    the solve ends after one iteration with the exact eigenvalues."""
+    n = 300
+    A = sp.diags(np.arange(1.0, n + 1)).tocsr()
+    X0 = np.zeros((n, 11))
+    X0[np.arange(11), np.arange(11)] = 1.0
+    res = L.lobpcg(A, X0, 10, 1e-8)
+    assert res.converged and res.iterations == 1 and res.ortho_switch_iter == 1
+    assert np.array_equal(res.theta[:10], np.arange(1.0, 11.0))
+    assert res.history[0].n_w == 0
+
+
 def test_maxit_returns_not_converged():
     w = P.workload(0)
     res = _solve(w, maxit=3)
