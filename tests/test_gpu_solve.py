@@ -380,6 +380,28 @@ def test_callback_error_is_reported(lib):
     assert e.value.code == -6
 
 
+def test_exactly_converged_start_drops_zero_residuals(lib):
+    """Every residual of X0 is exactly zero (unit vectors of a diagonal A), so W = 0:
+    the zero pivots reject the Cholesky path, orthoDrop removes every W column and
+    the solve ends after one iteration with the exact eigenvalues, as in the oracle."""
+    import scipy.sparse as sp
+
+    from paper_1704_07458_amd import binding as B
+
+    n = 300
+    As = sp.diags(np.arange(1.0, n + 1)).tocsr()
+    X0 = np.zeros((n, 11))
+    X0[np.arange(11), np.arange(11)] = 1.0
+    s = B.Solver(P.from_scipy(As), 10)
+    info = s.solve(1e-8, X0)
+    assert info["converged"], info
+    assert info["iterations"] == 1 and info["ortho_switch_iter"] == 1
+    ref = L.lobpcg(As, X0, 10, 1e-8)
+    assert ref.iterations == 1 and ref.ortho_switch_iter == 1
+    lam = s.eigpairs(10)[0].cpu().numpy()
+    assert np.allclose(lam, np.arange(1.0, 11.0), rtol=1e-14, atol=0)
+
+
 def test_maxit_reports_not_converged(lib):
     w = P.workload(0)
     s, info = _gpu_solve(w, maxit=3)
