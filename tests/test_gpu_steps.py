@@ -186,6 +186,31 @@ def test_update_fp32(lib, n, K, N):
     assert np.all(np.abs(Y - ref) <= bound)
 
 
+def test_steps_with_empty_dimensions(lib):
+    """Degenerate sizes through the step entry points: no columns in the sparse
+    product, no rows in the Gram (a zero matrix), an empty inner dimension in the
+    update (alpha S C + 0 Y = 0) and no columns in the update."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    A = P.laplacian_2d_dirichlet(10)
+    rp = torch.from_numpy(A.rowptr).cuda()
+    ci = torch.from_numpy(A.colind).cuda()
+    va = torch.from_numpy(A.values).cuda()
+    X0 = torch.zeros((A.n, 0), dtype=torch.float64, device="cuda")
+    assert tuple(B.spmm(rp, ci, va, X0).shape) == (A.n, 0)
+    L0 = torch.zeros((0, 5), dtype=torch.float64, device="cuda")
+    R0 = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    G = B.gram(L0, R0).cpu().numpy()
+    assert G.shape[0] >= 3 and np.all(G == 0.0)
+    S = torch.ones((70, 0), dtype=torch.float64, device="cuda")
+    Y = B.update(S, torch.zeros((0, 4), dtype=torch.float64)).cpu().numpy()
+    assert Y.shape == (70, 4) and np.all(Y == 0.0)
+    S2 = torch.ones((70, 6), dtype=torch.float64, device="cuda")
+    Y2 = B.update(S2, torch.zeros((6, 0), dtype=torch.float64))
+    assert tuple(Y2.shape) == (70, 0)
+
+
 def test_residual_and_criterion9(lib):
     torch = _torch()
     from paper_1704_07458_amd import binding as B
