@@ -177,15 +177,16 @@ struct Mfma<float> {
 // and writes a partial tile to part[split][i][j].
 constexpr int kGramTM = 128, kGramTP = 128, kKB = 16, kLdsPad = 2;
 
-template <typename T, int TM, int TP, int WM>
-__global__ __launch_bounds__(256, 2) void gram_partial_kernel(
+template <typename T, int TM, int TP, int WM, int WP = 4 / WM>
+__global__ __launch_bounds__(kWave * WM * WP, 2) void gram_partial_kernel(
     int64_t n, int m, int p, int p1, const T* __restrict__ L, int64_t ldl,
     const T* __restrict__ R1, int64_t ldr1, const T* __restrict__ R2, int64_t ldr2,
     double* __restrict__ part, int tiles_m, int tiles_p, int64_t rows_per_split) {
   using acc_t = typename Mfma<T>::acc_t;
-  // WM waves along m, 4 / WM along p; each wave RM x CP of the tile in FA x FB
-  // MFMA blocks of 16 x 16
-  constexpr int WP = 4 / WM, RM = TM / WM, CP = TP / WP;
+  // WM waves along m, WP along p (four waves, or seven 16-row stripes of a
+  // 112 x 112 tile); each wave RM x CP of the tile in FA x FB MFMA blocks of 16 x 16
+  constexpr int kThreads = kWave * WM * WP;
+  constexpr int RM = TM / WM, CP = TP / WP;
   constexpr int FA = RM / 16, FB = CP / 16;
   static_assert(FA * 16 == RM && FB * 16 == CP, "16-row/column blocks");
   __shared__ T Ls[2][kKB][TM + kLdsPad];
@@ -206,7 +207,8 @@ __global__ __launch_bounds__(256, 2) void gram_partial_kernel(
 
   // Global-load assignment: thread owns column ca of the L tile and rows
   // ra + RA i, and column cb of the R tile and rows rb + RB i.
-  constexpr int RA = 256 / TM, RB = 256 / TP;  // a 112-wide tile leaves threads 224.. idle
+  // (256 threads and a 112-wide tile leave threads 224.. idle)
+  constexpr int RA = kThreads / TM, RB = kThreads / TP;
   constexpr int KA = kKB / RA, KBr = kKB / RB;  // rows per thread per stage
   const int ca = tid % TM, ra = tid / TM;
   const int cbt = tid % TP, rb = tid / TP;
@@ -336,7 +338,7 @@ GramPlan gram_plan(int64_t n, int m, int p) {
   // 112-wide side (seven 16-blocks, n_s = 330 -> 336, 2 n_w = 220 -> 224) takes
   // a 4 x 1 or 1 x 4 wave layout, so the other side must be 128 or 64
   auto padded = [](int x, int t) { return (int64_t)((x + t - 1) / t) * t; };
-  static const int kPairs[8][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
+  static const int kPairs[9][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}, {112, 112},
                                    {128, 112}, {112, 128}, {112, 64}, {64, 112}};
   int64_t best = -1;
   for (const auto& tt : kPairs) {
@@ -1487,7 +1489,11 @@ void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const
   hipLaunchKernelGGL((gram_partial_kernel<T, TMv, TPv, WMv>), dim3(grid), dim3(256), 0, s, n, m, \
                      p, p1, L, ldl, R1, ldr1, R2e, ldr2e, part, g.tiles_m, g.tiles_p,          \
                      g.rows_per_split)
-    if (g.tm == 128 && g.tp == 128) LOBPCG_GRAM_LAUNCH(128, 128, 2);
+    if (g.tm == 112 && g.tp == 112)  // seven waves, one 16-row stripe of 7 blocks each
+      hipLaunchKernelGGL((gram_partial_kernel<T, 112, 112, 7, 1>), dim3(grid), dim3(kWave * 7), 0,
+                         s, n, m, p, p1, L, ldl, R1, ldr1, R2e, ldr2e, part, g.tiles_m, g.tiles_p,
+                         g.rows_per_split);
+    else if (g.tm == 128 && g.tp == 128) LOBPCG_GRAM_LAUNCH(128, 128, 2);
     else if (g.tm == 128 && g.tp == 64) LOBPCG_GRAM_LAUNCH(128, 64, 2);
     else if (g.tm == 64 && g.tp == 128) LOBPCG_GRAM_LAUNCH(64, 128, 2);
     else if (g.tm == 64 && g.tp == 64) LOBPCG_GRAM_LAUNCH(64, 64, 2);
