@@ -1186,16 +1186,23 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
           const int rd = R0 + lq + 4 * q;
           acc[q] = (rd < n && cd < n) ? A[(int64_t)cd * lda + rd] : 0.0;
         }
-        // operands: A(row R0 + l%16, k = 4s + l/16), B(k = 4s + l/16, column C0 + l%16)
+        // operands: A(row R0 + l%16, k = 4s + l/16), B(k = 4s + l/16, column C0 + l%16),
+        // four slices' operands loaded before their MFMAs (a masked slice adds 0 x 0)
         const int ra = R0 + li;
-        for (int s4 = 0; s4 < (kk + 3) / 4; ++s4) {  // wave-uniform trip count
-          const int k = 4 * s4 + lq;
-          double a = 0.0, b = 0.0;
-          if (k < kk) {
-            if (ra < n) a = -(k < nbp ? V[k * kTrdMaxN + ra] : W[(k - nbp) * kTrdMaxN + ra]);
-            if (cd < n) b = k < nbp ? W[k * kTrdMaxN + cd] : V[(k - nbp) * kTrdMaxN + cd];
+        for (int s0 = 0; s0 < (kk + 3) / 4; s0 += 4) {  // wave-uniform trip count
+          double a[4], b[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = 4 * (s0 + u) + lq;
+            a[u] = 0.0;
+            b[u] = 0.0;
+            if (k < kk) {
+              if (ra < n) a[u] = -(k < nbp ? V[k * kTrdMaxN + ra] : W[(k - nbp) * kTrdMaxN + ra]);
+              if (cd < n) b[u] = k < nbp ? W[k * kTrdMaxN + cd] : V[(k - nbp) * kTrdMaxN + cd];
+            }
           }
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
