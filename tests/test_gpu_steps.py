@@ -480,6 +480,41 @@ def test_projected_eigensolver_backward_error(lib, n_s):
     assert orth <= 4 * n_s * U64
 
 
+@pytest.mark.parametrize("n_s,nx,scale", [(213, 71, 1e-6), (213, 71, 1e-10), (213, 71, 1e-14),
+                                           (330, 110, 1e-12), (97, 33, 1e-9)])
+def test_projected_eigensolver_near_convergence(lib, n_s, nx, scale):
+    """The projected matrices of a tight-tolerance solve: a diagonal X block of
+    Ritz values with exact multiplicities (as a Laplacian's), couplings to the
+    rest of the basis of size `scale`, and a dense remainder.  The tridiagonal
+    form then has tiny off-diagonal entries, so the divide and conquer deflates
+    heavily; its output must still be a backward-stable eigendecomposition."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(7 * n_s + int(-np.log10(scale)))
+    theta = np.sort(np.repeat(rng.uniform(0.1, 2.0, (nx + 2) // 3), 3)[:nx])
+    m = n_s - nx
+    Mr = rng.standard_normal((m, m))
+    GA = np.zeros((n_s, n_s))
+    GA[:nx, :nx] = np.diag(theta)
+    GA[nx:, nx:] = 0.5 * (Mr + Mr.T) + 4.0 * np.eye(m)
+    E = scale * rng.standard_normal((nx, m))
+    GA[:nx, nx:] = E
+    GA[nx:, :nx] = E.T
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(np.eye(n_s)).cuda(), n_s, 0,
+                    True, L.Tolerances().tau_skip)
+    th = got["theta"].cpu().numpy()
+    Z = got["Cx"].cpu().numpy()
+    nrm = np.linalg.norm(GA, 2)
+    res = np.abs(GA @ Z - Z * th).max() / nrm
+    orth = np.abs(Z.T @ Z - np.eye(n_s)).max()
+    print(f"n_s={n_s} scale={scale:g}: residual {res / U64:.1f} eps, orthogonality {orth / U64:.1f} eps")
+    assert np.all(np.isfinite(th)) and np.all(np.diff(th) >= 0)
+    assert np.max(np.abs(th - np.sort(np.linalg.eigvalsh(GA)))) <= 4 * n_s * U64 * nrm
+    assert res <= 4 * n_s * U64
+    assert orth <= 4 * n_s * U64
+
+
 def test_rr_step_is_bitwise_reproducible(lib):
     """Repeated calls on the same projected pencil give bit-identical results.
 
