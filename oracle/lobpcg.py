@@ -533,6 +533,75 @@ def lobpcg(
                         switch_iter, ostats)
 
 
+@dataclasses.dataclass
+class BasicResult:
+    converged: bool
+    breakdown: bool  # the Cholesky of Algorithm 2 failed
+    iterations: int
+    theta: np.ndarray
+    X: np.ndarray
+    rho: np.ndarray
+    normA: float
+    normB: float
+
+
+def lobpcg_basic(A, X0: np.ndarray, k: int, tol: float, B=None,
+                 precond: Optional[Callable[[np.ndarray], np.ndarray]] = None,
+                 maxit: int = 2000) -> BasicResult:
+    """Algorithm 1, the basic LOBPCG, with Algorithm 2 for every Rayleigh-Ritz.
+
+    S = [X, W, P] with W = K^-1 R for all n_x columns (no locking), every block
+    of S^T A S and S^T B S explicit, X = S C(:, 1:n_x) and
+    P = S(:, n_x+1:end) C(n_x+1:end, 1:n_x).  Convergence as in lobpcg (criterion
+    (9), leading run, reading R6).  When S^T B S has no Cholesky factor (a column
+    of zero B-norm or an indefinite pencil in rounding) the method stops with
+    breakdown = True: Algorithm 1 has no way around it, which is what
+    Algorithms 5-8 add.
+    """
+    Aop, Bop = Operator(_csr(A)), Operator(_csr(B))
+    Kinv = precond if precond is not None else (lambda R: R.copy())
+    X0 = np.asarray(X0, dtype=np.float64)
+    n, n_x = X0.shape
+    normA = sketch_norm(Aop, X0)
+    normB = 1.0 if Bop.is_identity else sketch_norm(Bop, X0)
+
+    def rr(S):
+        AS, BS = Aop(S), Bop(S)
+        GA, GB = S.T @ AS, S.T @ BS
+        GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+        if not np.all(np.diag(GB) > 0.0):
+            return None, None
+        try:
+            return rayleigh_ritz(GA, GB)
+        except np.linalg.LinAlgError:
+            return None, None
+
+    C, theta = rr(X0)
+    if C is None:
+        return BasicResult(False, True, 0, np.zeros(n_x), X0, np.full(n_x, np.inf), normA, normB)
+    X = X0 @ C
+    thx = theta
+    R = Aop(X) - Bop(X) * thx[None, :]
+    P = np.zeros((n, 0))
+    rho = criterion9(R, X, thx, normA, normB)
+    for it in range(1, maxit + 1):
+        W = Kinv(R)
+        S = np.hstack([X, W, P])
+        C, theta = rr(S)
+        if C is None:
+            return BasicResult(False, True, it, thx.copy(), X, rho, normA, normB)
+        X = S @ C[:, :n_x]
+        P = S[:, n_x:] @ C[n_x:, :n_x]
+        thx = theta[:n_x]
+        R = Aop(X) - Bop(X) * thx[None, :]
+        rho = criterion9(R, X, thx, normA, normB)
+        ok = rho <= tol
+        n_c = int(np.argmin(ok)) if not np.all(ok) else n_x
+        if n_c >= k:
+            return BasicResult(True, False, it, thx.copy(), X, rho, normA, normB)
+    return BasicResult(False, False, maxit, thx.copy(), X, rho, normA, normB)
+
+
 def jacobi_precond(A):
     """K^-1 R for K = the (possibly shifted) diagonal of A."""
     d = jacobi_diagonal(A)

@@ -502,6 +502,29 @@ def test_exactly_converged_start_drops_zero_residuals():
     assert res.history[0].n_w == 0
 
 
+# ------------------------------------------- Algorithm 1: the basic LOBPCG
+def test_basic_lobpcg_reaches_closed_form_on_an_easy_problem():
+    w = P.workload(0)
+    res = L.lobpcg_basic(w.A.to_scipy(), w.X0, w.k, w.tol)
+    assert res.converged and not res.breakdown
+    ex = cf.smallest(cf.laplacian_2d_dirichlet(32), w.k)
+    assert np.max(np.abs(res.theta[: w.k] - ex) / ex) < 1e-10
+
+
+def test_basic_lobpcg_breaks_down_on_the_section_4_1_example():
+    """W0 = [-e3, e3] / sqrt(2) makes S = [X, W] rank deficient: Algorithm 2's
+    Cholesky fails and Algorithm 1 stops, where Algorithm 8 switches to orthoDrop
+    and converges to the tridiagonal's smallest eigenvalues."""
+    n = 8
+    A, X0 = _e1_setup(n)
+    res = L.lobpcg_basic(A, X0, 2, 1e-10)
+    assert res.breakdown and res.iterations == 1 and not res.converged
+    r8 = L.lobpcg(A, X0, 2, 1e-10)
+    assert r8.converged and r8.ortho_switch_iter == 1
+    ex = np.linalg.eigvalsh(A.toarray())[:2]
+    assert np.max(np.abs(r8.theta[:2] - ex) / ex) < 1e-10
+
+
 def test_maxit_returns_not_converged():
     w = P.workload(0)
     res = _solve(w, maxit=3)
