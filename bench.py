@@ -117,8 +117,8 @@ def cpu_baseline(w, iters, gpu_iters):
 # section 5.2 (version 4, the aggressive type); then orthoDrop (version 5), then
 # skipping orthogonalisation until Algorithm 7 rejects the Cholesky path
 # (version 6), then the X/P blocks from eqs. (12)-(14) (version 7, Algorithm 8
-# as printed); and Algorithm 8 with A X recomputed by the sparse product, this
-# solver's default.
+# as printed); Algorithm 8 with A X recomputed by the sparse product, this
+# solver's default; and Algorithm 1, the basic LOBPCG the paper starts from.
 ABLATION = [
     ("v2_hl_ortho", 2, {"force_ortho": 1, "ortho_mode": 1, "implicit_gram": 0,
                         "implicit_products": 0}),
@@ -132,6 +132,7 @@ ABLATION = [
                           "implicit_products": 1}),
     ("v7_algorithm8_spmm_products", 7, {"force_ortho": 0, "ortho_mode": 0, "implicit_gram": 1,
                                         "implicit_products": 0}),
+    ("algorithm1_basic", "Alg. 1", {"basic": 1}),
 ]
 
 

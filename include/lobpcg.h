@@ -109,6 +109,12 @@ typedef struct {
                                 Algorithm 7), as the versions without skipped orthogonalisation */
   int32_t implicit_gram;     /* 1 = the X and P blocks of S^T A S and S^T B S from eqs. (12)-(14)
                                 (default); 0 = computed explicitly (with A P and B P) */
+  int32_t basic;             /* 1 = Algorithm 1, the basic LOBPCG, instead of Algorithm 8: W for
+                                every column (no locking), every Gram block explicit,
+                                Algorithm 2's Rayleigh-Ritz with no condition test and
+                                P = S(:, n_x+1:end) C(n_x+1:end, 1:n_x); when S^T B S has no
+                                Cholesky factor the solve stops with LOBPCG_ERR_BREAKDOWN (the
+                                failure Algorithms 5-8 remove).  Other switches are ignored */
   int32_t largest;           /* 1 = the k largest eigenpairs instead (section 2: the Ritz values
                                 ordered the other way round), computed as the k smallest of
                                 (-A, B); lobpcg_eigpairs then returns descending values.  The

@@ -67,6 +67,7 @@ class lobpcg_options(C.Structure):
         ("ortho_mode", C.c_int32),
         ("force_ortho", C.c_int32),
         ("implicit_gram", C.c_int32),
+        ("basic", C.c_int32),
         ("largest", C.c_int32),
     ]
 

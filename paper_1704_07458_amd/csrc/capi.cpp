@@ -68,6 +68,7 @@ void lobpcg_default_options(lobpcg_options* opt) {
   opt->ortho_mode = 0;
   opt->force_ortho = 0;
   opt->implicit_gram = 1;
+  opt->basic = 0;
   opt->largest = 0;
 }
 

@@ -221,7 +221,7 @@ void Dense::rr_p_block(const double* Z, int ns, int nx, int nc, bool literal_lq,
 RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int ns, int nx,
                             int nc, bool use_ortho, bool literal_lq, double tau_skip, double* C,
                             int64_t ldc, double* theta, double* theta_p, int64_t ldtp,
-                            bool defer_p, int n_ident) {
+                            bool defer_p, int n_ident, bool basic_p) {
   LOBPCG_CHECK(ns <= nsmax_ && nx <= ns && nc <= nx && n_ident >= 0 && n_ident <= ns,
                LOBPCG_ERR_ARG, "rr_modified: bad sizes");
   join_p();
@@ -301,6 +301,18 @@ RROutput Dense::rr_modified(const double* GA, const double* GB, int64_t ldg, int
     launch_set_identity(ns, ns, T, ld, s_);
   }
   const double* Z = H;
+  if (basic_p) {
+    // C_x = T Z(:, 1:n_x); C_p = C_x with the rows of X zeroed
+    gemm(rocblas_operation_none, rocblas_operation_none, ns, nx, ns, 1.0, T, ld, Z, ld, 0.0, C,
+         ldc);
+    LOBPCG_HIP(hipMemcpy2DAsync(C + (int64_t)nx * ldc, sizeof(double) * ldc, C,
+                                sizeof(double) * ldc, sizeof(double) * ns, nx,
+                                hipMemcpyDeviceToDevice, s_));
+    LOBPCG_HIP(hipMemset2DAsync(C + (int64_t)nx * ldc, sizeof(double) * ldc, 0,
+                                sizeof(double) * nx, nx, s_));
+    out.np = nx;
+    return out;
+  }
   const int m = ns - nx;
   const int na = nx - nc;
   const int np = std::min(na, m);

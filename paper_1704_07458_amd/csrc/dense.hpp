@@ -42,10 +42,13 @@ class Dense {
   // n_ident: the leading n_ident x n_ident block of GB is exactly the identity
   // (the X and P blocks of eqs. (12)-(14)); the Cholesky factor is then formed
   // blockwise and only the Schur complement of the W block is factored.
+  //
+  // basic_p: Algorithm 1's P instead of the P block of Algorithm 7:
+  // C_p = C_x with its first n_x rows zeroed (P = S(:, n_x+1:end) C(n_x+1:end, 1:n_x)), n_p = n_x.
   RROutput rr_modified(const double* GA, const double* GB, int64_t ldg, int ns, int nx, int nc,
                        bool use_ortho, bool literal_lq, double tau_skip, double* C, int64_t ldc,
                        double* theta, double* theta_p, int64_t ldtp, bool defer_p = false,
-                       int n_ident = 0);
+                       int n_ident = 0, bool basic_p = false);
 
   // Orders the main stream after the deferred P block (no-op when none).
   void join_p();

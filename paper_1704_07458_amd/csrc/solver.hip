@@ -140,6 +140,7 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   LOBPCG_CHECK(opt.ortho_mode == 0 || opt.ortho_mode == 1, LOBPCG_ERR_ARG,
                "ortho_mode must be 0 (orthoDrop) or 1 (ortho)");
   LOBPCG_CHECK(opt.largest == 0 || opt.largest == 1, LOBPCG_ERR_ARG, "largest must be 0/1");
+  LOBPCG_CHECK(opt.basic == 0 || opt.basic == 1, LOBPCG_ERR_ARG, "basic must be 0/1");
   // The k largest pairs of (A, B) are the k smallest of (-A, B).
   if (opt.largest)
     for (double& v : va) v = -v;
@@ -443,7 +444,10 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
                      rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
   // useOrtho starts false, or true from the start in the versions of
   // section 6 that orthogonalise every iteration
-  bool use_ortho = opt_.force_ortho != 0;
+  // Algorithm 1 (basic): no orthogonalisation, no locking of W, explicit Gram
+  // blocks, Algorithm 2's Rayleigh-Ritz, and its own P
+  const bool basic = opt_.basic != 0;
+  bool use_ortho = !basic && opt_.force_ortho != 0;
   int rc = LOBPCG_NOT_CONVERGED;
   int it = 0;
   for (it = 1; it <= maxit; ++it) {
@@ -451,7 +455,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     T* Sn = b.S[cur ^ 1].template as<T>();
     const int nv = nx + np;
     T* W = Sc + nv;
-    int nw = nx - nc;
+    int nw = basic ? nx : nx - nc;
     T* AWc = impl ? ASp(cur) + nv : AW;
     const int64_t ldAW = impl ? ldS : ldX;
     // W from the residual with the preconditioner applied (W0 = K^-1 R).
@@ -477,7 +481,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       phase_mark(3);
       gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AWc, ldAW, B ? BW : W,
               B ? ldX : ldS, GA, nv, GB, nv, ldg, nv);
-      if (opt_.implicit_gram) {
+      if (opt_.implicit_gram && !basic) {
         launch_fill_implicit(nx, np, theta, theta_p, nx, GA, use_ortho ? nullptr : GB, ldg, s_);
       } else {
         // The X and P blocks computed explicitly: [X P]^T [AX AP] and
@@ -499,11 +503,15 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       {
         const int tok = timer_.start(s_);
         // with the implicit blocks the X/P block of S^T B S is exactly I
-        o = dense_->rr_modified(GA, GB, ldg, ns, nx, nc, use_ortho, lq_literal, tau_skip, C, ldc,
-                                theta, theta_p, nx, true, opt_.implicit_gram ? nv : 0);
+        o = dense_->rr_modified(GA, GB, ldg, ns, nx, nc, use_ortho, lq_literal,
+                                basic ? 0.0 : tau_skip, C, ldc, theta, theta_p, nx, !basic,
+                                opt_.implicit_gram && !basic ? nv : 0, basic);
         timer_.stop(tok, 4, 0.0, s_);
       }
       if (!o.flipped) break;
+      if (basic)
+        throw Error(LOBPCG_ERR_BREAKDOWN,
+                    "Algorithm 1: S^T B S has no Cholesky factor (basic LOBPCG broke down)");
       // Cholesky rejected: switch to orthogonalised W for good and redo the step.
       use_ortho = true;
       if (info) {

@@ -44,6 +44,7 @@ def test_default_options_values():
     assert o.maxit == 2000 and o.precision == 0 and o.tau_ortho == 1e-12
     assert o.drop_factor == 10.0 and o.skip_factor == 10.0 and o.implicit_products == -1
     assert o.ortho_mode == 0 and o.force_ortho == 0 and o.implicit_gram == 1 and o.largest == 0
+    assert o.basic == 0
 
 
 def _create(A, k, B_=None, **kw):
@@ -106,6 +107,8 @@ def test_rejects_implicit_products_with_B_and_bad_ortho_mode():
     assert code == -1 and "ortho_mode" in msg
     code, msg = _create(A, 2, largest=2)
     assert code == -1 and "largest" in msg
+    code, msg = _create(A, 2, basic=2)
+    assert code == -1 and "basic" in msg
 
 
 def test_rejects_mismatched_B_and_nonfinite_values():

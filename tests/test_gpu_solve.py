@@ -277,6 +277,46 @@ def test_e1_first_iteration_orthodrop_against_ortho(lib, ortho_mode):
         assert abs(lam[0] - g["spurious_theta1"][0]) < 1e-8
 
 
+@pytest.mark.parametrize("idx", [0, 2])
+def test_basic_lobpcg_matches_oracle(lib, idx):
+    """Algorithm 1 (basic LOBPCG) against the oracle's: B = I and the FEM pencil."""
+    w = P.workload(idx, small=idx != 0)
+    s, info = _gpu_solve(w, basic=1)
+    assert info["converged"], info
+    A = w.A.to_scipy()
+    Bm = None if w.B is None else w.B.to_scipy()
+    pre = L.jacobi_precond(A) if w.precond == "jacobi" else None
+    ref = L.lobpcg_basic(A, w.X0, w.k, w.tol, B=Bm, precond=pre)
+    assert ref.converged
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    th = ref.theta[: w.k]
+    assert np.max(np.abs(lam - th) / np.abs(th)) <= EIG_RTOL
+    assert abs(info["iterations"] - ref.iterations) <= max(2, 0.1 * ref.iterations)
+    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], info["norm_B_est"]) <= RESID_TOL)
+
+
+def test_basic_lobpcg_breaks_down_on_the_section_4_1_example(lib):
+    """Algorithm 1 stops in its first iteration on the section 4.1 example (S = [X, W]
+    is rank deficient), where the default Algorithm 8 converges (n = 256)."""
+    from paper_1704_07458_amd import binding as B
+
+    n = 256
+    A = P.tridiag_1d(n, 1.0, 3.0, 1.0)
+    X0 = np.zeros((n, 2))
+    X0[0] = [1.0, 1.0]
+    X0[1] = [-1.0, 1.0]
+    X0 /= np.sqrt(2.0)
+    s = B.Solver(A, 2, block_size=2, basic=1)
+    with pytest.raises(RuntimeError, match="BREAKDOWN"):
+        s.solve(1e-10, X0)
+    s8 = B.Solver(A, 2, block_size=2)
+    info = s8.solve(1e-10, X0)
+    assert info["converged"] and info["ortho_switch_iter"] == 1
+    lam = s8.eigpairs(2)[0].cpu().numpy()
+    ex = np.linalg.eigvalsh(A.to_scipy().toarray())[:2]
+    assert np.max(np.abs(lam - ex) / ex) <= EIG_RTOL
+
+
 def test_largest_eigenpairs_closed_form_and_oracle(lib):
     """Section 2's reversed ordering: the 10 largest pairs of the 32^2 Laplacian."""
     w = P.workload(0)
