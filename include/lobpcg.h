@@ -108,7 +108,9 @@ typedef struct {
                                 projected problem as a standard one (never the Cholesky path of
                                 Algorithm 7), as the versions without skipped orthogonalisation */
   int32_t implicit_gram;     /* 1 = the X and P blocks of S^T A S and S^T B S from eqs. (12)-(14)
-                                (default); 0 = computed explicitly (with A P and B P) */
+                                (default), except in a step that follows a Cholesky factor
+                                with cond_1(R) > tau_skip^(-1/4) (see explicit_xp_steps);
+                                0 = always computed explicitly (with A P and B P) */
   int32_t basic;             /* 1 = Algorithm 1, the basic LOBPCG, instead of Algorithm 8: W for
                                 every column (no locking), every Gram block explicit,
                                 Algorithm 2's Rayleigh-Ritz with no condition test and
@@ -139,6 +141,11 @@ typedef struct {
   double norm_B_est;          /* same for B (1 when B = I) */
   double seconds_total;       /* wall time of lobpcg_solve */
   double seconds_phase[8];
+  int32_t explicit_xp_steps;  /* steps whose X and P Gram blocks were computed explicitly instead
+                                 of from eqs. (12)-(14) because the previous step's cond_1(R)
+                                 exceeded tau_skip^(-1/4): [X P] is B-orthonormal only to about
+                                 eps cond(R)^2 after such a step, and the implicit blocks would
+                                 hide that error from the next step's Cholesky test */
 } lobpcg_info;
 
 /* Fill *opt with the defaults documented above. */

@@ -86,6 +86,7 @@ class lobpcg_info(C.Structure):
         ("norm_B_est", C.c_double),
         ("seconds_total", C.c_double),
         ("seconds_phase", C.c_double * 8),
+        ("explicit_xp_steps", C.c_int32),
     ]
 
     def as_dict(self):

@@ -11,8 +11,9 @@
 //   update by default (explicit products), AW for the Gram blocks.
 //   BXP = [B X | B P], BW when B != I.
 // Projected matrices GA, GB (n_s x n_s, column-major, FP64): the X and P blocks
-// come from eqs. (12)-(14) (Theta, 0, Theta_p, I); only the W columns are
-// computed (Gram kernel), then Algorithm 7 runs on the device in FP64.
+// come from eqs. (12)-(14) (Theta, 0, Theta_p, I) except in the step after an
+// ill-conditioned Cholesky factor; only the W columns are computed (Gram
+// kernel), then Algorithm 7 runs on the device in FP64.
 #include "solver.hpp"
 
 #include <algorithm>
@@ -448,6 +449,17 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   // blocks, Algorithm 2's Rayleigh-Ritz, and its own P
   const bool basic = opt_.basic != 0;
   bool use_ortho = !basic && opt_.force_ortho != 0;
+  // The implicit X and P blocks (eqs. (12)-(14)) take [X P] as exactly
+  // B-orthonormal.  A Cholesky-based step leaves it so only to about
+  // eps cond(R)^2, and these errors compound from step to step while the
+  // cond(R) test, which sees the assumed identity block, stays blind to them:
+  // a long run with tiny residuals (cond(R) of 1e3-1e5 for tens of steps)
+  // can drift to O(1e-2) and lose eigenvectors.  After a step whose cond(R)
+  // exceeded tau_skip^(-1/4) (FP64: 4.6e3, at most about sqrt(eps / 10) of
+  // orthonormality error per step), the next step forms the X and P blocks
+  // explicitly, so that its factor and condition test see S^T B S itself.
+  const double cond_xp = tau_skip > 0.0 ? std::pow(tau_skip, -0.25) : HUGE_VAL;
+  bool xp_explicit = false;
   int rc = LOBPCG_NOT_CONVERGED;
   int it = 0;
   for (it = 1; it <= maxit; ++it) {
@@ -481,7 +493,9 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       phase_mark(3);
       gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AWc, ldAW, B ? BW : W,
               B ? ldX : ldS, GA, nv, GB, nv, ldg, nv);
-      if (opt_.implicit_gram && !basic) {
+      const bool implicit_xp = opt_.implicit_gram && !basic && !xp_explicit;
+      if (info && opt_.implicit_gram && !basic && xp_explicit) info->explicit_xp_steps++;
+      if (implicit_xp) {
         launch_fill_implicit(nx, np, theta, theta_p, nx, GA, use_ortho ? nullptr : GB, ldg, s_);
       } else {
         // The X and P blocks computed explicitly: [X P]^T [AX AP] and
@@ -505,7 +519,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
         // with the implicit blocks the X/P block of S^T B S is exactly I
         o = dense_->rr_modified(GA, GB, ldg, ns, nx, nc, use_ortho, lq_literal,
                                 basic ? 0.0 : tau_skip, C, ldc, theta, theta_p, nx, !basic,
-                                opt_.implicit_gram && !basic ? nv : 0, basic);
+                                implicit_xp ? nv : 0, basic);
         timer_.stop(tok, 4, 0.0, s_);
       }
       if (!o.flipped) break;
@@ -522,6 +536,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       nw = ortho_drop<T>(b, B, W, ldS, nw, Sc, ldS, MV, ldmv, nv, tau_ortho, eps, info);
     }
     if (o.flipped) throw Error(LOBPCG_ERR_BREAKDOWN, "Rayleigh-Ritz failed after orthoDrop");
+    xp_explicit = !use_ortho && o.cond > cond_xp;
     const int ns = nv + nw;
     const int npn = o.np;
     // Basis update [X, P] = S [C_x, C_p]: X now, P once the P block is done.
