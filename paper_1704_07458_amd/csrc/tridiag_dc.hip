@@ -32,7 +32,7 @@ namespace lobpcg {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kDcLeaf = 32;
+constexpr int kDcLeaf = 16;
 constexpr int kDcMaxN = 512;
 constexpr int kDcThreads = 256;
 constexpr int kDcQlIter = 60;
