@@ -127,3 +127,38 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.lobpcg_solve(None, 1e-8, None, 0, B.PRECOND_FN(), None, None) == -1
     assert lib.lobpcg_eigpairs(None, 1, None, None, 1, None, 0) == -1
     lib.lobpcg_destroy(None)
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the header's field names, offsets and size.
+
+    A C program compiled against include/lobpcg.h prints offsetof for each field the
+    binding declares and sizeof for each structure; a field added to one side only, or
+    in a different order, changes an offset or the size.
+    """
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [B.lobpcg_csr, B.lobpcg_options, B.lobpcg_info, B.lobpcg_kernel_stat]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lobpcg.h"', "int main(void) {"]
+    for S in structs:
+        n = S.__name__
+        lines.append(f'  printf("{n} sizeof %zu\\n", sizeof({n}));')
+        for f, _ in S._fields_:
+            lines.append(f'  printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out.splitlines())}
+    for S in structs:
+        n = S.__name__
+        assert got[(n, "sizeof")] == C.sizeof(S), n
+        for f, _ in S._fields_:
+            assert got[(n, f)] == getattr(S, f).offset, (n, f)
