@@ -410,6 +410,11 @@ def main():
             "n": w.A.n, "k": w.k, "n_x": w.n_x, "tol": w.tol, "precond": "jacobi",
         },
         "iterations": iters64,
+        # steps whose X/P Gram blocks were formed explicitly after an
+        # ill-conditioned Cholesky factor, and the step of the switch to
+        # orthogonalised W (-1: never)
+        "explicit_xp_steps": infos64[-1]["explicit_xp_steps"],
+        "ortho_switch_iter": infos64[-1]["ortho_switch_iter"],
         "iters_per_s": iters64 / t64,
         "max_rho": rho64,
         "eig_rel_err_vs_closed_form": err64,
