@@ -494,7 +494,8 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AWc, ldAW, B ? BW : W,
               B ? ldX : ldS, GA, nv, GB, nv, ldg, nv);
       const bool implicit_xp = opt_.implicit_gram && !basic && !xp_explicit;
-      if (info && opt_.implicit_gram && !basic && xp_explicit) info->explicit_xp_steps++;
+      if (info && attempt == 0 && opt_.implicit_gram && !basic && xp_explicit)
+        info->explicit_xp_steps++;
       if (implicit_xp) {
         launch_fill_implicit(nx, np, theta, theta_p, nx, GA, use_ortho ? nullptr : GB, ldg, s_);
       } else {
