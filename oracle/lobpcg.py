@@ -12,7 +12,10 @@ is checked against).
 
 Readings taken where the paper is silent or ambiguous (each is also an option
 of the HIP path, with the same default):
-  R1  the sketch Omega of section 4.3 is the transposed Gaussian initial block.
+  R1  the sketch Omega of section 4.3 is an n_x x n Gaussian matrix drawn from
+      the seed by a counter-based generator (oracle/philox.py, stream 1),
+      independent of the initial block, so that a warm start from converged
+      vectors does not bias the estimate.
   R2  the preconditioner K^-1 of section 2 / Algorithm 1 is applied to the
       residual wherever Algorithm 8 uses R (W0 = K^-1 R).
   R3  Cholesky is declared unreliable (section 5.3) when cond_1(R)^3 * tau_skip
@@ -35,6 +38,8 @@ from typing import Callable, List, Optional
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+
+from . import philox
 
 EPS64 = np.finfo(np.float64).eps
 
@@ -407,6 +412,7 @@ def lobpcg(
     maxit: int = 2000,
     tols: Optional[Tolerances] = None,
     Omega_T: Optional[np.ndarray] = None,
+    sketch_seed: int = 0,
     literal_lq: bool = False,
     exact_norms: Optional[tuple] = None,
     force_ortho: bool = False,
@@ -419,7 +425,8 @@ def lobpcg(
     A, B: sparse symmetric (B SPD, None = I).  X0: n x n_x initial block.
     k (= n_v): number of wanted eigenpairs, n_v <= n_x.  tol: tau of eq. (9).
     precond: W0 = precond(R) applies K^-1 column-wise (None = identity).
-    Omega_T: m x k sketch for the norm estimate (default X0, reading R1).
+    Omega_T: n x m sketch for the norm estimate; default: the n x n_x Gaussian
+    block of philox.sketch(sketch_seed, n, n_x) (reading R1).
     exact_norms: (||A||_2, ||B||_2) to use instead of the sketch.
     force_ortho, ortho_kind: the section 6 ablation of the algorithm's
     versions.  force_ortho orthogonalises W from the first iteration and never
@@ -454,7 +461,7 @@ def lobpcg(
     if exact_norms is not None:
         normA, normB = exact_norms
     else:
-        Om = X0 if Omega_T is None else Omega_T
+        Om = philox.sketch(sketch_seed, n, n_x) if Omega_T is None else Omega_T
         normA = sketch_norm(Aop, Om)
         normB = 1.0 if Bop.is_identity else sketch_norm(Bop, Om)
 
@@ -547,7 +554,7 @@ class BasicResult:
 
 def lobpcg_basic(A, X0: np.ndarray, k: int, tol: float, B=None,
                  precond: Optional[Callable[[np.ndarray], np.ndarray]] = None,
-                 maxit: int = 2000) -> BasicResult:
+                 maxit: int = 2000, sketch_seed: int = 0) -> BasicResult:
     """Algorithm 1, the basic LOBPCG, with Algorithm 2 for every Rayleigh-Ritz.
 
     S = [X, W, P] with W = K^-1 R for all n_x columns (no locking), every block
@@ -562,8 +569,9 @@ def lobpcg_basic(A, X0: np.ndarray, k: int, tol: float, B=None,
     Kinv = precond if precond is not None else (lambda R: R.copy())
     X0 = np.asarray(X0, dtype=np.float64)
     n, n_x = X0.shape
-    normA = sketch_norm(Aop, X0)
-    normB = 1.0 if Bop.is_identity else sketch_norm(Bop, X0)
+    Om = philox.sketch(sketch_seed, n, n_x)
+    normA = sketch_norm(Aop, Om)
+    normB = 1.0 if Bop.is_identity else sketch_norm(Bop, Om)
 
     def rr(S):
         AS, BS = Aop(S), Bop(S)
