@@ -97,7 +97,9 @@ typedef struct {
   double skip_factor;        /* tau_skip = skip_factor * eps; Cholesky of S^T B S is rejected when
                                 cond_1(R)^3 * tau_skip > 1 (section 5.3); <= 0: 10 */
   double fp32_tol;           /* criterion (9) threshold ending the FP32 phase; <= 0: 1e-5 */
-  uint64_t seed;             /* seed of the Gaussian initial block when X0 is NULL */
+  uint64_t seed;             /* seed of the counter-based Gaussian generator (Philox-4x32-10,
+                                Box-Muller): stream 0 gives the initial block when X0 is
+                                NULL, stream 1 the sketch Omega of section 4.3 */
   void* stream;              /* hipStream_t for all work; NULL = default stream */
   /* Switches for the version ladder of section 6 (Figure 2); the defaults give
    * Algorithm 8. */
@@ -122,6 +124,19 @@ typedef struct {
                                 (-A, B); lobpcg_eigpairs then returns descending values.  The
                                 Jacobi preconditioner is built from -A (its diagonal shifted
                                 positive).  lobpcg_adjoint rejects this mode (LOBPCG_ERR_ARG) */
+  /* Device-memory hooks.  When both are non-NULL every device buffer the handle
+   * owns (the matrices, the blocks, the projected-problem and rocBLAS /
+   * rocSOLVER workspaces, the adjoint's temporaries) comes from
+   * dev_alloc(bytes, alloc_user), which returns a device pointer aligned to at
+   * least 256 bytes or NULL on failure (the call then fails with
+   * LOBPCG_ERR_ALLOC), and is returned through dev_free(ptr, alloc_user) when
+   * the handle no longer needs it (at the latest in lobpcg_destroy).  Memory is
+   * used only on `stream` and, for Algorithm 7's P block, on one internal
+   * stream that the handle synchronises before freeing.  Both NULL: hipMalloc /
+   * hipFree.  Giving only one of them is LOBPCG_ERR_ARG. */
+  void* (*dev_alloc)(size_t bytes, void* alloc_user);
+  void (*dev_free)(void* ptr, void* alloc_user);
+  void* alloc_user;
 } lobpcg_options;
 
 /* Per-solve statistics. seconds_phase: 0 sparse products, 1 preconditioner,
@@ -137,7 +152,9 @@ typedef struct {
   int32_t svqb_calls;         /* svqb + svqbDrop passes inside orthogonalisation */
   int32_t ortho_calls;        /* orthoDrop (or ortho, ortho_mode 1) calls */
   int32_t flips;              /* Cholesky rejections (0 or 1 per phase) */
-  double norm_A_est;          /* ||A||_2 lower bound from the Gaussian sketch (section 4.3) */
+  double norm_A_est;          /* ||A||_2 lower bound ||Omega A||_F / ||Omega||_F from the
+                                 Gaussian sketch of section 4.3 (Omega: n_x x n, stream 1 of
+                                 opt.seed; independent of X0, formed once per handle) */
   double norm_B_est;          /* same for B (1 when B = I) */
   double seconds_total;       /* wall time of lobpcg_solve */
   double seconds_phase[8];
@@ -146,6 +163,9 @@ typedef struct {
                                  exceeded tau_skip^(-1/4): [X P] is B-orthonormal only to about
                                  eps cond(R)^2 after such a step, and the implicit blocks would
                                  hide that error from the next step's Cholesky test */
+  int32_t fp32_fallback;      /* precision split: 1 when the FP32 phase broke down (or met a
+                                 non-finite value) and the FP64 phase took over from the last
+                                 finite block (or from X0) */
 } lobpcg_info;
 
 /* Fill *opt with the defaults documented above. */
@@ -163,7 +183,7 @@ int lobpcg_create(lobpcg_t* out, const lobpcg_csr* A, const lobpcg_csr* B, int32
 /* Run Algorithm 8 to criterion (9) with threshold tol.
  * X0: row-major n x n_x initial block (ld = n_x), host memory when
  * x0_on_device = 0, device memory when 1; NULL = Gaussian N(0,1) block from
- * opt.seed.  X0 is copied.  The sketch Omega of section 4.3 is X0^T.
+ * opt.seed (stream 0).  X0 is copied.
  * K: preconditioner callback (used when opt.precond = 2), K_user its argument.
  * info: may be NULL.
  * Returns LOBPCG_OK, LOBPCG_NOT_CONVERGED (maxit reached), or an error. */

@@ -61,6 +61,23 @@ def fem_q1_3d(N: int) -> np.ndarray:
     return np.sort((m[:, None, None] + m[None, :, None] + m[None, None, :]).ravel())
 
 
+def dirichlet_3d_modes(N: int, count: int):
+    """Eigenvectors of the 3D 7-point Dirichlet Laplacian on N^3 for its `count`
+    smallest eigenvalues: the tensor sine modes s_i(x) s_j(y) s_l(z) (grid index
+    x + N y + N^2 z), orthonormal, with their eigenvalues e_i + e_j + e_l.  When
+    count cuts a degenerate cluster the members kept are an arbitrary subset, so
+    callers take count at a cluster boundary."""
+    e = dirichlet_1d(N)
+    lam = (e[:, None, None] + e[None, :, None] + e[None, None, :]).ravel()  # index i*N*N + j*N + l
+    order = np.argsort(lam, kind="stable")[:count]
+    S = np.stack([sine_mode(N, i) for i in range(1, N + 1)], axis=1)  # S[:, i-1] = s_i
+    V = np.empty((N ** 3, count))
+    for c, q in enumerate(order):
+        i, j, l = q // (N * N), (q // N) % N, q % N
+        V[:, c] = np.kron(S[:, l], np.kron(S[:, j], S[:, i]))
+    return V, lam[order]
+
+
 def smallest(values: np.ndarray, count: int) -> np.ndarray:
     """The `count` smallest values (full sort; for grids up to 96^3 this is cheap)."""
     return np.sort(values)[:count]

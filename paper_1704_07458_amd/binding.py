@@ -49,6 +49,10 @@ class lobpcg_csr(C.Structure):
     ]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class lobpcg_options(C.Structure):
     _fields_ = [
         ("block_size", C.c_int32),
@@ -69,6 +73,9 @@ class lobpcg_options(C.Structure):
         ("implicit_gram", C.c_int32),
         ("basic", C.c_int32),
         ("largest", C.c_int32),
+        ("dev_alloc", ALLOC_FN),
+        ("dev_free", FREE_FN),
+        ("alloc_user", C.c_void_p),
     ]
 
 
@@ -87,6 +94,7 @@ class lobpcg_info(C.Structure):
         ("seconds_total", C.c_double),
         ("seconds_phase", C.c_double * 8),
         ("explicit_xp_steps", C.c_int32),
+        ("fp32_fallback", C.c_int32),
     ]
 
     def as_dict(self):
@@ -229,11 +237,49 @@ def _csr_struct(M, keep: list):
     return s
 
 
+class TorchAllocator:
+    """dev_alloc / dev_free hooks that take the handle's device memory from torch's
+    caching allocator on the given stream (lobpcg_options.dev_alloc)."""
+
+    def __init__(self, stream=None):
+        import torch
+
+        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = self.stream.device
+        self.live = 0  # bytes currently handed out
+        self._sizes = {}
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            p = int(self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                             self.stream))
+            self._sizes[p] = int(nbytes)
+            self.live += int(nbytes)
+            return p
+        except Exception:
+            return None
+
+    def _free(self, ptr, user):
+        try:
+            self.live -= self._sizes.pop(int(ptr), 0)
+            self._torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+
 class Solver:
-    """Handle around lobpcg_create / solve / eigpairs / adjoint / destroy."""
+    """Handle around lobpcg_create / solve / eigpairs / adjoint / destroy.
+
+    allocator: "torch" (default) routes every device allocation of the handle
+    through torch's caching allocator on the current stream (the dev_alloc /
+    dev_free hooks of lobpcg_options); "hip" lets the library call hipMalloc.
+    """
 
     def __init__(self, A, k: int, B=None, precond: str = "none", precision: str = "fp64",
-                 block_size: int = 0, maxit: int = 2000, **opts):
+                 block_size: int = 0, maxit: int = 2000, allocator: str = "torch", **opts):
         lib = load()
         o = default_options()
         o.block_size = block_size
@@ -248,6 +294,13 @@ class Solver:
         for key, val in opts.items():
             setattr(o, key, val)
         o.stream = _stream()
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = TorchAllocator()
+            o.dev_alloc = self._alloc.alloc_fn
+            o.dev_free = self._alloc.free_fn
+        elif allocator != "hip":
+            raise ValueError("allocator must be 'torch' or 'hip'")
         keep: list = []
         a = _csr_struct(A, keep)
         b = _csr_struct(B, keep) if B is not None else None

@@ -257,7 +257,13 @@ int lobpcg_rr_step(int32_t n_s, int32_t n_x, int32_t n_c, int32_t use_ortho, int
     lobpcg::RROutput o = d.rr_modified(GA, GB, ldg, n_s, n_x, n_c, use_ortho != 0,
                                        lq_literal != 0, tau_skip, C, ldc, theta, theta_p, n_x,
                                        false, n_ident);
+    int32_t stalled = 0;
+    LOBPCG_HIP(hipMemcpyAsync(&stalled, d.status_word(), sizeof(int32_t), hipMemcpyDeviceToHost,
+                              as_stream(stream)));
     LOBPCG_HIP(hipStreamSynchronize(as_stream(stream)));
+    LOBPCG_CHECK(stalled != 2, LOBPCG_ERR_NONFINITE, "non-finite projected matrix");
+    LOBPCG_CHECK(stalled == 0, LOBPCG_ERR_BREAKDOWN,
+                 "projected eigenproblem: an implicit QL leaf did not converge");
     if (n_p) *n_p = o.np;
     if (flipped) *flipped = o.flipped ? 1 : 0;
     if (cond) *cond = o.cond;

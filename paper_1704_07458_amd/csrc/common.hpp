@@ -33,16 +33,54 @@ struct Error : public std::runtime_error {
     if (!(cond)) throw ::lobpcg::Error((code), (msg)); \
   } while (0)
 
-// Owning device allocation (hipMalloc / hipFree).
+// Device allocator of a solver handle: the caller's hooks of lobpcg_options
+// (dev_alloc / dev_free / alloc_user) or, when they are NULL, hipMalloc /
+// hipFree.
+struct DevAllocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* user = nullptr;
+  bool hooked() const { return alloc != nullptr && free != nullptr; }
+};
+
+// The allocator DevBuf::alloc uses on this thread (null = hipMalloc); set for
+// the extent of a solver call by AllocatorScope.
+inline const DevAllocator*& current_allocator() {
+  thread_local const DevAllocator* a = nullptr;
+  return a;
+}
+
+class AllocatorScope {
+ public:
+  explicit AllocatorScope(const DevAllocator* a) : prev_(current_allocator()) {
+    current_allocator() = a;
+  }
+  ~AllocatorScope() { current_allocator() = prev_; }
+  AllocatorScope(const AllocatorScope&) = delete;
+  AllocatorScope& operator=(const AllocatorScope&) = delete;
+
+ private:
+  const DevAllocator* prev_;
+};
+
+// Owning device allocation.  The allocator in force when the buffer is
+// allocated (current_allocator(), else hipMalloc) is remembered and frees it.
 class DevBuf {
  public:
   DevBuf() = default;
   explicit DevBuf(size_t bytes) { alloc(bytes); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), a_(o.a_) { o.p_ = nullptr; o.n_ = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    if (this != &o) {
+      release();
+      p_ = o.p_;
+      n_ = o.n_;
+      a_ = o.a_;
+      o.p_ = nullptr;
+      o.n_ = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
@@ -50,11 +88,20 @@ class DevBuf {
   void alloc(size_t bytes) {
     release();
     if (bytes == 0) return;
-    hipError_t e = hipMalloc(&p_, bytes);
-    if (e != hipSuccess) {
-      p_ = nullptr;
-      throw Error(LOBPCG_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
-                                        hipGetErrorString(e));
+    const DevAllocator* a = current_allocator();
+    if (a && a->hooked()) {
+      a_ = *a;
+      p_ = a_.alloc(bytes, a_.user);
+      if (!p_)
+        throw Error(LOBPCG_ERR_ALLOC, "dev_alloc of " + std::to_string(bytes) + " bytes failed");
+    } else {
+      a_ = DevAllocator{};
+      hipError_t e = hipMalloc(&p_, bytes);
+      if (e != hipSuccess) {
+        p_ = nullptr;
+        throw Error(LOBPCG_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) +
+                                          " bytes failed: " + hipGetErrorString(e));
+      }
     }
     n_ = bytes;
   }
@@ -63,7 +110,10 @@ class DevBuf {
     if (bytes > n_) alloc(bytes);
   }
   void release() {
-    if (p_) (void)hipFree(p_);
+    if (p_) {
+      if (a_.hooked()) a_.free(p_, a_.user);
+      else (void)hipFree(p_);
+    }
     p_ = nullptr;
     n_ = 0;
   }
@@ -75,6 +125,7 @@ class DevBuf {
  private:
   void* p_ = nullptr;
   size_t n_ = 0;
+  DevAllocator a_{};
 };
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }

@@ -5,7 +5,6 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
-#include <cstdlib>
 #include <cmath>
 #include <string>
 
@@ -28,9 +27,7 @@ namespace lobpcg {
 // rows in 16-byte pairs.
 Dense::Dense(int nsmax, int nxmax, hipStream_t s)
     : nsmax_(nsmax + (nsmax & 1)), nxmax_(nxmax), s_(s) {
-  if (const char* e = std::getenv("LOBPCG_EIGENSOLVER")) eig_ = std::atoi(e);
-  kTridiagMaxN = std::min(512, sytrd_max_n());
-  if (const char* e = std::getenv("LOBPCG_TRIDIAG_MAX_N")) kTridiagMaxN = std::atoi(e);
+  kTridiagMaxN = std::min(sytrd_max_n(), tridiag_dc_max_n());
   LOBPCG_ROCBLAS(rocblas_create_handle(&h_));
   LOBPCG_ROCBLAS(rocblas_set_stream(h_, s_));
   // Reproducible results: no split-K GEMM kernels that accumulate with
@@ -58,6 +55,7 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s)
   th2_.alloc(sizeof(double) * nsmax_);
   scale_.alloc(sizeof(double) * nsmax_);
   info_.alloc(sizeof(int32_t) * 8);
+  LOBPCG_HIP(hipMemsetAsync(info_.get(), 0, sizeof(int32_t) * 8, s_));
   cond_.alloc(sizeof(double) * 2);
   sinfo_.alloc(sizeof(int32_t) * 2);
   dcY_.alloc(sq);
@@ -67,6 +65,42 @@ Dense::Dense(int nsmax, int nxmax, hipStream_t s)
   dcr_.alloc(sizeof(double) * 64);
   LOBPCG_HIP(hipHostMalloc((void**)&hinfo_, sizeof(int32_t) * 8, hipHostMallocDefault));
   LOBPCG_HIP(hipHostMalloc((void**)&hcond_, sizeof(double) * 2, hipHostMallocDefault));
+  // The library routines' device workspace comes from this object's allocator
+  // too: size it for the largest projected problem, then hand it to the handles.
+  lib_ws_.alloc(library_workspace_bytes(h_));
+  LOBPCG_ROCBLAS(rocblas_set_workspace(h_, lib_ws_.get(), lib_ws_.size()));
+  lib_ws2_.alloc(library_workspace_bytes(h2_));
+  LOBPCG_ROCBLAS(rocblas_set_workspace(h2_, lib_ws2_.get(), lib_ws2_.size()));
+}
+
+// Device workspace the rocBLAS / rocSOLVER calls of this object need at the
+// largest sizes (their device-memory size query); the buffers passed are real
+// ones of the right sizes, nothing is computed.
+size_t Dense::library_workspace_bytes(rocblas_handle h) {
+  const int n = nsmax_;
+  const int64_t ld = nsmax_;
+  double* A = H_.as<double>();
+  double* w = d_.as<double>();
+  double* e = E_.as<double>();
+  int32_t* info = info_.as<int32_t>();
+  size_t bytes = 0;
+  LOBPCG_ROCBLAS(rocblas_start_device_memory_size_query(h));
+  (void)rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, A, (rocblas_int)ld, w,
+                         e, info);
+  (void)rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, w, e, A, (rocblas_int)ld, info);
+  (void)rocsolver_dpotrf(h, rocblas_fill_upper, n, A, (rocblas_int)ld, info);
+  (void)rocsolver_dtrtri(h, rocblas_fill_upper, rocblas_diagonal_non_unit, n, A, (rocblas_int)ld,
+                         info);
+  (void)rocsolver_dgeqrf(h, n, nxmax_, A, (rocblas_int)ld, tau_.as<double>());
+  (void)rocsolver_dorgqr(h, n, nxmax_, nxmax_, A, (rocblas_int)ld, tau_.as<double>());
+  const double one = 1.0, zero = 0.0;
+  (void)rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &one, A,
+                      (rocblas_int)ld, A, (rocblas_int)ld, &zero, R_.as<double>(), (rocblas_int)ld);
+  (void)rocblas_dgeam(h, rocblas_operation_transpose, rocblas_operation_none, n, n, &one, A,
+                      (rocblas_int)ld, &zero, R_.as<double>(), (rocblas_int)ld, R_.as<double>(),
+                      (rocblas_int)ld);
+  LOBPCG_ROCBLAS(rocblas_stop_device_memory_size_query(h, &bytes));
+  return std::max<size_t>(bytes, 256);
 }
 
 Dense::~Dense() {
@@ -109,16 +143,7 @@ static void copy_cm(int m, int n, const double* src, int64_t lds, double* dst, i
 
 void Dense::syev(int n, double* A, int64_t lda, double* w) {
   int32_t* dinfo = info_.as<int32_t>() + 2;
-  if (eig_ == 2) {
-    // Jacobi (sorted ascending), tolerance at the level of rounding.
-    double* resid = cond_.as<double>() + 1;
-    LOBPCG_ROCBLAS(rocsolver_dsyevj(h_, rocblas_esort_ascending, rocblas_evect_original,
-                                    rocblas_fill_upper, n, A, (rocblas_int)lda, 0.0, resid, 100,
-                                    dinfo + 1, w, dinfo));
-  } else if (eig_ == 1) {
-    LOBPCG_ROCBLAS(rocsolver_dsyevdj(h_, rocblas_evect_original, rocblas_fill_upper, n, A,
-                                     (rocblas_int)lda, w, dinfo));
-  } else if ((eig_ == 0 || eig_ == 4) && n <= kTridiagMaxN && n >= 2) {
+  if (n >= 2 && n <= kTridiagMaxN) {
     // Householder tridiagonalisation in one workgroup (kernels.hip), then
     // divide and conquer on the tridiagonal and the back-transformation Q Z_T.
     double* e = E_.as<double>();
@@ -130,14 +155,9 @@ void Dense::syev(int n, double* A, int64_t lda, double* w) {
       timer_->stop(tok, 5, 4.0 / 3.0 * n * (double)n * n, s_);
       tok = timer_->start(s_);
     }
-    if (eig_ == 0 && n <= tridiag_dc_max_n()) {
-      tridiag_dc(n, w, e, w, Z, nsmax_, Mt_.as<double>(), ZQ_.as<double>(), Qs_.as<double>(),
-                 dcY_.as<double>(), dcv_.as<double>(), dci_.as<int32_t>(), dcw_.as<double>(),
-                 dcr_.as<double>(), h_, s_);
-    } else {
-      LOBPCG_ROCBLAS(rocsolver_dstedc(h_, rocblas_evect_tridiagonal, n, w, e, Z,
-                                      (rocblas_int)nsmax_, dinfo));
-    }
+    tridiag_dc(n, w, e, w, Z, nsmax_, Mt_.as<double>(), ZQ_.as<double>(), Qs_.as<double>(),
+               dcY_.as<double>(), dcv_.as<double>(), dci_.as<int32_t>(), dcw_.as<double>(),
+               dcr_.as<double>(), status_word(), h_, s_);
     if (timer_) {
       timer_->stop(tok, 6, 0.0, s_);
       tok = timer_->start(s_);

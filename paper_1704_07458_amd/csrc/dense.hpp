@@ -63,12 +63,12 @@ class Dense {
   rocblas_handle handle() const { return h_; }
   hipStream_t stream() const { return s_; }
 
-  // Eigen-solver selection for the projected problem: 0 = automatic (the
-  // one-workgroup tridiagonalisation, divide and conquer on the tridiagonal and
-  // the back-transformation up to kTridiagMaxN, syevd above), 1 = syevdj,
-  // 2 = syevj, 3 = syevd always, 4 = as 0 with rocSOLVER's stedc for the
-  // tridiagonal.  The environment variable LOBPCG_EIGENSOLVER overrides it.
-  void set_eigensolver(int which) { eig_ = which; }
+  // Device status word that the tridiagonal eigensolver sets to 1 when an
+  // implicit-QL leaf fails to converge (never cleared here; zero before use).
+  // Default: a word of this object, zeroed at construction.
+  int32_t* status_word() const { return status_ ? status_ : info_.as<int32_t>() + 7; }
+  void set_status_word(int32_t* w) { status_ = w; }
+
   // Kernel-class timing of the tridiagonalisation (kind 5), the tridiagonal
   // eigensolver (kind 6) and the QR / back-transformation kernels (kind 7).
   void set_timer(KernelTimer* t) { timer_ = t; }
@@ -77,7 +77,11 @@ class Dense {
   void gemm(rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double alpha,
             const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
             int64_t ldc);
+  // Eigenpairs of a symmetric n x n matrix (column-major, lda), ascending:
+  // the one-workgroup tridiagonalisation, divide and conquer and
+  // back-transformation for 2 <= n <= kTridiagMaxN, rocSOLVER's syevd otherwise.
   void syev(int n, double* A, int64_t lda, double* w);
+  size_t library_workspace_bytes(rocblas_handle h);
   // Algorithm 7's P block (from Z and T = D R^-1 in place) on stream s with handle h.
   void rr_p_block(const double* Z, int ns, int nx, int nc, bool literal_lq, const double* theta,
                   double* C, int64_t ldc, double* theta_p, int64_t ldtp, hipStream_t s,
@@ -93,12 +97,13 @@ class Dense {
   rocblas_handle h2_ = nullptr;
   hipEvent_t ev_z_ = nullptr, ev_p_ = nullptr;
   bool p_pending_ = false;
-  int eig_ = 0;
   KernelTimer* timer_ = nullptr;
+  int32_t* status_ = nullptr;
   int kTridiagMaxN = 512;
   // scratch (column-major, leading dimension nsmax_)
   DevBuf H_, R_, Ri_, T1_, Mt_, ZQ_, Qs_, d_, E_, tau_, info_, cond_, th2_, scale_, sinfo_;
   DevBuf dcY_, dcv_, dci_, dcw_, dcr_;  // divide-and-conquer workspace
+  DevBuf lib_ws_, lib_ws2_;  // rocBLAS / rocSOLVER device workspace of h_ and h2_
   int32_t* hinfo_ = nullptr;  // pinned host status words
   double* hcond_ = nullptr;
 };

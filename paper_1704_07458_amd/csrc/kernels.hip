@@ -702,12 +702,15 @@ __device__ __forceinline__ void philox_round(uint32_t c[4], const uint32_t k[2])
   c[3] = lo0;
 }
 
+// Element pair (2q, 2q + 1) of the row-major block comes from the counter
+// (q mod 2^32, q div 2^32, stream, 0) under the key (seed mod 2^32, seed div
+// 2^32); stream 0 is the initial block, 1 the sketch of section 4.3.
 __global__ void gaussian_kernel(int64_t n, int ncols, double* __restrict__ dst, int64_t ldd,
-                                uint64_t seed) {
+                                uint64_t seed, uint32_t stream) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = n * ncols;
   if (2 * idx >= total) return;
-  uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), 0u, 0u};
+  uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), stream, 0u};
   uint32_t k[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   for (int r = 0; r < 10; ++r) {
     philox_round(c, k);
@@ -1627,11 +1630,12 @@ void launch_copy2d_reverse(int64_t n, int ncols, const T* src, int64_t lds, T* d
   LOBPCG_HIP(hipGetLastError());
 }
 
-void launch_gaussian(int64_t n, int ncols, double* dst, int64_t ldd, uint64_t seed, hipStream_t s) {
+void launch_gaussian(int64_t n, int ncols, double* dst, int64_t ldd, uint64_t seed,
+                     uint32_t stream, hipStream_t s) {
   const int64_t pairs = (n * ncols + 1) / 2;
   if (pairs == 0) return;
   hipLaunchKernelGGL(gaussian_kernel, dim3(blocks_for(pairs)), dim3(256), 0, s, n, ncols, dst, ldd,
-                     seed);
+                     seed, stream);
   LOBPCG_HIP(hipGetLastError());
 }
 

@@ -63,9 +63,14 @@ template <typename T>
 void launch_copy2d_reverse(int64_t n, int ncols, const T* src, int64_t lds, T* dst, int64_t ldd,
                            hipStream_t s);
 
-// Fill a row-major n x ncols block with Gaussian N(0,1) values from a
-// counter-based generator keyed by seed (Philox-style 4x32 rounds + Box-Muller).
-void launch_gaussian(int64_t n, int ncols, double* dst, int64_t ldd, uint64_t seed, hipStream_t s);
+// Fill a row-major n x ncols block with Gaussian N(0,1) values: Philox-4x32-10
+// (Salmon et al., SC'11) keyed by seed, counter (pair index, stream, 0), then
+// Box-Muller on 53-bit uniforms.  Streams: 0 = the initial block drawn when
+// none is given, 1 = the norm sketch of section 4.3.
+constexpr uint32_t kStreamInitialBlock = 0;
+constexpr uint32_t kStreamSketch = 1;
+void launch_gaussian(int64_t n, int ncols, double* dst, int64_t ldd, uint64_t seed,
+                     uint32_t stream, hipStream_t s);
 
 // ---- small dense FP64 helpers (column-major, single workgroup or tiny grids) ----
 

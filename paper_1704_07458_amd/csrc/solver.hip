@@ -122,6 +122,12 @@ void Blocks<T>::alloc(int64_t n, int64_t ldS, int64_t ldX, bool haveB, bool impl
 
 Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_options& opt)
     : opt_(opt) {
+  LOBPCG_CHECK((opt.dev_alloc == nullptr) == (opt.dev_free == nullptr), LOBPCG_ERR_ARG,
+               "dev_alloc and dev_free must be given together");
+  alloc_.alloc = opt.dev_alloc;
+  alloc_.free = opt.dev_free;
+  alloc_.user = opt.alloc_user;
+  AllocatorScope scope(&alloc_);
   s_ = static_cast<hipStream_t>(opt.stream);
   std::vector<int64_t> rp;
   std::vector<int32_t> ci;
@@ -172,7 +178,7 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   theta_p_.alloc(sizeof(double) * (size_t)nx_ * nx_);
   rho_.alloc(sizeof(double) * nx_);
   nc_.alloc(sizeof(int32_t) * 4);
-  nrm_.alloc(sizeof(double) * 8 * nx_);
+  nrm_.alloc(sizeof(double) * (8 * nx_ + 8));
   X0buf_.alloc(sizeof(double) * (size_t)n_ * nx_);
   int64_t ws = gram_workspace_bound(n_, nsmax_, 2 * nx_);
   ws = std::max(ws, residual_workspace_bytes(n_, nx_));
@@ -186,10 +192,41 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   }
   dense_.reset(new Dense(nsmax_, nx_, s_));
   dense_->set_timer(&timer_);
+  // nc_[2]: set by the tridiagonal eigensolver when a QL leaf did not
+  // converge; read with n_c once per iteration
+  dense_->set_status_word(nc_.as<int32_t>() + 2);
   LOBPCG_HIP(hipHostMalloc((void**)&hbuf_, sizeof(int32_t) * 8, hipHostMallocDefault));
   LOBPCG_HIP(hipHostMalloc((void**)&hdbl_, sizeof(double) * 8, hipHostMallocDefault));
   LOBPCG_HIP(hipEventCreateWithFlags(&ev_nc_, hipEventDisableTiming));
-  LOBPCG_HIP(hipStreamSynchronize(s_));
+  sketch_norms();
+}
+
+// Section 4.3: ||A||_2 >= ||Omega A||_F / ||Omega||_F for a Gaussian Omega
+// (n_x x n), here stream 1 of the seeded generator, independent of the initial
+// block (a warm start from converged vectors would bias an estimate taken on
+// it toward the smallest eigenvalues).  The estimate depends on the operator
+// and the seed only, so it is formed once per handle.
+void Solver::sketch_norms() {
+  const int64_t n = n_;
+  const int nx = nx_;
+  double* Om = b64_.S[0].as<double>();
+  double* AO = b64_.AX.as<double>();
+  double* nrm = nrm_.as<double>();
+  launch_gaussian(n, nx, Om, ldS_, opt_.seed, kStreamSketch, s_);
+  spmm<double>(A_, Om, ldS_, AO, ldX_, nx);
+  launch_colsq<double>(n, nx, AO, ldX_, nrm, work_.get(), s_);
+  launch_sqrt_sum(nx, nrm, nrm + 4 * nx, s_);
+  launch_colsq<double>(n, nx, Om, ldS_, nrm, work_.get(), s_);
+  launch_sqrt_sum(nx, nrm, nrm + 4 * nx + 1, s_);
+  if (haveB_) {
+    spmm<double>(B_, Om, ldS_, AO, ldX_, nx);
+    launch_colsq<double>(n, nx, AO, ldX_, nrm, work_.get(), s_);
+    launch_sqrt_sum(nx, nrm, nrm + 4 * nx + 2, s_);
+  }
+  LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx, sizeof(double) * 3, hipMemcpyDeviceToHost, s_));
+  sync();
+  normA_ = hdbl_[0] / hdbl_[1];
+  normB_ = haveB_ ? hdbl_[2] / hdbl_[1] : 1.0;
 }
 
 Solver::~Solver() {
@@ -314,23 +351,21 @@ int Solver::ortho_drop(Blocks<T>& b, const DevCsr* B, T* U, int64_t ldu, int nu,
   double* Gv = GA_.as<double>();       // scratch: V^T M U (nv x nu)
   double* Tu = C_.as<double>();        // svqb transform (nu x nkeep, ld nu)
   double* nrm = nrm_.as<double>();
+  // device slots read back together once per inner pass:
+  //   t[0] ||U^T M U - I||_F, t[1] ||U||_F, t[2] ||MU||_F, t[3] ||V^T M U||_F, t[4] ||MV||_F
+  double* t = nrm + 4 * nx_;
   T* U2 = b.U2.template as<T>();
   T* MU = B ? b.MU.template as<T>() : U;
   const int64_t ldmu = B ? ldX_ : ldu;
-  // ||MV||_F (for the outer test).
-  double mv_norm = 0.0;
   if (nv > 0) {
     launch_colsq<T>(n_, nv, MV, ldmv, nrm, work_.get(), s_);
-    launch_sqrt_sum(nv, nrm, nrm + 4 * nx_, s_);
-    LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx_, sizeof(double), hipMemcpyDeviceToHost, s_));
-    sync();
-    mv_norm = hdbl_[0];
+    launch_sqrt_sum(nv, nrm, t + 4, s_);
   }
   auto gram_u = [&]() {
     if (B) spmm<T>(*B, U, ldu, MU, ldmu, nu);
     gram<T>(n_, nu, nu, nu, U, ldu, MU, ldmu, nullptr, 0, G, 0, nullptr, 0, ldg, 0);
   };
-  double u_norm = 0.0;
+  double outer_err = 0.0;
   for (int i = 0; i < 3 && nu > 0; ++i) {
     // Outer pass: U = U - V (V^T M U) (block classical Gram-Schmidt).
     if (nv > 0) {
@@ -351,28 +386,27 @@ int Solver::ortho_drop(Blocks<T>& b, const DevCsr* B, T* U, int64_t ldu, int nu,
       update<T>(n_, nu, keep, U, ldu, Tu, nu, 1.0, 0.0, U2, ldX_);
       launch_copy2d<T, T>(n_, keep, U2, ldX_, U, ldu, s_);
       nu = keep;
-      // Inner test: ||U^T M U - I|| / (||MU|| ||U||) with MU recomputed.
+      // Inner test ||U^T M U - I|| / (||MU|| ||U||) with MU recomputed, and the
+      // outer test ||V^T M U|| / (||MV|| ||U||) on the same U, read back together
+      // (the outer value is used only when this inner pass ends the inner loop).
       gram_u();
-      launch_fro_minus_identity(nu, G, ldg, nrm + 4 * nx_, s_);
+      launch_fro_minus_identity(nu, G, ldg, t, s_);
       launch_colsq<T>(n_, nu, U, ldu, nrm, work_.get(), s_);
-      launch_sqrt_sum(nu, nrm, nrm + 4 * nx_ + 1, s_);
+      launch_sqrt_sum(nu, nrm, t + 1, s_);
       launch_colsq<T>(n_, nu, MU, ldmu, nrm, work_.get(), s_);
-      launch_sqrt_sum(nu, nrm, nrm + 4 * nx_ + 2, s_);
-      LOBPCG_HIP(
-          hipMemcpyAsync(hdbl_, nrm + 4 * nx_, sizeof(double) * 3, hipMemcpyDeviceToHost, s_));
+      launch_sqrt_sum(nu, nrm, t + 2, s_);
+      if (nv > 0) {
+        gram<T>(n_, nv, nu, nu, MV, ldmv, U, ldu, nullptr, 0, Gv, 0, nullptr, 0, ldg, 0);
+        launch_fro(nv, nu, Gv, ldg, t + 3, s_);
+      }
+      LOBPCG_HIP(hipMemcpyAsync(hdbl_, t, sizeof(double) * 5, hipMemcpyDeviceToHost, s_));
       sync();
-      u_norm = hdbl_[1];
+      outer_err = nv > 0 ? hdbl_[3] / (hdbl_[4] * hdbl_[1]) : 0.0;
       const double err = hdbl_[0] / (hdbl_[2] * hdbl_[1]);
       if (err <= tau_ortho) break;
     }
     if (nv == 0 || nu == 0) break;
-    // Outer test: ||V^T M U|| / (||MV|| ||U||).
-    gram<T>(n_, nv, nu, nu, MV, ldmv, U, ldu, nullptr, 0, Gv, 0, nullptr, 0, ldg, 0);
-    launch_fro(nv, nu, Gv, ldg, nrm + 4 * nx_, s_);
-    LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx_, sizeof(double), hipMemcpyDeviceToHost, s_));
-    sync();
-    const double err = hdbl_[0] / (mv_norm * u_norm);
-    if (err <= tau_ortho) break;
+    if (outer_err <= tau_ortho) break;
   }
   return nu;
 }
@@ -407,9 +441,14 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   T* Rb = b.R.template as<T>();
   int cur = 0;
   *iters_out = 0;
-
+  int np = 0, nc = 0;
+  int rc = LOBPCG_NOT_CONVERGED;
+  int it = 0;
+  bool have_x = false;  // S[cur] holds a Rayleigh-Ritz block X
+  try {
   // Algorithm 8's start: Rayleigh-Ritz on X0 (Algorithm 2), X = X0 C.
   phase_mark(7);
+  LOBPCG_HIP(hipMemsetAsync(nc_.get(), 0, sizeof(int32_t) * 4, s_));
   T* S0 = b.S[0].template as<T>();
   launch_copy2d<double, T>(n, nx, X0dev, nx, S0, ldS, s_);
   phase_mark(0);
@@ -430,6 +469,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   T* S1 = b.S[1].template as<T>();
   update<T>(n, nx, nx, S0, ldS, C, ldc, 1.0, 0.0, S1, ldS);
   cur = 1;
+  have_x = true;
   // First residual R = AX - BX Theta; W = K^-1 R stored reversed after X (P is empty).
   phase_mark(0);
   if (impl) {
@@ -439,7 +479,6 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   spmm<T>(A, S1, ldS, AX, ldAX, nx);
   if (B) spmm<T>(*B, S1, ldS, BXP, ldBXP, nx);
   phase_mark(6);
-  int np = 0, nc = 0;
   launch_residual<T>(n, nx, AX, ldAX, B ? BXP : nullptr, ldBXP, S1, ldS, theta, dinv,
                      use_cb ? Rb : S1 + nx, use_cb ? ldX : ldS, normA_, normB_, tol,
                      rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
@@ -460,8 +499,6 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   // explicitly, so that its factor and condition test see S^T B S itself.
   const double cond_xp = tau_skip > 0.0 ? std::pow(tau_skip, -0.25) : HUGE_VAL;
   bool xp_explicit = false;
-  int rc = LOBPCG_NOT_CONVERGED;
-  int it = 0;
   for (it = 1; it <= maxit; ++it) {
     T* Sc = b.S[cur].template as<T>();
     T* Sn = b.S[cur ^ 1].template as<T>();
@@ -565,8 +602,10 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     }
     // Number of converged pairs (leading run meeting criterion 9); the
     // host waits for this copy only, the P update runs on meanwhile.
-    LOBPCG_HIP(hipMemcpyAsync(hbuf_, nc_.get(), sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s_));
+    LOBPCG_HIP(hipMemcpyAsync(hbuf_, nc_.get(), sizeof(int32_t) * 3, hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipEventRecord(ev_nc_, s_));
+    // the wait for Algorithm 7's P block (second stream) is Rayleigh-Ritz time
+    phase_mark(4);
     dense_->join_p();
     phase_mark(5);
     if (npn > 0) {
@@ -576,6 +615,12 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     }
     np = npn;
     LOBPCG_HIP(hipEventSynchronize(ev_nc_));
+    if (hbuf_[2] == 2)
+      throw Error(LOBPCG_ERR_NONFINITE, "non-finite projected matrix");
+    if (hbuf_[2])
+      throw Error(LOBPCG_ERR_BREAKDOWN,
+                  "projected eigenproblem: an implicit QL leaf of the tridiagonal "
+                  "divide and conquer did not converge");
     if (hbuf_[1]) throw Error(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
     nc = hbuf_[0];
     if (nc >= k_) {
@@ -583,6 +628,30 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       break;
     }
     if (nx - nc == 0 && np == 0) throw Error(LOBPCG_ERR_BREAKDOWN, "search space collapsed");
+  }
+  } catch (const Error& e) {
+    // A breakdown or a non-finite value in the FP32 phase of the precision
+    // split does not end the solve: the FP64 phase takes over, from the last
+    // block X when it is finite (breakdown) or from the initial block
+    // (non-finite values), which X0buf still holds.
+    const bool recoverable = e.code == LOBPCG_ERR_BREAKDOWN || e.code == LOBPCG_ERR_NONFINITE;
+    if (sizeof(T) != 4 || !recoverable || !fp32_soft_) throw;
+    dense_->join_p();
+    phase_mark(7);
+    fp32_failure_ = e.what();
+    *iters_out = std::min(it, maxit);
+    final_nc_ = 0;
+    if (e.code == LOBPCG_ERR_BREAKDOWN && have_x) {
+      const T* Xc = b.S[cur].template as<T>();
+      double* nrm = nrm_.as<double>();
+      launch_colsq<T>(n, nx, Xc, ldS, nrm, work_.get(), s_);
+      launch_sqrt_sum(nx, nrm, nrm + 4 * nx, s_);
+      LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx, sizeof(double), hipMemcpyDeviceToHost, s_));
+      sync();
+      if (std::isfinite(hdbl_[0]))
+        launch_copy2d<T, double>(n, nx, Xc, ldS, X0buf_.as<double>(), nx, s_);
+    }
+    return e.code;
   }
   phase_mark(7);
   *iters_out = std::min(it, maxit);
@@ -602,6 +671,7 @@ int Solver::solve(double tol, const double* X0, bool x0_dev, lobpcg_precond_fn K
   LOBPCG_CHECK(tol > 0.0, LOBPCG_ERR_ARG, "tol must be positive");
   LOBPCG_CHECK(opt_.precond != 2 || K != nullptr, LOBPCG_ERR_ARG,
                "precond = 2 needs a callback");
+  AllocatorScope scope(&alloc_);
   lobpcg_info local{};
   lobpcg_info* inf = info ? info : &local;
   std::memset(inf, 0, sizeof(*inf));
@@ -615,32 +685,10 @@ int Solver::solve(double tol, const double* X0, bool x0_dev, lobpcg_precond_fn K
   const int nx = nx_;
   double* X0b = X0buf_.as<double>();
   if (X0 == nullptr) {
-    launch_gaussian(n, nx, X0b, nx, opt_.seed, s_);
+    launch_gaussian(n, nx, X0b, nx, opt_.seed, kStreamInitialBlock, s_);
   } else {
     LOBPCG_HIP(hipMemcpyAsync(X0b, X0, sizeof(double) * n * nx,
                               x0_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s_));
-  }
-  // Section 4.3: ||A||_2 >= ||Omega A||_F / ||Omega||_F with Omega = X0^T.
-  {
-    double* S0 = b64_.S[0].as<double>();
-    double* AX = b64_.AX.as<double>();
-    double* nrm = nrm_.as<double>();
-    launch_copy2d<double, double>(n, nx, X0b, nx, S0, ldS_, s_);
-    spmm<double>(A_, S0, ldS_, AX, ldX_, nx);
-    launch_colsq<double>(n, nx, AX, ldX_, nrm, work_.get(), s_);
-    launch_sqrt_sum(nx, nrm, nrm + 4 * nx, s_);
-    launch_colsq<double>(n, nx, S0, ldS_, nrm, work_.get(), s_);
-    launch_sqrt_sum(nx, nrm, nrm + 4 * nx + 1, s_);
-    if (haveB_) {
-      spmm<double>(B_, S0, ldS_, AX, ldX_, nx);
-      launch_colsq<double>(n, nx, AX, ldX_, nrm, work_.get(), s_);
-      launch_sqrt_sum(nx, nrm, nrm + 4 * nx + 2, s_);
-    }
-    LOBPCG_HIP(hipMemcpyAsync(hdbl_, nrm + 4 * nx, sizeof(double) * 3, hipMemcpyDeviceToHost, s_));
-    sync();
-    LOBPCG_CHECK(hdbl_[1] > 0.0, LOBPCG_ERR_ARG, "X0 is zero");
-    normA_ = hdbl_[0] / hdbl_[1];
-    normB_ = haveB_ ? hdbl_[2] / hdbl_[1] : 1.0;
   }
   inf->norm_A_est = normA_;
   inf->norm_B_est = normB_;
@@ -651,9 +699,17 @@ int Solver::solve(double tol, const double* X0, bool x0_dev, lobpcg_precond_fn K
   int iters = 0;
   if (opt_.precision == 1) {
     const double tol32 = std::max(opt_.fp32_tol > 0 ? opt_.fp32_tol : 1e-5, tol);
-    rc = run<float>(b32_, A_, B, tol32, maxit, X0b, skip * kEps32, 1e-5, K, Kuser, inf, &iters);
+    fp32_soft_ = true;
+    try {
+      rc = run<float>(b32_, A_, B, tol32, maxit, X0b, skip * kEps32, 1e-5, K, Kuser, inf, &iters);
+    } catch (...) {
+      fp32_soft_ = false;
+      throw;
+    }
+    fp32_soft_ = false;
     inf->fp32_iterations = iters;
     inf->iterations = iters;
+    if (rc < 0) inf->fp32_fallback = 1;
     // FP64 refinement: Algorithm 8 again, started from the FP32 block (now in X0buf).
     const int left = std::max(1, maxit - iters);
     rc = run<double>(b64_, A_, B, tol, left, X0b, skip * kEps64,

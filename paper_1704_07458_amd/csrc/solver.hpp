@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -69,7 +70,10 @@ class Solver {
               double alpha, double beta, T* Y, int64_t ldy);
   void phase_mark(int phase);
   void sync();
+  // ||A||^(Omega), ||B||^(Omega) of section 4.3 from the seeded sketch.
+  void sketch_norms();
 
+  DevAllocator alloc_{};  // the caller's device-allocation hooks (or hipMalloc)
   hipStream_t s_ = nullptr;
   int64_t n_ = 0;
   int k_ = 0, nx_ = 0, nsmax_ = 0;
@@ -90,6 +94,10 @@ class Solver {
   double normA_ = 0.0, normB_ = 1.0;
   const double* Xres_ = nullptr;  // points into b64_.S[cur]
   bool profile_ = false;
+  // FP32 phase of the precision split: a breakdown or non-finite value hands
+  // over to the FP64 phase instead of ending the solve
+  bool fp32_soft_ = false;
+  std::string fp32_failure_;
   double tmark_ = 0.0;
   int cur_phase_ = 7;
   double* phase_acc_ = nullptr;

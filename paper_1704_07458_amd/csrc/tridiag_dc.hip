@@ -52,6 +52,30 @@ __device__ __forceinline__ void dc_range(int n, int level, int idx, int& lo, int
 
 __device__ __forceinline__ double dc_wave_sum(double v) { return wave64_sum(v); }
 
+// ---------------------------------------------------------------- input check
+// One workgroup.  A non-finite d or e (a non-finite projected matrix) would
+// make the merges' rank computations and orderings undefined; such an input is
+// replaced by the zero tridiagonal (every later kernel then sees finite values)
+// and reported through *fail = 2.
+__global__ __launch_bounds__(256) void dc_sanitize_kernel(int n, double* d, double* e, int* fail) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    if (!isfinite(d[i])) mine = 1;
+    if (i < n - 1 && !isfinite(e[i])) mine = 1;
+  }
+  if (mine) atomicOr(&bad, 1);
+  __syncthreads();
+  if (!bad) return;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    d[i] = 0.0;
+    if (i < n - 1) e[i] = 0.0;
+  }
+  if (threadIdx.x == 0) atomicMax(fail, 2);
+}
+
 // ---------------------------------------------------------------- tear
 // d[mid - 1] and d[mid] lose |e[mid - 1]| for every internal node (distinct
 // indices: children are at least kDcLeaf / 2 rows apart from their parent's mid).
@@ -92,7 +116,8 @@ __device__ __forceinline__ double dc_lane_get(double v, int i) {
 __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const double* __restrict__ d,
                                                          const double* __restrict__ e,
                                                          double* __restrict__ lam,
-                                                         double* __restrict__ Z, int64_t ldz) {
+                                                         double* __restrict__ Z, int64_t ldz,
+                                                         int* __restrict__ fail) {
   __shared__ double V[kDcLeaf][kDcLeaf + 1];  // V[row][col]
   __shared__ double dl[kDcLeaf];
   __shared__ int perm[kDcLeaf];
@@ -112,8 +137,10 @@ __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const 
   dv = ldexp(dv, -ex);
   ev = ldexp(ev, -ex);
   __syncthreads();
+  bool stalled = false;
   for (int l = 0; l < m; ++l) {
-    for (int it = 0; it < kDcQlIter; ++it) {
+    int it = 0;
+    for (; it < kDcQlIter; ++it) {
       // first negligible e_mm at or after l (a wave-wide test)
       const bool neg = !(lane >= l && lane < m - 1) ||
                        fabs(ev) <= eps * (fabs(dv) + fabs(__shfl_down(dv, 1, kWave)));
@@ -161,7 +188,11 @@ __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const 
       }
       if (lane == mm) ev = 0.0;
     }
+    stalled = stalled || it == kDcQlIter;
   }
+  // a leaf that did not converge within kDcQlIter sweeps per eigenvalue is
+  // reported (its values are not trusted by the caller)
+  if (stalled && lane == 0) atomicMax(fail, 1);
   if (lane < m) dl[lane] = ldexp(dv, ex);
   __syncthreads();
   // ascending order (rank sort, ties by index)
@@ -620,7 +651,7 @@ int tridiag_dc_int_workspace() { return kDcInts; }
 
 void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64_t ldz,
                 double* Qs, double* Dl, double* G, double* Y, double* vec4, int* iw, double* rw,
-                double* rhoK, rocblas_handle h, hipStream_t s) {
+                double* rhoK, int* fail, rocblas_handle h, hipStream_t s) {
   LOBPCG_CHECK(n >= 1 && n <= kDcMaxN && ldz >= n, LOBPCG_ERR_ARG, "tridiag_dc: bad sizes");
   int depth = 0;
   while (((n + (1 << depth) - 1) >> depth) > kDcLeaf) ++depth;
@@ -628,13 +659,15 @@ void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64
   double* zsort = vec4 + n;
   double* lamk = vec4 + 2 * n;
   double* zh = vec4 + 3 * n;
+  hipLaunchKernelGGL(dc_sanitize_kernel, dim3(1), dim3(256), 0, s, n, d, const_cast<double*>(e),
+                     fail);
   if (depth > 0) {
     const int internal = (1 << depth) - 1;
     hipLaunchKernelGGL(dc_tear_kernel, dim3(dc_blocks(internal, 64)), dim3(64), 0, s, n, depth, e,
                        d);
   }
   hipLaunchKernelGGL(dc_leaf_kernel, dim3(1u << depth), dim3(kWave), 0, s, n, depth, d, e, lam, Z,
-                     ldz);
+                     ldz, fail);
   LOBPCG_HIP(hipGetLastError());
   for (int level = depth - 1; level >= 0; --level) {
     const int nodes = 1 << level;

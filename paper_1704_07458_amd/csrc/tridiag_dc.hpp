@@ -16,9 +16,12 @@ int tridiag_dc_int_workspace();
 // overwritten), Z column-major with leading dimension ldz.  Workspace (device):
 // Qs, Dl, G, Y: n x n each with leading dimension ldz; vec4: 4 n doubles;
 // iw: tridiag_dc_int_workspace() ints; rw: 2 tridiag_dc_max_n() doubles; rhoK: 64
-// doubles.  All on stream s; h runs the merge GEMMs.
+// doubles.  fail: device int raised (never cleared) to 1 when a leaf's implicit
+// QL iteration did not converge, to 2 when d or e held a non-finite value (the
+// tridiagonal is then replaced by zeros; e may be written).  All on stream s;
+// h runs the merge GEMMs.
 void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64_t ldz,
                 double* Qs, double* Dl, double* G, double* Y, double* vec4, int* iw, double* rw,
-                double* rhoK, rocblas_handle h, hipStream_t s);
+                double* rhoK, int* fail, rocblas_handle h, hipStream_t s);
 
 }  // namespace lobpcg

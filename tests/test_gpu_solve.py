@@ -13,6 +13,7 @@ import scipy.linalg as sla
 from oracle import adjoint as ADJ
 from oracle import closed_forms as cf
 from oracle import lobpcg as L
+from oracle import philox as PH
 from paper_1704_07458_amd import problems as P
 
 pytestmark = pytest.mark.gpu
@@ -43,6 +44,16 @@ def _oracle(w, tol=None, **kw):
     return L.lobpcg(A, w.X0, w.k, tol if tol is not None else w.tol, B=Bm, precond=pre, **kw)
 
 
+def _oracle_norms(w, seed=0):
+    """||A||^(Omega), ||B||^(Omega) of section 4.3 computed by the oracle on its own
+    draw of the seeded sketch (the GPU's estimates are compared with these)."""
+    n = w.A.n
+    Om = PH.sketch(seed, n, w.n_x)
+    nA = L.sketch_norm(L.Operator(w.A.to_scipy()), Om)
+    nB = 1.0 if w.B is None else L.sketch_norm(L.Operator(w.B.to_scipy()), Om)
+    return nA, nB
+
+
 def _host_rho(w, lam, X, normA, normB):
     A = w.A.to_scipy()
     BX = X if w.B is None else w.B.to_scipy() @ X
@@ -50,13 +61,15 @@ def _host_rho(w, lam, X, normA, normB):
 
 
 def _sin_angle(X, Y, Bm=None):
-    """Sine of the largest principal angle between span X and span Y (B inner product)."""
+    """Sine of the largest principal angle between span X and span Y (B inner product),
+    as the 2-norm of (I - Qy Qy^T) Qx for orthonormal bases Qx, Qy: accurate to
+    rounding, where sqrt(1 - cos^2) from the cosines bottoms out near sqrt(eps)."""
     if Bm is not None:
         Lc = np.linalg.cholesky(Bm.toarray() if hasattr(Bm, "toarray") else Bm)
         X, Y = Lc.T @ X, Lc.T @ Y
     Qx, Qy = sla.orth(X), sla.orth(Y)
-    s = np.linalg.svd(Qx.T @ Qy, compute_uv=False)
-    return float(np.sqrt(max(0.0, 1.0 - s.min() ** 2)))
+    E = Qx - Qy @ (Qy.T @ Qx)
+    return float(np.linalg.norm(E, 2))
 
 
 def test_cfg0_full_against_closed_form_and_oracle(lib):
@@ -68,7 +81,7 @@ def test_cfg0_full_against_closed_form_and_oracle(lib):
     assert np.max(np.abs(lam - exact) / exact) <= EIG_RTOL
     ref = _oracle(w)
     assert np.max(np.abs(lam - ref.theta[: w.k]) / np.abs(ref.theta[: w.k])) <= EIG_RTOL
-    host = _host_rho(w, lam, X, info["norm_A_est"], info["norm_B_est"])
+    host = _host_rho(w, lam, X, *_oracle_norms(w))
     assert np.all(host <= RESID_TOL)
     assert np.allclose(rho, host, rtol=1e-6)
     # the exact ||A||_2 gives an even smaller ratio (the sketch is a lower bound)
@@ -81,6 +94,28 @@ def test_cfg0_full_against_closed_form_and_oracle(lib):
     # rotation an eigensolver returns decides how a pair's residual splits
     # between its two columns, and criterion (9) is applied per column.
     assert abs(info["iterations"] - ref.iterations) <= max(3, ref.iterations // 10)
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3])
+def test_sketch_norms_match_the_oracle(lib, idx):
+    """norm_A_est / norm_B_est (section 4.3) equal the oracle's sketch norms: both
+    sides draw Omega from the same seeded counter-based generator."""
+    w = P.workload(idx, small=True)
+    s, info = _gpu_solve(w, maxit=1)
+    nA, nB = _oracle_norms(w)
+    assert abs(info["norm_A_est"] - nA) <= 1e-12 * nA
+    assert abs(info["norm_B_est"] - nB) <= 1e-12 * nB
+    # independent of the initial block and of the call: a warm start gives the same values
+    lam, X, _ = s.eigpairs(w.n_x)
+    info2 = s.solve(w.tol, X.contiguous())
+    assert info2["norm_A_est"] == info["norm_A_est"]
+    # another seed draws another sketch
+    from paper_1704_07458_amd import binding as B
+
+    s3 = B.Solver(w.A, w.k, B=w.B, precond=w.precond, maxit=1, seed=7)
+    info3 = s3.solve(w.tol, w.X0)
+    nA7, _ = _oracle_norms(w, seed=7)
+    assert abs(info3["norm_A_est"] - nA7) <= 1e-12 * nA7
 
 
 @pytest.mark.parametrize("iters", [1, 2, 5, 20])
@@ -121,7 +156,7 @@ def test_small_workloads_match_oracle_and_dense(lib, idx):
     assert np.max(np.abs(lam - exact) / np.abs(exact)) <= EIG_RTOL
     ref = _oracle(w)
     assert np.max(np.abs(lam - ref.theta[: w.k]) / np.abs(ref.theta[: w.k])) <= EIG_RTOL
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], info["norm_B_est"]) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
     if w.B is not None:
         Bm = w.B.to_scipy()
         assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
@@ -148,7 +183,7 @@ def test_forced_ortho_switch_runs_orthodrop(lib):
         hist = {h.it: h.cond_R for h in ref.history}
         c = hist.get(sw, np.inf)
         assert c ** 3 * tols.tau_skip > 0.3
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], 1.0) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
 
 
 def test_forced_ortho_switch_generalized_pencil(lib):
@@ -196,7 +231,7 @@ def test_section6_versions_match_oracle(lib, idx, gpu_opts, ref_opts):
         ref_svqb = ref.ortho_stats.svqb_calls
         assert abs(info["svqb_calls"] - ref_svqb) <= 0.25 * ref_svqb + 2
     Bm = None if w.B is None else w.B.to_scipy()
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], info["norm_B_est"]) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
     if Bm is not None:
         assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
 
@@ -225,7 +260,7 @@ def test_implicit_product_updates_match_oracle(lib, idx, gpu_opts, ref_opts):
     assert np.max(np.abs(lam - th) / np.abs(th)) <= EIG_RTOL
     assert abs(info["iterations"] - ref.iterations) <= max(2, 0.1 * ref.iterations)
     # the true residual, recomputed on the host, not the implicitly updated one
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], 1.0) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
 
 
 def test_implicit_product_updates_fp32_split(lib):
@@ -235,7 +270,7 @@ def test_implicit_product_updates_fp32_split(lib):
     lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
     exact = cf.smallest(cf.laplacian_3d_dirichlet(12), w.k)
     assert np.max(np.abs(lam - exact) / exact) <= EIG_RTOL
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], 1.0) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
 
 
 def _golden(name):
@@ -292,7 +327,7 @@ def test_basic_lobpcg_matches_oracle(lib, idx):
     th = ref.theta[: w.k]
     assert np.max(np.abs(lam - th) / np.abs(th)) <= EIG_RTOL
     assert abs(info["iterations"] - ref.iterations) <= max(2, 0.1 * ref.iterations)
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], info["norm_B_est"]) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
 
 
 def test_basic_lobpcg_breaks_down_on_the_section_4_1_example(lib):
@@ -328,7 +363,7 @@ def test_largest_eigenpairs_closed_form_and_oracle(lib):
     ref = _oracle(w, largest=True)
     assert np.max(np.abs(lam - ref.theta[: w.k]) / ref.theta[: w.k]) <= EIG_RTOL
     assert abs(info["iterations"] - ref.iterations) <= max(2, 0.1 * ref.iterations)
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], 1.0) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
     with pytest.raises(RuntimeError, match="largest"):
         s.adjoint(1, np.ones(1), None)
 
@@ -342,7 +377,7 @@ def test_largest_eigenpairs_generalized_pencil(lib):
     ex = sla.eigh(Am.toarray(), Bm.toarray(), eigvals_only=True)[::-1][: w.k]
     assert np.max(np.abs(lam - ex) / np.abs(ex)) <= EIG_RTOL
     assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], info["norm_B_est"]) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
 
 
 def test_long_run_below_the_floor_generalized_pencil(lib):
@@ -392,7 +427,85 @@ def test_fp32_split_reaches_fp64_residual(lib):
     lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
     exact = cf.smallest(cf.laplacian_3d_dirichlet(12), w.k)
     assert np.max(np.abs(lam - exact) / exact) <= EIG_RTOL
-    assert np.all(_host_rho(w, lam, X, info["norm_A_est"], 1.0) <= RESID_TOL)
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
+
+
+@pytest.mark.parametrize("idx", [2, 3])
+def test_fp32_split_small_pencils_match_oracle(lib, idx):
+    """The precision split on the structures of the generalised FEM pencil (B != I:
+    FP32 B X, B P, B W and orthoDrop in the B metric) and of the disordered
+    Hamiltonian (shifted Jacobi): after the FP64 refinement the pairs meet the
+    FP64 bars against the dense solution and the FP64 oracle; the split's own
+    eigenvalue error against the FP64 path is printed."""
+    w = P.workload(idx, small=True)
+    s, info = _gpu_solve(w, precision="split")
+    assert info["converged"], info
+    assert info["fp32_iterations"] > 0 and info["fp64_iterations"] > 0
+    assert info["fp32_fallback"] == 0
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    A = w.A.to_scipy().toarray()
+    if w.B is None:
+        exact = np.linalg.eigvalsh(A)[: w.k]
+    else:
+        exact = sla.eigh(A, w.B.to_scipy().toarray(), eigvals_only=True)[: w.k]
+    assert np.max(np.abs(lam - exact) / np.abs(exact)) <= EIG_RTOL
+    ref = _oracle(w)
+    assert np.max(np.abs(lam - ref.theta[: w.k]) / np.abs(ref.theta[: w.k])) <= EIG_RTOL
+    assert np.all(_host_rho(w, lam, X, *_oracle_norms(w)) <= RESID_TOL)
+    if w.B is not None:
+        Bm = w.B.to_scipy()
+        assert np.allclose(X.T @ (Bm @ X), np.eye(w.k), atol=1e-9)
+    s64, _ = _gpu_solve(w)
+    lam64 = s64.eigpairs(w.k)[0].cpu().numpy()
+    print(f"cfg{idx} small split: {info['fp32_iterations']} FP32 + {info['fp64_iterations']} FP64 "
+          f"iterations; eigenvalue error vs FP64 path "
+          f"{np.max(np.abs(lam - lam64) / np.abs(lam64)):.2e}")
+
+
+def test_fp32_phase_overflow_hands_over_to_fp64(lib):
+    """A pencil whose products overflow FP32 (the 12^2 Laplacian scaled by 1e36: the
+    FP32 Gram sums pass 3.4e38) but not FP64: the FP32 phase meets non-finite values
+    and the FP64 phase takes over from the initial block instead of failing."""
+    w = P.workload(0, small=True)
+    scale = 1e36
+    Ascaled = P.CSR(w.A.n, w.A.rowptr, w.A.colind, w.A.values * scale)
+    w2 = P.Workload(w.name, Ascaled, None, w.k, w.n_x, w.tol, w.precond, w.X0)
+    s, info = _gpu_solve(w2, precision="split")
+    assert info["fp32_fallback"] == 1, info
+    assert info["converged"], info
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    exact = scale * cf.smallest(cf.laplacian_2d_dirichlet(12), w.k)
+    assert np.max(np.abs(lam - exact) / exact) <= EIG_RTOL
+    assert np.all(_host_rho(w2, lam, X, *_oracle_norms(w2)) <= RESID_TOL)
+
+
+@pytest.mark.parametrize("idx", [2, 4])
+def test_subspace_angles_at_tight_tolerance_small_pencils(lib, idx):
+    """Principal angles against the oracle at tau = 1e-12 (B inner product for the
+    FEM pencil), on the first c pairs with c the last cluster boundary <= k; the
+    Davis-Kahan bound ||R||_F / gap is checked beside the angle."""
+    w = P.workload(idx, small=True)
+    s, info = _gpu_solve(w, tol=1e-12)
+    assert info["converged"], info
+    lam, X, _ = (t.cpu().numpy() for t in s.eigpairs(w.k))
+    ref = _oracle(w, tol=1e-12)
+    assert ref.converged
+    A = w.A.to_scipy().toarray()
+    Bd = None if w.B is None else w.B.to_scipy().toarray()
+    lam_all = sla.eigh(A, Bd, eigvals_only=True)
+    c = cf.cluster_boundary(lam_all, w.k)
+    assert c >= w.k // 2
+    Bm = None if w.B is None else w.B.to_scipy()
+    sin_gpu_ref = _sin_angle(X[:, :c], ref.X[:, :c], Bm)
+    # against the dense invariant subspace: both sides are pinned, not only their agreement
+    _, V = sla.eigh(A, Bd)
+    sin_gpu_exact = _sin_angle(X[:, :c], V[:, :c], Bm)
+    BX = X[:, :c] if Bm is None else Bm @ X[:, :c]
+    R = A @ X[:, :c] - BX * lam[:c]
+    bound = np.linalg.norm(R) / (lam_all[c] - lam_all[c - 1])
+    print(f"cfg{idx} small: c {c}, sin vs oracle {sin_gpu_ref:.2e}, vs dense {sin_gpu_exact:.2e}, "
+          f"||R||_F/gap {bound:.2e}")
+    assert sin_gpu_ref <= 1e-7 and sin_gpu_exact <= 1e-7
 
 
 def _device_view(torch, ptr, n, ncols, ld, dtype):

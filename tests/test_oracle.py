@@ -540,3 +540,13 @@ def test_jacobi_diagonal_shift_makes_indefinite_diagonal_positive():
     # no shift when the diagonal is already positive
     A1 = P.laplacian_3d(6).to_scipy()
     assert np.all(L.jacobi_diagonal(A1) == 6.0)
+
+
+def test_dirichlet_3d_modes_are_orthonormal_eigenvectors():
+    """The closed-form invariant subspace used by the subspace-angle checks."""
+    N = 9
+    V, lam = cf.dirichlet_3d_modes(N, 40)
+    A = P.laplacian_3d(N).to_scipy()
+    assert np.allclose(V.T @ V, np.eye(40), atol=1e-13)
+    assert np.max(np.abs(A @ V - V * lam)) <= 1e-13
+    assert np.allclose(lam, cf.smallest(cf.laplacian_3d_dirichlet(N), 40), rtol=1e-14)
