@@ -19,9 +19,10 @@ isation counts, phase breakdown).
 --ksweep solves the 64^3 Laplacian for k = 25, 50, 100, 150, 200 (the analog of
 Fig. 4's time against the number of eigenpairs) and prints one line per k.
 
---workloads times the other synthetic pencils: the 48^3 Q1 FEM pencil with
-k = 400 to convergence, and the first 30 iterations of the 96^3 periodic
-Laplacian + potential with k = 1000 (one line each, with phase shares).
+--workloads [fem48|periodic96|all] times the other synthetic pencils to
+convergence, in FP64 and in the precision split: the 48^3 Q1 FEM pencil with
+k = 400 and the 96^3 periodic Laplacian + U[-8, 8] potential with k = 1000
+(one line each, with host checks of the returned pairs).
 """
 
 from __future__ import annotations
@@ -201,45 +202,141 @@ def run_ksweep(torch, B, P):
         s.close()
 
 
-def _timed_with_phases(torch, s, tol, X0):
-    s.solve(tol, X0)  # warm-up
+def _progress_printer(label, every=10):
+    def cb(it, nc, phase):
+        if it % every == 0:
+            _log(f"[bench] {label}: iteration {it} ({'fp32' if phase else 'fp64'}), "
+                 f"{nc} pairs converged")
+    return cb
+
+
+def _pencil_checks(A, Bm, lam, X, normA, normB, normA_bound=None):
+    """Host FP64 checks of returned pairs: criterion (9) with the solver's sketch
+    norms (and with an upper bound of ||A||_2 when given), B-orthonormality, and
+    the a-posteriori eigenvalue bounds from the residual norms: Weyl |theta - lambda|
+    <= ||r||_{B^-1} (B = I: ||r||) and Kato-Temple ||r||^2 / delta, with delta the
+    distance from theta_i to the other computed Ritz values less their residuals."""
+    BX = X if Bm is None else Bm @ X
+    R = A @ X - BX * lam
+    rn = np.linalg.norm(R, axis=0)
+    xn = np.linalg.norm(X, axis=0)
+    rho = rn / ((normA + np.abs(lam) * normB) * xn)
+    out = {"max_rho": float(rho.max())}
+    if normA_bound is not None:
+        out["max_rho_with_normA_bound"] = float(
+            (rn / ((normA_bound + np.abs(lam) * normB) * xn)).max())
+    G = X.T @ BX
+    out["max_orthonormality_error"] = float(np.max(np.abs(G - np.eye(G.shape[0]))))
+    if Bm is None:
+        srt = np.sort(lam)
+        gaps = np.empty_like(lam)
+        for i, t in enumerate(lam):
+            d = np.abs(srt - t)
+            d[np.argmin(d)] = np.inf
+            gaps[i] = d.min()
+        delta = np.maximum(gaps - rn, 0.0)
+        kt = np.where(delta > 0, rn ** 2 / np.where(delta > 0, delta, 1.0), np.inf)
+        out["weyl_bound_max"] = float(rn.max())
+        out["kato_temple_bound_median"] = float(np.median(kt))
+        out["kato_temple_bound_max_finite"] = float(np.max(kt[np.isfinite(kt)])) if np.any(
+            np.isfinite(kt)) else None
+        out["pairs_with_kato_temple_bound"] = int(np.sum(np.isfinite(kt)))
+    return out
+
+
+def _timed_solve(torch, s, tol, X0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = s.solve(tol, X0)
     torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    s.set_profiling(True)
-    ph = s.solve(tol, X0)["seconds_phase"]
-    s.set_profiling(False)
-    tot = sum(ph.values())
-    return info, sec, {k: v / tot for k, v in ph.items()} if tot > 0 else None
+    return info, time.perf_counter() - t0
 
 
-def run_workloads(torch, B, P):
-    w = P.workload(2)
-    X0 = torch.from_numpy(w.X0).cuda()
-    s = B.Solver(w.A, w.k, B=w.B, precond="jacobi")
-    info, sec, share = _timed_with_phases(torch, s, w.tol, X0)
-    print(json.dumps({"workload": "Q1 FEM pencil (K, M) 48^3 (n=110592), k=400, n_x=440, Jacobi, "
-                                  "tol 1e-8", "status": info["status"],
-                      "iterations": info["iterations"], "seconds": sec,
-                      "ms_per_iteration": 1e3 * sec / info["iterations"],
-                      "phase_share": share}), flush=True)
-    s.close()
-    del X0
-    L3 = P.laplacian_3d(96, periodic=True)
-    A = P.add_diagonal(L3, P.potential(0, L3.n, -8.0, 8.0))
-    n_x = P.block_size(1000)
-    gen = torch.Generator(device="cuda").manual_seed(0)
-    X0 = torch.randn((A.n, n_x), generator=gen, dtype=torch.float64, device="cuda")
-    s = B.Solver(A, 1000, precond="jacobi", maxit=30)
-    info, sec, share = _timed_with_phases(torch, s, 1e-8, X0)
-    print(json.dumps({"workload": "periodic 3D 7-point 96^3 + U[-8,8] (n=884736), k=1000, "
-                                  "n_x=1100, Jacobi; first 30 iterations (device N(0,1) X0)",
-                      "status": info["status"], "iterations": info["iterations"],
-                      "seconds": sec, "ms_per_iteration": 1e3 * sec / info["iterations"],
-                      "phase_share": share}), flush=True)
-    s.close()
+def run_workloads(torch, B, P, which):
+    """Time to k eigenpairs on the generalised FEM pencil (48^3, k = 400) and the
+    disordered Hamiltonian (periodic 96^3 + U[-8, 8], k = 1000), each in FP64 and
+    in the precision split, with host checks of the returned pairs."""
+    if which in ("fem48", "all"):
+        w = P.workload(2)
+        X0 = torch.from_numpy(w.X0).cuda()
+        A, Bm = w.A.to_scipy(), w.B.to_scipy()
+        lams = {}
+        for prec in ("fp64", "split"):
+            s = B.Solver(w.A, w.k, B=w.B, precond="jacobi", precision=prec)
+            s.solve(w.tol, X0)  # warm-up (library set-up, kernel loading)
+            info, sec = _timed_solve(torch, s, w.tol, X0)
+            s.kernel_stats(True)
+            s.solve(w.tol, X0)
+            st = s.kernel_stats(False)
+            lam, X, _ = s.eigpairs(w.k)
+            lam, X = lam.cpu().numpy(), X.cpu().numpy()
+            lams[prec] = lam
+            exact = _fem_smallest(48, w.k)
+            line = {"workload": "Q1 FEM pencil (K, M) 48^3 (n=110592), k=400, n_x=440, Jacobi, "
+                                "tol 1e-8, seeded N(0,1) X0",
+                    "precision": prec, "status": info["status"],
+                    "iterations": info["iterations"],
+                    "iterations_fp32": info["fp32_iterations"],
+                    "iterations_fp64": info["fp64_iterations"], "seconds": sec,
+                    "ms_per_iteration": 1e3 * sec / info["iterations"],
+                    "ortho_switch_iter": info["ortho_switch_iter"],
+                    "eig_rel_err_vs_closed_form": float(np.max(np.abs(lam - exact) / exact)),
+                    "kernel_seconds": {k: v["seconds"] for k, v in st.items()},
+                    **_pencil_checks(A, Bm, lam, X, info["norm_A_est"], info["norm_B_est"])}
+            if prec == "split":
+                line["eig_rel_err_vs_fp64"] = float(np.max(np.abs(lam - lams["fp64"]) /
+                                                           np.abs(lams["fp64"])))
+            print(json.dumps(line), flush=True)
+            s.close()
+        del X0
+    if which in ("periodic96", "all"):
+        L3 = P.laplacian_3d(96, periodic=True)
+        A = P.add_diagonal(L3, P.potential(0, L3.n, -8.0, 8.0))
+        k = 1000
+        As = A.to_scipy()
+        normA_bound = float(np.max(np.asarray(abs(As).sum(axis=1)).ravel()))  # Gershgorin
+        lams = {}
+        for prec in ("split", "fp64"):
+            s = B.Solver(A, k, precond="jacobi", precision=prec,
+                         progress=_progress_printer(f"periodic96 {prec}"))
+            s.kernel_stats(True)
+            # X0 = NULL: the library's seeded Gaussian block (Philox stream 0, seed 0)
+            info, sec = _timed_solve(torch, s, 1e-8, None)
+            st = s.kernel_stats(False)
+            _log(f"[bench] periodic96 {prec}: {info['status']} after {info['iterations']} "
+                 f"iterations, {sec:.1f} s")
+            lam, X, _ = s.eigpairs(k)
+            lam, X = lam.cpu().numpy(), X.cpu().numpy()
+            lams[prec] = lam
+            line = {"workload": "periodic 3D 7-point 96^3 + U[-8,8] (n=884736), k=1000, "
+                                "n_x=1100, shifted Jacobi, tol 1e-8, X0 from the library's "
+                                "seeded generator",
+                    "precision": prec, "status": info["status"],
+                    "iterations": info["iterations"],
+                    "iterations_fp32": info["fp32_iterations"],
+                    "iterations_fp64": info["fp64_iterations"],
+                    "fp32_fallback": info["fp32_fallback"], "seconds": sec,
+                    "timing_note": "HIP-event kernel statistics on during the solve (~2 %)",
+                    "ms_per_iteration": 1e3 * sec / info["iterations"],
+                    "ortho_switch_iter": info["ortho_switch_iter"],
+                    "normA_gershgorin": normA_bound, "norm_A_est": info["norm_A_est"],
+                    "kernels": {kk: {"seconds": v["seconds"], "launches": v["launches"],
+                                     "work": v["work"]} for kk, v in st.items()},
+                    **_pencil_checks(As, None, lam, X, info["norm_A_est"], 1.0, normA_bound)}
+            if prec == "fp64" and "split" in lams:
+                d = np.abs(lams["split"] - lam)
+                line["eig_abs_diff_split_vs_fp64_max"] = float(d.max())
+                line["eig_rel_diff_split_vs_fp64_max"] = float(np.max(d / np.abs(lam)))
+            print(json.dumps(line), flush=True)
+            del X
+            s.close()
+
+
+def _fem_smallest(N, k):
+    h = 1.0 / (N + 1)
+    t = np.arange(1, N + 1) * np.pi / (N + 1)
+    mu = 6.0 * (1.0 - np.cos(t)) / (h * h * (2.0 + np.cos(t)))
+    return np.sort((mu[:, None, None] + mu[None, :, None] + mu[None, None, :]).ravel())[:k]
 
 
 def kernel_source_hash() -> str:
@@ -281,8 +378,9 @@ def main():
                     help="solve with each version of section 6 instead (one line each)")
     ap.add_argument("--ksweep", action="store_true",
                     help="time to k eigenpairs for several k instead (one line each)")
-    ap.add_argument("--workloads", action="store_true",
-                    help="time the FEM k=400 and periodic k=1000 pencils instead")
+    ap.add_argument("--workloads", nargs="?", const="all", default=None,
+                    choices=["all", "fem48", "periodic96"],
+                    help="time the FEM k=400 and/or periodic k=1000 pencils instead")
     ap.add_argument("--phases", action="store_true",
                     help="one extra untimed FP64 solve with per-phase timing (stream syncs)")
     args = ap.parse_args()
@@ -311,7 +409,7 @@ def main():
     torch.cuda.set_device(0)
     B.load()
     if args.workloads:
-        run_workloads(torch, B, P)
+        run_workloads(torch, B, P, args.workloads)
         return
     w = P.workload(1)
     exact = dirichlet3d_smallest(64, w.k)

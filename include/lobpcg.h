@@ -137,6 +137,13 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* alloc_user);
   void (*dev_free)(void* ptr, void* alloc_user);
   void* alloc_user;
+  /* Progress report of long solves: when non-NULL, called on the host after
+   * every iteration (both phases of the precision split) with the iteration
+   * count so far, the number of converged leading pairs and the phase (0 FP64,
+   * 1 FP32).  It reads values the iteration copies to the host anyway: no
+   * extra synchronisation.  It must not call into the handle. */
+  void (*progress)(void* progress_user, int32_t iteration, int32_t n_converged, int32_t phase);
+  void* progress_user;
 } lobpcg_options;
 
 /* Per-solve statistics. seconds_phase: 0 sparse products, 1 preconditioner,

@@ -51,6 +51,7 @@ class lobpcg_csr(C.Structure):
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32)
 
 
 class lobpcg_options(C.Structure):
@@ -76,6 +77,8 @@ class lobpcg_options(C.Structure):
         ("dev_alloc", ALLOC_FN),
         ("dev_free", FREE_FN),
         ("alloc_user", C.c_void_p),
+        ("progress", PROGRESS_FN),
+        ("progress_user", C.c_void_p),
     ]
 
 
@@ -279,9 +282,15 @@ class Solver:
     """
 
     def __init__(self, A, k: int, B=None, precond: str = "none", precision: str = "fp64",
-                 block_size: int = 0, maxit: int = 2000, allocator: str = "torch", **opts):
+                 block_size: int = 0, maxit: int = 2000, allocator: str = "torch",
+                 progress=None, **opts):
         lib = load()
         o = default_options()
+        # progress(iteration, n_converged, phase) after every iteration (phase 1 = FP32)
+        self._progress = None
+        if progress is not None:
+            self._progress = PROGRESS_FN(lambda user, it, nc, ph: progress(it, nc, ph))
+            o.progress = self._progress
         o.block_size = block_size
         o.maxit = maxit
         o.precision = {"fp64": 0, "split": 1, "fp32-split": 1}[precision]

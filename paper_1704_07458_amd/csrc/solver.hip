@@ -623,6 +623,9 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
                   "divide and conquer did not converge");
     if (hbuf_[1]) throw Error(LOBPCG_ERR_NONFINITE, "non-finite Ritz value or residual");
     nc = hbuf_[0];
+    if (opt_.progress)
+      opt_.progress(opt_.progress_user, (info ? info->iterations : 0) + it, nc,
+                    sizeof(T) == 4 ? 1 : 0);
     if (nc >= k_) {
       rc = LOBPCG_OK;
       break;
