@@ -44,6 +44,24 @@ int lobpcg_gram(int64_t n, int32_t m, int32_t p, int32_t p1, int32_t dtype, cons
                 double* G, int64_t ldg, int32_t col_offset, int32_t mirror, void* work,
                 void* stream);
 
+/* lobpcg_gram without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same G, with the split-K partial tiles kept in a fixed
+ * device array of lobpcg_gram_noalloc_max_bytes() bytes (16 MiB) that the
+ * library holds on each GPU it runs on until the process ends (the split count
+ * is reduced to fit, so the summation order may differ from lobpcg_gram within
+ * the same rounding bound).  Nothing is allocated and no memset is issued.
+ * Returns LOBPCG_ERR_ARG when m * p * 8 exceeds that size.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (concurrent
+ * streams or threads) race and must be serialised by the caller. */
+int lobpcg_gram_noalloc(int64_t n, int32_t m, int32_t p, int32_t p1, int32_t dtype,
+                        const void* L, int64_t ldl, const void* R1, int64_t ldr1, const void* R2,
+                        int64_t ldr2, double* G, int64_t ldg, int32_t col_offset, int32_t mirror,
+                        void* stream);
+
+/* Size in bytes of lobpcg_gram_noalloc's fixed device array. */
+int64_t lobpcg_gram_noalloc_max_bytes(void);
+
 /* Basis update Y = beta * Y + alpha * S C (section 5.1, eqs. 10-11 and
  * Algorithm 8's basis update).  S: n x K (lds), C: K x N FP64 COLUMN-major (ldc >= K),
  * rounded to dtype inside the kernel; Y: n x N (ldy).  beta must be 0 or 1;

@@ -144,6 +144,11 @@ SIGNATURES = {
                               C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                               C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
                               C.c_void_p]),
+    "lobpcg_gram_noalloc": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                      C.c_int64, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                      C.c_void_p]),
+    "lobpcg_gram_noalloc_max_bytes": (C.c_int64, []),
     "lobpcg_update": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                 C.c_int64, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                 C.c_void_p, C.c_int64, C.c_void_p]),
@@ -453,6 +458,26 @@ def gram(L, R1, R2=None, col_offset: int = 0, mirror: bool = False, out=None):
                              R2.stride(0) if R2 is not None else 0, _ptr(out), ldg, col_offset,
                              1 if mirror else 0, _ptr(work), _stream()))
     # column-major: tensor row j holds column j
+    G = out.t()
+    return G[:m, col_offset:col_offset + p] if not mirror else G[:m, :col_offset + p]
+
+
+def gram_noalloc(L, R1, R2=None, col_offset: int = 0, mirror: bool = False, out=None):
+    """As gram(), through lobpcg_gram_noalloc (no workspace: the library's fixed
+    device scratch array).  `out` must be preallocated by the caller when the call
+    may not allocate (e.g. under graph capture)."""
+    import torch
+
+    n, m = L.shape
+    p1 = R1.shape[1]
+    p = p1 + (R2.shape[1] if R2 is not None else 0)
+    ldg = max(m, col_offset + p)
+    if out is None:
+        out = torch.zeros((col_offset + p, ldg), dtype=torch.float64, device="cuda")
+    check(load().lobpcg_gram_noalloc(n, m, p, p1, _dtype_code(L), _ptr(L), L.stride(0), _ptr(R1),
+                                     R1.stride(0), _ptr(R2) if R2 is not None else None,
+                                     R2.stride(0) if R2 is not None else 0, _ptr(out), ldg,
+                                     col_offset, 1 if mirror else 0, _stream()))
     G = out.t()
     return G[:m, col_offset:col_offset + p] if not mirror else G[:m, :col_offset + p]
 

@@ -201,6 +201,33 @@ int lobpcg_gram(int64_t n, int32_t m, int32_t p, int32_t p1, int32_t dtype, cons
   });
 }
 
+int lobpcg_gram_noalloc(int64_t n, int32_t m, int32_t p, int32_t p1, int32_t dtype,
+                        const void* L, int64_t ldl, const void* R1, int64_t ldr1, const void* R2,
+                        int64_t ldr2, double* G, int64_t ldg, int32_t col_offset, int32_t mirror,
+                        void* stream) {
+  return guarded([&]() {
+    LOBPCG_CHECK(n >= 0 && m >= 0 && p >= 0 && p1 >= 0 && p1 <= p && ldl >= m && ldg >= m &&
+                     col_offset >= 0,
+                 LOBPCG_ERR_ARG, "lobpcg_gram_noalloc: bad sizes");
+    LOBPCG_CHECK(p1 == p || R2 != nullptr, LOBPCG_ERR_ARG, "lobpcg_gram_noalloc: R2 missing");
+    LOBPCG_CHECK(dtype == 0 || dtype == 1, LOBPCG_ERR_ARG, "dtype must be 0 or 1");
+    LOBPCG_CHECK(!mirror || (col_offset <= m && ldg >= col_offset + p), LOBPCG_ERR_ARG,
+                 "lobpcg_gram_noalloc: mirror needs col_offset <= m and ldg >= col_offset + p");
+    const int mr = mirror ? std::min<int32_t>(col_offset, m) : 0;
+    if (dtype == 0)
+      lobpcg::launch_gram_noalloc<double>(n, m, p, p1, (const double*)L, ldl, (const double*)R1,
+                                          ldr1, (const double*)R2, ldr2, G, col_offset, G,
+                                          col_offset + p1, ldg, mr, as_stream(stream));
+    else
+      lobpcg::launch_gram_noalloc<float>(n, m, p, p1, (const float*)L, ldl, (const float*)R1,
+                                         ldr1, (const float*)R2, ldr2, G, col_offset, G,
+                                         col_offset + p1, ldg, mr, as_stream(stream));
+    return LOBPCG_OK;
+  });
+}
+
+int64_t lobpcg_gram_noalloc_max_bytes(void) { return lobpcg::kGramScratchBytes; }
+
 int lobpcg_update(int64_t n, int32_t K, int32_t N, int32_t dtype, const void* S, int64_t lds,
                   const double* C, int64_t ldc, double alpha, double beta, void* Y, int64_t ldy,
                   void* stream) {

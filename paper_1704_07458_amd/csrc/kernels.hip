@@ -18,6 +18,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -1483,12 +1486,12 @@ int64_t gram_workspace_bytes(int64_t n, int m, int p) {
   return (int64_t)g.nsplit * m * p * (int64_t)sizeof(double);
 }
 
+namespace {
 template <typename T>
-void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const T* R1,
-                 int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,
-                 int64_t ldg, int mirror_rows, void* work, hipStream_t s) {
-  if (m == 0 || p == 0) return;
-  const GramPlan g = gram_plan(n, m, p);
+void launch_gram_plan(const GramPlan& g, int64_t n, int m, int p, int p1, const T* L, int64_t ldl,
+                      const T* R1, int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1,
+                      double* G2, int c2, int64_t ldg, int mirror_rows, void* work,
+                      hipStream_t s) {
   const int nsplit = n > 0 ? g.nsplit : 0;
   double* part = static_cast<double*>(work);
   if (nsplit > 0) {
@@ -1517,6 +1520,68 @@ void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for((int64_t)m * p)), dim3(256), 0, s, m, p,
                      p1, nsplit, part, G1, c1, G2 ? G2 : G1, c2, ldg, mirror_rows);
   LOBPCG_HIP(hipGetLastError());
+}
+}  // namespace
+
+template <typename T>
+void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const T* R1,
+                 int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,
+                 int64_t ldg, int mirror_rows, void* work, hipStream_t s) {
+  if (m == 0 || p == 0) return;
+  launch_gram_plan<T>(gram_plan(n, m, p), n, m, p, p1, L, ldl, R1, ldr1, R2, ldr2, G1, c1, G2, c2,
+                      ldg, mirror_rows, work, s);
+}
+
+// ------------------------------------------------------------------ Gram without allocation
+// The split-K partial tiles of lobpcg_gram_noalloc live in this fixed device
+// array (one per GPU, held until the process ends) instead of a caller's
+// workspace.  In host code the name is only a stand-in: kernels get the
+// device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kGramScratchBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device ordinal
+}  // namespace
+
+void* gram_scratch_address() {
+  int dev = 0;
+  LOBPCG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      throw Error(LOBPCG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+template <typename T>
+void launch_gram_noalloc(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const T* R1,
+                         int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2,
+                         int c2, int64_t ldg, int mirror_rows, hipStream_t s) {
+  if (m == 0 || p == 0) return;
+  const int64_t tile_bytes = (int64_t)m * p * (int64_t)sizeof(double);
+  LOBPCG_CHECK(tile_bytes <= kGramScratchBytes, LOBPCG_ERR_ARG,
+               "lobpcg_gram_noalloc: m * p * 8 = " + std::to_string(tile_bytes) +
+                   " bytes exceeds the fixed scratch of " + std::to_string(kGramScratchBytes) +
+                   " bytes");
+  // the launch of lobpcg_gram, with the split count capped so that the
+  // partial tiles fit the scratch (fewer, longer row ranges)
+  GramPlan g = gram_plan(n, m, p);
+  const int64_t max_split = kGramScratchBytes / tile_bytes;
+  if (g.nsplit > max_split) {
+    int64_t rps = (n + max_split - 1) / max_split;
+    rps = round_up(std::max<int64_t>(rps, kKB), kKB);
+    g.nsplit = (int)std::max<int64_t>(1, (n + rps - 1) / rps);
+    g.rows_per_split = rps;
+  }
+  launch_gram_plan<T>(g, n, m, p, p1, L, ldl, R1, ldr1, R2, ldr2, G1, c1, G2, c2, ldg,
+                      mirror_rows, gram_scratch_address(), s);
 }
 
 int64_t gram_workspace_bound(int64_t n, int m, int p) {
@@ -1782,6 +1847,9 @@ void launch_sqrt_sum(int n, const double* v, double* out, hipStream_t s) {
   template void launch_gram<T>(int64_t, int, int, int, const T*, int64_t, const T*, int64_t,   \
                                const T*, int64_t, double*, int, double*, int, int64_t, int,     \
                                void*, hipStream_t);                                             \
+  template void launch_gram_noalloc<T>(int64_t, int, int, int, const T*, int64_t, const T*,    \
+                                       int64_t, const T*, int64_t, double*, int, double*, int,  \
+                                       int64_t, int, hipStream_t);                              \
   template void launch_update<T>(int64_t, int, int, const T*, int64_t, const double*, int64_t, \
                                  double, double, T*, int64_t, hipStream_t);                     \
   template void launch_residual<T>(int64_t, int, const T*, int64_t, const T*, int64_t,         \

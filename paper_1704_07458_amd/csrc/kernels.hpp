@@ -26,6 +26,18 @@ void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const
                  int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,
                  int64_t ldg, int mirror_rows, void* work, hipStream_t s);
 
+// launch_gram with the split-K partial tiles in a fixed device array of
+// kGramScratchBytes per GPU instead of a workspace (the split count is capped
+// to fit); m * p * 8 > kGramScratchBytes is LOBPCG_ERR_ARG.  Calls that overlap
+// on one GPU share that array and race.
+constexpr int64_t kGramScratchBytes = int64_t(16) << 20;
+template <typename T>
+void launch_gram_noalloc(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const T* R1,
+                         int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2,
+                         int c2, int64_t ldg, int mirror_rows, hipStream_t s);
+// Device address of that array on the current device (looked up once per device).
+void* gram_scratch_address();
+
 // Y = beta*Y + alpha * S C; C is FP64 column-major K x N (ldc).
 template <typename T>
 void launch_update(int64_t n, int K, int N, const T* S, int64_t lds, const double* C, int64_t ldc,
