@@ -1,4 +1,4 @@
-"""Gradients of eigenpairs with respect to the stored values of A (B = I).
+"""Gradients of eigenpairs with respect to the stored values of A (and of B).
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
@@ -16,6 +16,22 @@ form splits y_i into the part inside the computed block X (a k x k sum) and the
 part outside it, which solves the projected shifted system
   (I - X X^T)(A - lambda_i I)(I - X X^T) z_i = -(I - X X^T) xbar_i,  z_i _|_ X,
 by conjugate gradients (block_adjoint()).
+
+Generalised pencil A x = lambda B x with X^T B X = I (the *_generalized
+functions).  Perturbing (A, B) gives
+  d lambda_i = x_i^T (dA - lambda_i dB) x_i,
+  d x_i = sum_{j != i} x_j x_j^T (dA - lambda_i dB) x_i / (lambda_i - lambda_j)
+          - 1/2 x_i (x_i^T dB x_i)        (the last term keeps x_i^T B x_i = 1),
+so with the same y_i (now over B-orthonormal eigenvectors)
+  dL = sum_i lambda_bar_i x_i^T (dA - lambda_i dB) x_i + sum_i y_i^T (dA - lambda_i dB) x_i
+       - 1/2 sum_i (xbar_i^T x_i) x_i^T dB x_i,
+i.e. the A gradient has the form above and the B gradient is
+  g^B_rc = sum_i a_i x_i(r) x_i(c) + 1/2 sum_i b_i (y_i(r) x_i(c) + x_i(r) y_i(c)),
+  a_i = -(lambda_bar_i lambda_i + 1/2 xbar_i^T x_i),  b_i = -lambda_i.
+Outside the computed block y_i solves, with Pi = I - X X^T B (the B-orthogonal
+projector onto the complement of span X),
+  Pi^T (A - lambda_i B) Pi z_i = -Pi^T xbar_i,  y_i = Pi z_i,
+because sum_{j > k} x_j x_j^T = B^-1 - X X^T.
 """
 
 from __future__ import annotations
@@ -24,16 +40,53 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def gradient_on_pattern(A, X, lam_bar, Y):
-    """g over the stored nonzeros of CSR A (same order as A.data / A.indices)."""
+def gradient_on_pattern(A, X, lam_bar, Y, ycoef=None):
+    """g over the stored nonzeros of CSR A (same order as A.data / A.indices):
+    g_rc = sum_i lam_bar_i x_i(r) x_i(c) + 1/2 sum_i ycoef_i (y_i(r) x_i(c) + x_i(r) y_i(c)),
+    ycoef = 1 by default."""
     A = sp.csr_matrix(A)
     rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
     cols = A.indices
     g = np.zeros(A.nnz)
     for i in range(X.shape[1]):
+        b = 1.0 if ycoef is None else ycoef[i]
         g += lam_bar[i] * X[rows, i] * X[cols, i]
-        g += 0.5 * (Y[rows, i] * X[cols, i] + X[rows, i] * Y[cols, i])
+        g += 0.5 * b * (Y[rows, i] * X[cols, i] + X[rows, i] * Y[cols, i])
     return g
+
+
+def b_coefficients(lam, lam_bar, X, X_bar):
+    """(a_i, b_i) of the B gradient: a_i = -(lambda_bar_i lambda_i + 1/2 xbar_i^T x_i),
+    b_i = -lambda_i."""
+    xx = np.einsum("ij,ij->j", X_bar, X) if X_bar is not None else np.zeros(len(lam))
+    return -(lam_bar * lam + 0.5 * xx), -np.asarray(lam, dtype=np.float64)
+
+
+def dense_gradient_generalized(A, B, k, lam_bar, X_bar):
+    """Reference gradients (g_A, g_B) from a full generalised eigendecomposition of
+    the dense pencil (n small); eigenvectors B-orthonormal.  Returns (gA, gB, lam, X)
+    with gA on A's stored pattern and gB on B's."""
+    import scipy.linalg as sla
+
+    Ad = A.toarray() if sp.issparse(A) else np.asarray(A)
+    Bd = B.toarray() if sp.issparse(B) else np.asarray(B)
+    lam_all, V = sla.eigh(Ad, Bd)
+    n = Ad.shape[0]
+    X = V[:, :k]
+    Xb = X_bar(X) if callable(X_bar) else X_bar
+    Y = np.zeros((n, k))
+    for i in range(k):
+        c = V.T @ Xb[:, i]
+        denom = lam_all - lam_all[i]
+        coef = np.zeros(n)
+        mask = np.arange(n) != i
+        coef[mask] = c[mask] / denom[mask]
+        Y[:, i] = -V @ coef
+    lam = lam_all[:k]
+    gA = gradient_on_pattern(A, X, lam_bar, Y)
+    a, b = b_coefficients(lam, lam_bar, X, Xb)
+    gB = gradient_on_pattern(B, X, a, Y, ycoef=b)
+    return gA, gB, lam, X
 
 
 def dense_gradient(A, k, lam_bar, X_bar):
@@ -104,6 +157,56 @@ def projected_cg(A, X, lam, rhs, tol=1e-12, maxit=5000):
             rr = rr_new
         Z[:, i] = proj(z)
     return Z, iters
+
+
+def projected_cg_generalized(A, B, X, lam, rhs, tol=1e-12, maxit=5000):
+    """Solve Pi^T (A - lam_i B) Pi z_i = rhs_i (Pi = I - X X^T B) column by column by
+    plain conjugate gradients from zero; returns y_i = Pi z_i.  rhs must satisfy
+    X^T rhs = 0 (it lies in the range of Pi^T)."""
+    A = sp.csr_matrix(A)
+    B = sp.csr_matrix(B)
+    BX = B @ X
+    Pi = lambda v: v - X @ (BX.T @ v)
+    PiT = lambda v: v - BX @ (X.T @ v)
+    n, k = rhs.shape
+    Z = np.zeros((n, k))
+    iters = np.zeros(k, dtype=int)
+    for i in range(k):
+        b = rhs[:, i]
+        bn = np.linalg.norm(b)
+        if bn == 0.0:
+            continue
+        z = np.zeros(n)
+        r = b.copy()
+        p = r.copy()
+        rr = r @ r
+        for it in range(maxit):
+            q = Pi(p)
+            Ap = PiT(A @ q - lam[i] * (B @ q))
+            alpha = rr / (p @ Ap)
+            z += alpha * p
+            r -= alpha * Ap
+            rr_new = r @ r
+            iters[i] = it + 1
+            if np.sqrt(rr_new) <= tol * bn:
+                break
+            p = r + (rr_new / rr) * p
+            rr = rr_new
+        Z[:, i] = Pi(z)
+    return Z, iters
+
+
+def block_adjoint_generalized(A, B, lam, X, lam_bar, X_bar, tol=1e-12, maxit=5000):
+    """(g_A, g_B) from the k computed B-orthonormal eigenpairs (lam, X) of (A, B)."""
+    B = sp.csr_matrix(B)
+    Yin = in_block_part(lam, X, X_bar)
+    rhs = -(X_bar - (B @ X) @ (X.T @ X_bar))
+    Yout, iters = projected_cg_generalized(A, B, X, lam, rhs, tol=tol, maxit=maxit)
+    Y = Yin + Yout
+    gA = gradient_on_pattern(A, X, lam_bar, Y)
+    a, b = b_coefficients(lam, lam_bar, X, X_bar)
+    gB = gradient_on_pattern(B, X, a, Y, ycoef=b)
+    return gA, gB, iters
 
 
 def block_adjoint(A, lam, X, lam_bar, X_bar, tol=1e-12, maxit=5000):
