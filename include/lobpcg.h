@@ -172,7 +172,8 @@ typedef struct {
                                  hide that error from the next step's Cholesky test */
   int32_t fp32_fallback;      /* precision split: 1 when the FP32 phase broke down (or met a
                                  non-finite value) and the FP64 phase took over from the last
-                                 finite block (or from X0) */
+                                 finite block (or from X0); 2 when it stopped because no further
+                                 pair met fp32_tol within 200 iterations (FP32 residual floor) */
 } lobpcg_info;
 
 /* Fill *opt with the defaults documented above. */
@@ -206,26 +207,31 @@ int lobpcg_eigpairs(lobpcg_t h, int32_t count, double* lambda, double* X, int64_
                     double* rel_resid, int32_t on_device);
 
 /* Gradient of a loss L(lambda_1..k, x_1..k) with respect to the stored values
- * of A, from the first `count` eigenpairs of the last solve (B = I only).
- * First-order perturbation: d lambda_i = x_i^T dA x_i; eigenvector adjoints
- * y_i = -sum_{j != i} x_j (x_j^T xbar_i) / (lambda_j - lambda_i), split into the
- * part inside the computed block and a projected conjugate-gradient solve of
- * (I - X X^T)(A - lambda_i I)(I - X X^T) z = -(I - X X^T) xbar_i for the rest.
- * grad[p] for stored entry p = (r, c):
- *   sum_i lambda_bar_i x_i(r) x_i(c) + 1/2 sum_i (y_i(r) x_i(c) + x_i(r) y_i(c)).
+ * of A (and of B) from the first `count` eigenpairs of the last solve (x_i
+ * B-orthonormal).  First-order perturbation of A x = lambda B x:
+ *   d lambda_i = x_i^T (dA - lambda_i dB) x_i,
+ *   y_i = -sum_{j != i} x_j (x_j^T xbar_i) / (lambda_j - lambda_i),
+ * split into the part inside the computed block and a projected conjugate-
+ * gradient solve of Pi^T (A - lambda_i B) Pi z = -Pi^T xbar_i, y_i = Pi z, with
+ * Pi = I - X X^T B (I - X X^T when B = I) for the rest.  For stored entry
+ * p = (r, c), with the symmetric convention (a_rc and a_cr move together):
+ *   grad[p]   = sum_i lambda_bar_i x_i(r) x_i(c) + 1/2 sum_i (y_i(r) x_i(c) + x_i(r) y_i(c)),
+ *   grad_B[p] = sum_i a_i x_i(r) x_i(c) + 1/2 sum_i b_i (y_i(r) x_i(c) + x_i(r) y_i(c)),
+ *   a_i = -(lambda_bar_i lambda_i + 1/2 xbar_i^T x_i), b_i = -lambda_i
+ * (the xbar_i^T x_i term keeps x_i^T B x_i = 1).
  * lambda_bar: count values (host, may be NULL = 0); X_bar: row-major n x count
  * DEVICE block with leading dimension ld_xbar (may be NULL = 0); grad: nnz(A)
- * DEVICE values.  cg_tol: relative residual of the projected solve (<= 0: 1e-12);
- * cg_maxit <= 0: 10000.  cg_iters (host, may be NULL) receives the largest CG
- * iteration count.  The CG residual is re-projected against X every step; a
- * column whose curvature p^T (projected operator) p is no longer positive has
- * reached the rounding floor and stops there.  Returns LOBPCG_OK, or
- * LOBPCG_NOT_CONVERGED when cg_maxit is reached with columns above cg_tol (grad
- * is still written, from the last iterate).  Errors: LOBPCG_ERR_STATE,
- * LOBPCG_ERR_ARG (B != I). */
+ * DEVICE values; grad_B: nnz(B) DEVICE values or NULL (must be NULL when B = I).
+ * cg_tol: relative residual of the projected solve (<= 0: 1e-12); cg_maxit <= 0:
+ * 10000.  cg_iters (host, may be NULL) receives the largest CG iteration count.
+ * The CG residual is re-projected every step; a column whose curvature
+ * p^T (projected operator) p is no longer positive has reached the rounding
+ * floor and stops there.  Returns LOBPCG_OK, or LOBPCG_NOT_CONVERGED when
+ * cg_maxit is reached with columns above cg_tol (the gradients are still
+ * written, from the last iterate).  Errors: LOBPCG_ERR_STATE, LOBPCG_ERR_ARG. */
 int lobpcg_adjoint(lobpcg_t h, int32_t count, const double* lambda_bar, const double* X_bar,
-                   int64_t ld_xbar, double* grad, double cg_tol, int32_t cg_maxit,
-                   int32_t* cg_iters);
+                   int64_t ld_xbar, double* grad, double* grad_B, double cg_tol,
+                   int32_t cg_maxit, int32_t* cg_iters);
 
 /* Problem dimensions of a handle (any pointer may be NULL). */
 int lobpcg_dims(lobpcg_t h, int64_t* n, int32_t* k, int32_t* n_x);

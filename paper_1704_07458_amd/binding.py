@@ -129,7 +129,8 @@ SIGNATURES = {
     "lobpcg_eigpairs": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                   C.c_void_p, C.c_int32]),
     "lobpcg_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
-                                 C.c_void_p, C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
+                                 C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                 C.POINTER(C.c_int32)]),
     "lobpcg_dims": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32)]),
     "lobpcg_destroy": (None, [C.c_void_p]),
@@ -329,6 +330,7 @@ class Solver:
         check(lib.lobpcg_dims(h, C.byref(n), C.byref(kk), C.byref(nx)))
         self.n, self.n_x = int(n.value), int(nx.value)
         self.nnz_A = int(a.nnz)
+        self.nnz_B = int(b.nnz) if b is not None else None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -397,11 +399,19 @@ class Solver:
         check(load().lobpcg_eigpairs(self._h, count, _ptr(lam), _ptr(X), count, _ptr(rho), 1))
         return lam, X, rho
 
-    def adjoint(self, count: int, lambda_bar, X_bar, cg_tol: float = 1e-12, cg_maxit: int = 0):
-        """Gradient on the stored values of A (device tensor of nnz(A) values)."""
+    def adjoint(self, count: int, lambda_bar, X_bar, cg_tol: float = 1e-12, cg_maxit: int = 0,
+                want_B: bool = False):
+        """Gradient on the stored values of A (device tensor of nnz(A) values) and the
+        largest CG iteration count; with want_B (B != I) also the gradient on B's
+        stored values: (grad_A, iters, grad_B)."""
         import torch
 
         grad = torch.empty(self.nnz_A, dtype=torch.float64, device="cuda")
+        gB = None
+        if want_B:
+            if self.nnz_B is None:
+                raise ValueError("want_B needs a pencil with B != I")
+            gB = torch.empty(self.nnz_B, dtype=torch.float64, device="cuda")
         lb = None
         if lambda_bar is not None:
             lb = np.ascontiguousarray(np.asarray(lambda_bar, dtype=np.float64))
@@ -410,10 +420,13 @@ class Solver:
         st = check(load().lobpcg_adjoint(self._h, int(count),
                                          lb.ctypes.data if lb is not None else None,
                                          _ptr(xb) if xb is not None else None, int(count),
-                                         _ptr(grad), float(cg_tol), int(cg_maxit), C.byref(iters)))
+                                         _ptr(grad), _ptr(gB) if gB is not None else None,
+                                         float(cg_tol), int(cg_maxit), C.byref(iters)))
         if st == LOBPCG_NOT_CONVERGED:
             warnings.warn(f"lobpcg_adjoint: projected CG reached cg_maxit ({int(iters.value)}) "
                           f"above cg_tol {cg_tol:g}", RuntimeWarning, stacklevel=2)
+        if want_B:
+            return grad, int(iters.value), gB
         return grad, int(iters.value)
 
 

@@ -1,13 +1,17 @@
 // Gradient of a loss on computed eigenpairs with respect to the stored values
-// of A (standard problem, B = I), from first-order perturbation theory:
-//   d lambda_i = x_i^T dA x_i,
+// of A (and of B for a generalised pencil), from first-order perturbation
+// theory of A x = lambda B x with X^T B X = I:
+//   d lambda_i = x_i^T (dA - lambda_i dB) x_i,
 //   y_i = -sum_{j != i} x_j (x_j^T xbar_i) / (lambda_j - lambda_i),
-//   grad_rc = sum_i lambda_bar_i x_i(r) x_i(c) + 1/2 sum_i (y_i(r) x_i(c) + x_i(r) y_i(c)).
+//   gradA_rc = sum_i lambda_bar_i x_i(r) x_i(c) + 1/2 sum_i (y_i(r) x_i(c) + x_i(r) y_i(c)),
+//   gradB_rc = sum_i a_i x_i(r) x_i(c) + 1/2 sum_i b_i (y_i(r) x_i(c) + x_i(r) y_i(c)),
+//   a_i = -(lambda_bar_i lambda_i + 1/2 xbar_i^T x_i), b_i = -lambda_i
+// (the 1/2 xbar_i^T x_i term comes from keeping x_i^T B x_i = 1).
 // y_i is split into the part inside the computed block X (a count x count sum)
 // and the part outside, which solves the projected shifted system
-//   (I - X X^T)(A - lambda_i I)(I - X X^T) z_i = -(I - X X^T) xbar_i
-// by conjugate gradients run on all columns at once (one sparse product per
-// step for the whole block).
+//   Pi^T (A - lambda_i B) Pi z_i = -Pi^T xbar_i,  y_i = Pi z_i,  Pi = I - X X^T B
+// (Pi = I - X X^T when B = I) by conjugate gradients run on all columns at once
+// (one sparse product with A, and one with B, per step for the whole block).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -163,10 +167,12 @@ __global__ void init_active_kernel(int m, const double* bn2, int* active) {
 }
 
 // One wave per row; lanes over eigenpair index i (chunks of 64), shuffle sums.
+// grad[p] = sum_i a_i x_i(r) x_i(c) + 1/2 b_i (y_i(r) x_i(c) + x_i(r) y_i(c)); b = NULL means 1.
 __global__ __launch_bounds__(256) void scatter_grad_kernel(
     int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind, int m,
     const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y, int64_t ldy,
-    const double* __restrict__ lbar, double* __restrict__ grad) {
+    const double* __restrict__ lbar, const double* __restrict__ ycoef,
+    double* __restrict__ grad) {
   const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   if (r >= n) return;
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(256) void scatter_grad_kernel(
       if (i < m) {
         const double xr = X[r * ldx + i], xc = X[c * ldx + i];
         const double yr = Y[r * ldy + i], yc = Y[c * ldy + i];
-        acc += lbar[i] * xr * xc + 0.5 * (yr * xc + xr * yc);
+        acc += lbar[i] * xr * xc + 0.5 * (ycoef ? ycoef[i] : 1.0) * (yr * xc + xr * yc);
       }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
@@ -186,19 +192,33 @@ __global__ __launch_bounds__(256) void scatter_grad_kernel(
   }
 }
 
+// a_i = -(lambda_bar_i lambda_i + 1/2 xbar_i^T x_i), b_i = -lambda_i, with
+// xbar_i^T x_i = G(i, i) of G = X^T Xbar (column-major, ldg; NULL = 0).
+__global__ void b_coef_kernel(int m, const double* __restrict__ lbar,
+                              const double* __restrict__ lam, const double* __restrict__ G,
+                              int64_t ldg, double* __restrict__ a, double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double xx = G ? G[i + (int64_t)i * ldg] : 0.0;
+  a[i] = -(lbar[i] * lam[i] + 0.5 * xx);
+  b[i] = -lam[i];
+}
+
 inline unsigned nblk(int64_t total) { return (unsigned)((total + 255) / 256); }
 
 }  // namespace
 
 int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, int64_t ld_xbar,
-                    double* grad, double cg_tol, int cg_maxit, int32_t* cg_iters) {
+                    double* grad, double* grad_B, double cg_tol, int cg_maxit,
+                    int32_t* cg_iters) {
   LOBPCG_CHECK(solved_, LOBPCG_ERR_STATE, "adjoint called before a solve");
-  LOBPCG_CHECK(!haveB_, LOBPCG_ERR_ARG, "adjoint supports B = I only");
   LOBPCG_CHECK(opt_.largest == 0, LOBPCG_ERR_ARG,
                "adjoint is not provided for the largest-eigenpair mode");
   LOBPCG_CHECK(count >= 1 && count <= nx_, LOBPCG_ERR_ARG, "count must be in [1, n_x]");
   LOBPCG_CHECK(grad != nullptr, LOBPCG_ERR_ARG, "grad is NULL");
+  LOBPCG_CHECK(grad_B == nullptr || haveB_, LOBPCG_ERR_ARG, "grad_B given but B = I");
   LOBPCG_CHECK(X_bar == nullptr || ld_xbar >= count, LOBPCG_ERR_ARG, "ld_xbar < count");
+  AllocatorScope scope(&alloc_);
   const double tol = cg_tol > 0 ? cg_tol : 1e-12;
   const int maxit = cg_maxit > 0 ? cg_maxit : 10000;
   const int64_t n = n_;
@@ -208,17 +228,25 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
   const int64_t ldx = ldS_;
   const double* lam = theta_.as<double>();
   hipStream_t s = s_;
+  const bool gen = haveB_;
 
   DevBuf Y(sizeof(double) * n * ld), Z(sizeof(double) * n * ld), R(sizeof(double) * n * ld),
       P(sizeof(double) * n * ld), AP(sizeof(double) * n * ld);
+  // B != I: B X, B P (then B Pi P) and Pi P
+  DevBuf BXb, BPb, Qb;
+  if (gen) {
+    BXb.alloc(sizeof(double) * n * ld);
+    BPb.alloc(sizeof(double) * n * ld);
+    Qb.alloc(sizeof(double) * n * ld);
+  }
   const int64_t nb = (n + kRows - 1) / kRows;
   DevBuf small(sizeof(double) * (size_t)(m * m * 3 + 16 * m + 16));
   DevBuf part(sizeof(double) * (size_t)std::max<int64_t>(nb * m, 1));
-  DevBuf gws(gram_workspace_bound(n, m, m));
+  DevBuf gws(gram_workspace_bound(n, m, m, false));
   DevBuf flags(sizeof(int) * (m + 4));
   double* G = small.as<double>();
-  double* coef = G + m * m;
-  double* vec = coef + m * m;
+  double* G0 = G + m * m;    // X^T Xbar, kept for the B coefficients
+  double* vec = G0 + m * m;
   double* lb = vec;          // m
   double* rr = lb + m;       // m
   double* rrn = rr + m;      // m
@@ -226,6 +254,9 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
   double* alpha = pap + m;   // m
   double* beta = alpha + m;  // m
   double* bn2 = beta + m;    // m
+  double* coefA = bn2 + m;   // m  (a_i of the B gradient)
+  double* coefB = coefA + m; // m  (b_i of the B gradient)
+  double* coef = coefB + m;  // m x m (in-block coefficients) -- fits: 3 m^2 + 16 m + 16
   int* active = flags.as<int>();
   int* nact = active + m;
 
@@ -238,6 +269,24 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
   double* Rp = R.as<double>();
   double* Pp = P.as<double>();
   double* APp = AP.as<double>();
+  double* BX = gen ? BXb.as<double>() : nullptr;
+  double* BPp = gen ? BPb.as<double>() : nullptr;
+  double* Qp = gen ? Qb.as<double>() : nullptr;
+  // B X (or X itself): Pi^T v = v - BX (X^T v)
+  const double* BXe = gen ? BX : X;
+  const int64_t ldbx = gen ? ld : ldx;
+  const DevCsr* Bm = gen ? &B_ : nullptr;
+  auto spmm_dev = [&](const DevCsr& M, const double* in, double* out) {
+    launch_spmm<double>(n, M.rowptr.as<int64_t>(), M.colind.as<int32_t>(), M.v64.as<double>(), in,
+                        ld, out, ld, m, s);
+  };
+  auto xt = [&](const double* V, int64_t ldv, double* out) {  // out = X^T V (m x m, cm)
+    launch_gram<double>(n, m, m, m, X, ldx, V, ldv, nullptr, 0, out, 0, nullptr, 0, m, 0,
+                        gws.get(), s);
+  };
+  if (gen)
+    launch_spmm<double>(n, Bm->rowptr.as<int64_t>(), Bm->colind.as<int32_t>(),
+                        Bm->v64.as<double>(), X, ldx, BX, ld, m, s);
   LOBPCG_HIP(hipMemsetAsync(Yp, 0, sizeof(double) * n * ld, s));
   LOBPCG_HIP(hipMemsetAsync(Zp, 0, sizeof(double) * n * ld, s));
   int iters = 0;
@@ -245,15 +294,14 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
   if (X_bar) {
     converged = false;
     // In-block part: Y = X coef, coef(j, i) = -(x_j^T xbar_i) / (lambda_j - lambda_i).
-    launch_gram<double>(n, m, m, m, X, ldx, X_bar, ld_xbar, nullptr, 0, G, 0, nullptr, 0, m, 0,
-                        gws.get(), s);
-    hipLaunchKernelGGL(inblock_coef_kernel, dim3(nblk(m * m)), dim3(256), 0, s, m, G, (int64_t)m,
-                       lam, coef, (int64_t)m);
+    xt(X_bar, ld_xbar, G0);
+    hipLaunchKernelGGL(inblock_coef_kernel, dim3(nblk(m * m)), dim3(256), 0, s, m, G0,
+                       (int64_t)m, lam, coef, (int64_t)m);
     launch_update<double>(n, m, m, X, ldx, coef, m, 1.0, 0.0, Yp, ld, s);
-    // rhs = -(I - X X^T) xbar = -xbar + X (X^T xbar)
+    // rhs = -Pi^T xbar = -xbar + BX (X^T xbar)
     hipLaunchKernelGGL(scale_copy_kernel, dim3(nblk(n * m)), dim3(256), 0, s, n, m, -1.0, X_bar,
                        ld_xbar, Rp, ld);
-    launch_update<double>(n, m, m, X, ldx, G, m, 1.0, 1.0, Rp, ld, s);
+    launch_update<double>(n, m, m, BXe, ldbx, G0, m, 1.0, 1.0, Rp, ld, s);
     // Projected CG, all columns at once.
     launch_copy2d<double, double>(n, m, Rp, ld, Pp, ld, s);
     auto coldot = [&](const double* A1, const double* B1, double* out) {
@@ -271,25 +319,35 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
     LOBPCG_HIP(hipHostMalloc((void**)&hflag, sizeof(int32_t) * 2, hipHostMallocDefault));
     try {
       for (iters = 0; iters < maxit; ++iters) {
-        // AP = (I - X X^T)(A - lambda I) P
-        launch_spmm<double>(n, A_.rowptr.as<int64_t>(), A_.colind.as<int32_t>(), A_.v64.as<double>(),
-                            Pp, ld, APp, ld, m, s);
-        hipLaunchKernelGGL(shift_kernel, dim3(nblk(n * m)), dim3(256), 0, s, n, m, lam, Pp, ld,
+        // AP = Pi^T (A - lambda B) Pi P.  B = I: P stays in the range of Pi
+        // (the residual is projected every step), so Pi P = P.
+        const double* Qs = Pp;
+        const double* BQ = Pp;
+        if (gen) {
+          // Q = Pi P = P - X (X^T B P); B Q = B P - B X (X^T B P)
+          spmm_dev(*Bm, Pp, BPp);
+          xt(BPp, ld, G);
+          launch_copy2d<double, double>(n, m, Pp, ld, Qp, ld, s);
+          launch_update<double>(n, m, m, X, ldx, G, m, -1.0, 1.0, Qp, ld, s);
+          launch_update<double>(n, m, m, BX, ld, G, m, -1.0, 1.0, BPp, ld, s);
+          Qs = Qp;
+          BQ = BPp;
+        }
+        spmm_dev(A_, Qs, APp);
+        hipLaunchKernelGGL(shift_kernel, dim3(nblk(n * m)), dim3(256), 0, s, n, m, lam, BQ, ld,
                            APp, ld);
-        launch_gram<double>(n, m, m, m, X, ldx, APp, ld, nullptr, 0, G, 0, nullptr, 0, m, 0,
-                            gws.get(), s);
-        launch_update<double>(n, m, m, X, ldx, G, m, -1.0, 1.0, APp, ld, s);
+        xt(APp, ld, G);
+        launch_update<double>(n, m, m, BXe, ldbx, G, m, -1.0, 1.0, APp, ld, s);
         coldot(Pp, APp, pap);
         hipLaunchKernelGGL(cg_alpha_kernel, dim3(nblk(m)), dim3(256), 0, s, m, rr, pap, active,
                            alpha, nact + 1);
         hipLaunchKernelGGL(cg_step_kernel, dim3(nblk(n * m)), dim3(256), 0, s, n, m, alpha, Pp,
                            APp, Zp, Rp, ld);
-        // R <- (I - X X^T) R: AP is orthogonal to X only up to rounding, and the
-        // part of R inside span(X) would otherwise accumulate, never decay, and
+        // R <- Pi^T R: AP lies in the range of Pi^T only up to rounding, and the
+        // part of R outside it would otherwise accumulate, never decay, and
         // put a floor under ||R|| that the projected operator cannot see.
-        launch_gram<double>(n, m, m, m, X, ldx, Rp, ld, nullptr, 0, G, 0, nullptr, 0, m, 0,
-                            gws.get(), s);
-        launch_update<double>(n, m, m, X, ldx, G, m, -1.0, 1.0, Rp, ld, s);
+        xt(Rp, ld, G);
+        launch_update<double>(n, m, m, BXe, ldbx, G, m, -1.0, 1.0, Rp, ld, s);
         coldot(Rp, Rp, rrn);
         hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(256), 0, s, m, rr, rrn, bn2, tol2, active,
                            beta, nact);
@@ -309,15 +367,26 @@ int Solver::adjoint(int count, const double* lambda_bar, const double* X_bar, in
       throw;
     }
     LOBPCG_HIP(hipHostFree(hflag));
-    // Z <- (I - X X^T) Z, then Y += Z (the out-of-block part).
-    launch_gram<double>(n, m, m, m, X, ldx, Zp, ld, nullptr, 0, G, 0, nullptr, 0, m, 0, gws.get(),
-                        s);
+    // Z <- Pi Z = Z - X (X^T B Z), then Y += Z (the out-of-block part).
+    if (gen) {
+      spmm_dev(*Bm, Zp, BPp);
+      xt(BPp, ld, G);
+    } else {
+      xt(Zp, ld, G);
+    }
     launch_update<double>(n, m, m, X, ldx, G, m, -1.0, 1.0, Zp, ld, s);
     hipLaunchKernelGGL(axpy_kernel, dim3(nblk(n * m)), dim3(256), 0, s, n, m, Zp, ld, Yp, ld);
   }
   hipLaunchKernelGGL(scatter_grad_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n,
                      A_.rowptr.as<int64_t>(), A_.colind.as<int32_t>(), m, X, ldx, Yp, ld, lb,
-                     grad);
+                     (const double*)nullptr, grad);
+  if (grad_B) {
+    hipLaunchKernelGGL(b_coef_kernel, dim3(nblk(m)), dim3(256), 0, s, m, lb, lam,
+                       X_bar ? G0 : nullptr, (int64_t)m, coefA, coefB);
+    hipLaunchKernelGGL(scatter_grad_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n,
+                       B_.rowptr.as<int64_t>(), B_.colind.as<int32_t>(), m, X, ldx, Yp, ld,
+                       coefA, coefB, grad_B);
+  }
   LOBPCG_HIP(hipGetLastError());
   LOBPCG_HIP(hipStreamSynchronize(s));
   if (cg_iters) *cg_iters = iters;

@@ -104,11 +104,11 @@ int lobpcg_eigpairs(lobpcg_t h, int32_t count, double* lambda, double* X, int64_
 }
 
 int lobpcg_adjoint(lobpcg_t h, int32_t count, const double* lambda_bar, const double* X_bar,
-                   int64_t ld_xbar, double* grad, double cg_tol, int32_t cg_maxit,
-                   int32_t* cg_iters) {
+                   int64_t ld_xbar, double* grad, double* grad_B, double cg_tol,
+                   int32_t cg_maxit, int32_t* cg_iters) {
   return guarded([&]() {
     LOBPCG_CHECK(h && h->solver, LOBPCG_ERR_ARG, "NULL handle");
-    return h->solver->adjoint(count, lambda_bar, X_bar, ld_xbar, grad, cg_tol, cg_maxit,
+    return h->solver->adjoint(count, lambda_bar, X_bar, ld_xbar, grad, grad_B, cg_tol, cg_maxit,
                               cg_iters);
   });
 }
@@ -171,9 +171,8 @@ int lobpcg_spmm(int64_t n, const int64_t* rowptr, const int32_t* colind, const v
 }
 
 int64_t lobpcg_gram_workspace(int64_t n, int32_t m, int32_t p, int32_t dtype) {
-  (void)dtype;
-  if (n < 0 || m < 0 || p < 0) return -1;
-  return lobpcg::gram_workspace_bytes(n, m, p);
+  if (n < 0 || m < 0 || p < 0 || (dtype != 0 && dtype != 1)) return -1;
+  return lobpcg::gram_workspace_bytes(n, m, p, dtype == 1);
 }
 
 int lobpcg_gram(int64_t n, int32_t m, int32_t p, int32_t p1, int32_t dtype, const void* L,

@@ -335,7 +335,13 @@ struct GramPlan {
 // resident at once even while a one-workgroup kernel holds a CU beside it.
 constexpr int kGramTargetBlocks = 510;
 
-GramPlan gram_plan(int64_t n, int m, int p) {
+// In FP32 the MFMA accumulators sum one split's rows in FP32; at most
+// kGramFp32MaxRows rows per split (the splits' partial tiles are summed in
+// FP64) keeps that rounding near sqrt(kGramFp32MaxRows) eps_32 (about 1e-5)
+// even when the tiles alone would leave a single split of ~1e6 rows.
+constexpr int64_t kGramFp32MaxRows = 8192;
+
+GramPlan gram_plan(int64_t n, int m, int p, bool fp32) {
   GramPlan g;
   // the tile pair that pads m x p least (ties: the earlier, larger tiles); a
   // 112-wide side (seven 16-blocks, n_s = 330 -> 336, 2 n_w = 220 -> 224) takes
@@ -359,6 +365,7 @@ GramPlan gram_plan(int64_t n, int m, int p) {
   int64_t target = std::max<int64_t>(1, kGramTargetBlocks / std::max(ntiles, 1));
   int64_t max_by_rows = std::max<int64_t>(1, n / 256);
   int64_t ns = std::min(target, max_by_rows);
+  if (fp32) ns = std::max(ns, (n + kGramFp32MaxRows - 1) / kGramFp32MaxRows);
   int64_t rps = (n + ns - 1) / ns;
   rps = round_up(std::max<int64_t>(rps, kKB), kKB);
   g.nsplit = (int)((n + rps - 1) / rps);
@@ -1480,9 +1487,9 @@ void launch_spmm(int64_t n, const int64_t* rowptr, const int32_t* colind, const 
   LOBPCG_HIP(hipGetLastError());
 }
 
-int64_t gram_workspace_bytes(int64_t n, int m, int p) {
+int64_t gram_workspace_bytes(int64_t n, int m, int p, bool fp32) {
   if (n == 0 || m == 0 || p == 0) return 0;
-  const GramPlan g = gram_plan(n, m, p);
+  const GramPlan g = gram_plan(n, m, p, fp32);
   return (int64_t)g.nsplit * m * p * (int64_t)sizeof(double);
 }
 
@@ -1528,7 +1535,8 @@ void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const
                  int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,
                  int64_t ldg, int mirror_rows, void* work, hipStream_t s) {
   if (m == 0 || p == 0) return;
-  launch_gram_plan<T>(gram_plan(n, m, p), n, m, p, p1, L, ldl, R1, ldr1, R2, ldr2, G1, c1, G2, c2,
+  launch_gram_plan<T>(gram_plan(n, m, p, sizeof(T) == 4), n, m, p, p1, L, ldl, R1, ldr1, R2, ldr2,
+                      G1, c1, G2, c2,
                       ldg, mirror_rows, work, s);
 }
 
@@ -1572,7 +1580,7 @@ void launch_gram_noalloc(int64_t n, int m, int p, int p1, const T* L, int64_t ld
                    " bytes");
   // the launch of lobpcg_gram, with the split count capped so that the
   // partial tiles fit the scratch (fewer, longer row ranges)
-  GramPlan g = gram_plan(n, m, p);
+  GramPlan g = gram_plan(n, m, p, sizeof(T) == 4);
   const int64_t max_split = kGramScratchBytes / tile_bytes;
   if (g.nsplit > max_split) {
     int64_t rps = (n + max_split - 1) / max_split;
@@ -1584,10 +1592,12 @@ void launch_gram_noalloc(int64_t n, int m, int p, int p1, const T* L, int64_t ld
                       mirror_rows, gram_scratch_address(), s);
 }
 
-int64_t gram_workspace_bound(int64_t n, int m, int p) {
-  (void)n;
-  // nsplit <= max(1, target / tiles) and m * p <= tiles * kGramTM * kGramTP.
-  return 8 * std::max<int64_t>((int64_t)kGramTargetBlocks * kGramTM * kGramTP, (int64_t)m * p);
+int64_t gram_workspace_bound(int64_t n, int m, int p, bool fp32) {
+  // nsplit <= max(1, target / tiles) and m * p <= tiles * kGramTM * kGramTP;
+  // in FP32 also nsplit <= ceil(n / kGramFp32MaxRows) for any m' <= m, p' <= p.
+  const int64_t row_splits = fp32 ? std::max<int64_t>(1, (n + kGramFp32MaxRows - 1) / kGramFp32MaxRows) : 1;
+  return 8 * std::max<int64_t>((int64_t)kGramTargetBlocks * kGramTM * kGramTP,
+                               (int64_t)m * p * row_splits);
 }
 
 template <typename T>

@@ -18,9 +18,10 @@ void launch_spmm(int64_t n, const int64_t* rowptr, const int32_t* colind, const 
 // Gram G = L^T [R1 | R2] (L: n x m, R1: n x p1, R2: n x (p - p1)), FP64 output,
 // column-major with leading dimension ldg: column j < p1 goes to column c1 + j of
 // G1, the others to column c2 + j - p1 of G2.  Rows i < mirror_rows are also
-// written transposed.  work must hold gram_workspace_bound(n, m, p) bytes.
-int64_t gram_workspace_bytes(int64_t n, int m, int p);
-int64_t gram_workspace_bound(int64_t n, int m, int p);
+// written transposed.  work must hold gram_workspace_bytes(n, m, p, fp32)
+// bytes; gram_workspace_bound(n, m, p, fp32) covers every m' <= m, p' <= p.
+int64_t gram_workspace_bytes(int64_t n, int m, int p, bool fp32);
+int64_t gram_workspace_bound(int64_t n, int m, int p, bool fp32);
 template <typename T>
 void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const T* R1,
                  int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,

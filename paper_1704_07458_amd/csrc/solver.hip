@@ -180,7 +180,7 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   nc_.alloc(sizeof(int32_t) * 4);
   nrm_.alloc(sizeof(double) * (8 * nx_ + 8));
   X0buf_.alloc(sizeof(double) * (size_t)n_ * nx_);
-  int64_t ws = gram_workspace_bound(n_, nsmax_, 2 * nx_);
+  int64_t ws = gram_workspace_bound(n_, nsmax_, 2 * nx_, split);
   ws = std::max(ws, residual_workspace_bytes(n_, nx_));
   ws = std::max(ws, colsq_workspace_bytes(n_, 2 * nx_));
   ws = std::max(ws, jacobi_workspace_bytes(n_));
@@ -445,6 +445,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
   int rc = LOBPCG_NOT_CONVERGED;
   int it = 0;
   bool have_x = false;  // S[cur] holds a Rayleigh-Ritz block X
+  int nc_best = 0, it_best = 0;  // FP32 phase: last iteration that raised n_c
   try {
   // Algorithm 8's start: Rayleigh-Ritz on X0 (Algorithm 2), X = X0 C.
   phase_mark(7);
@@ -630,6 +631,20 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       rc = LOBPCG_OK;
       break;
     }
+    if constexpr (sizeof(T) == 4) {
+      // The FP32 phase hands over once it stops making progress: when no
+      // further pair has met the FP32 threshold for kFp32StallIters iterations
+      // (its Gram blocks carry FP32 rounding, which sets a residual floor).
+      if (fp32_soft_) {
+        if (nc > nc_best) {
+          nc_best = nc;
+          it_best = it;
+        } else if (it - it_best >= kFp32StallIters) {
+          fp32_stalled_ = true;
+          break;
+        }
+      }
+    }
     if (nx - nc == 0 && np == 0) throw Error(LOBPCG_ERR_BREAKDOWN, "search space collapsed");
   }
   } catch (const Error& e) {
@@ -703,6 +718,7 @@ int Solver::solve(double tol, const double* X0, bool x0_dev, lobpcg_precond_fn K
   if (opt_.precision == 1) {
     const double tol32 = std::max(opt_.fp32_tol > 0 ? opt_.fp32_tol : 1e-5, tol);
     fp32_soft_ = true;
+    fp32_stalled_ = false;
     try {
       rc = run<float>(b32_, A_, B, tol32, maxit, X0b, skip * kEps32, 1e-5, K, Kuser, inf, &iters);
     } catch (...) {
@@ -713,6 +729,7 @@ int Solver::solve(double tol, const double* X0, bool x0_dev, lobpcg_precond_fn K
     inf->fp32_iterations = iters;
     inf->iterations = iters;
     if (rc < 0) inf->fp32_fallback = 1;
+    if (fp32_stalled_) inf->fp32_fallback = 2;
     // FP64 refinement: Algorithm 8 again, started from the FP32 block (now in X0buf).
     const int left = std::max(1, maxit - iters);
     rc = run<double>(b64_, A_, B, tol, left, X0b, skip * kEps64,

@@ -39,7 +39,9 @@ class Solver {
             lobpcg_info* info);
   int eigpairs(int count, double* lambda, double* X, int64_t ldx, double* rho, bool on_device);
   int adjoint(int count, const double* lambda_bar, const double* X_bar, int64_t ld_xbar,
-              double* grad, double cg_tol, int cg_maxit, int32_t* cg_iters);
+              double* grad, double* grad_B, double cg_tol, int cg_maxit, int32_t* cg_iters);
+  bool has_B() const { return haveB_; }
+  int64_t nnz_B() const { return haveB_ ? B_.nnz : 0; }
 
   int64_t n() const { return n_; }
   int k() const { return k_; }
@@ -97,6 +99,8 @@ class Solver {
   // FP32 phase of the precision split: a breakdown or non-finite value hands
   // over to the FP64 phase instead of ending the solve
   bool fp32_soft_ = false;
+  bool fp32_stalled_ = false;
+  static constexpr int kFp32StallIters = 200;
   std::string fp32_failure_;
   double tmark_ = 0.0;
   int cur_phase_ = 7;

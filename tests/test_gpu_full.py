@@ -349,14 +349,64 @@ def adjoint_case(lib):
     return _AdjointCase()
 
 
-def test_adjoint_32cubed_matches_oracle_on_same_pairs(adjoint_case):
-    """Every gradient entry against the oracle's block adjoint run on the GPU's own pairs."""
+@pytest.fixture(scope="module")
+def oracle_adjoint_32cubed():
+    """The oracle's own gradient of the same loss: its LOBPCG to tau = 1e-13 (tau_ortho
+    tightened as on the GPU side), then its block adjoint on its own pairs."""
+    w = P.workload(4)
+    A = w.A.to_scipy()
+    k = w.k
+    rng = np.random.default_rng(0 + 2000)
+    wts = rng.uniform(0.0, 1.0, k)
+    m = rng.uniform(0.0, 1.0, w.A.n)
+    ref = L.lobpcg(A, w.X0, k, 1e-13, precond=L.jacobi_precond(A), maxit=4000,
+                   tols=L.Tolerances(tau_ortho=1e-15))
+    assert ref.converged
+    lam, X = ref.eigenpairs(k)
+    xb = 2.0 * X * (m ** 2)[:, None]
+    g, iters = ADJ.block_adjoint(A, lam, X, wts, xb, tol=1e-13, maxit=5000)
+    return g, int(iters.max()), ref.iterations
+
+
+def test_adjoint_32cubed_matches_the_oracle(adjoint_case, oracle_adjoint_32cubed):
+    """Every gradient entry against the oracle's gradient, each side from its own solve
+    of the 32^3 + U[0, 4] pencil (k = 64) to tau = 1e-13."""
     c = adjoint_case
-    go, iters = ADJ.block_adjoint(c.A, c.lam, c.X, c.wts, c.xb, tol=1e-12, maxit=5000)
+    go, iters, oits = oracle_adjoint_32cubed
     rel = np.linalg.norm(c.g - go) / np.linalg.norm(go)
-    print(f"adjoint vs oracle block adjoint: rel {rel:.2e}; CG iterations GPU {c.cg_iters}, "
-          f"oracle max {iters.max()}")
-    assert rel <= 1e-10
+    print(f"adjoint vs the oracle's: rel {rel:.2e}; CG iterations GPU {c.cg_iters}, "
+          f"oracle max {iters}; oracle LOBPCG iterations {oits}")
+    assert rel <= 1e-9
+
+
+def test_autograd_function_32cubed(adjoint_case, oracle_adjoint_32cubed):
+    """The same loss through LobpcgFunction and torch.autograd.grad: gradients with
+    respect to A's stored values and to the potential V (A = L + diag(V), so
+    dL/dV_j is the gradient of A's diagonal entry j) against the oracle's."""
+    torch = _torch()
+    from paper_1704_07458_amd import autograd as AG
+
+    c = adjoint_case
+    go, _, _ = oracle_adjoint_32cubed
+    w = P.workload(4)
+    L3 = P.laplacian_3d(32)
+    assert np.array_equal(L3.colind, w.A.colind)
+    pat = AG.CsrPattern.from_host(w.A.rowptr, w.A.colind)
+    diag_p = torch.from_numpy(np.flatnonzero(c.rows == c.cols)).cuda()
+    base = torch.from_numpy(L3.values).cuda()
+    V = torch.from_numpy(w.potential).cuda().requires_grad_(True)
+    Avals = base.index_add(0, diag_p, V)
+    lam, X = AG.eigsh(Avals, pat, c.k, tol=1e-13, X0=w.X0, cg_tol=1e-13, precond="jacobi",
+                      maxit=4000, tau_ortho=1e-15)
+    wts = torch.from_numpy(c.wts).cuda()
+    mm = torch.from_numpy(c.m).cuda()
+    loss = (wts * lam).sum() + ((X * mm[:, None]) ** 2).sum()
+    gA, gV = torch.autograd.grad(loss, [Avals, V])
+    gA, gV = gA.cpu().numpy(), gV.cpu().numpy()
+    rel = np.linalg.norm(gA - go) / np.linalg.norm(go)
+    relV = np.linalg.norm(gV - go[np.flatnonzero(c.rows == c.cols)]) / np.linalg.norm(gV)
+    print(f"autograd vs the oracle: A values rel {rel:.2e}, potential rel {relV:.2e}")
+    assert rel <= 1e-9 and relV <= 1e-9
 
 
 def test_adjoint_32cubed_central_differences_h1e4(adjoint_case):

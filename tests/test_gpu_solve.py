@@ -612,6 +612,105 @@ def test_adjoint_matches_dense_reference_8cubed(lib):
     assert iters > 0
 
 
+def _random_fem_pencil(N, seed):
+    """Q1 stiffness + random diagonal, mass + random diagonal on N^3: a symmetric-
+    definite pencil with distinct eigenvalues (the tensor-product pencil has
+    degenerate ones, where eigenvector derivatives are undefined)."""
+    import scipy.sparse as sps
+
+    K, M = P.fem_q1_pencil(N)
+    K, M = K.to_scipy(), M.to_scipy()
+    rng = np.random.default_rng(seed)
+    n = K.shape[0]
+    A = P.from_scipy(K + sps.diags(rng.uniform(0.0, 4.0, n) * K.diagonal().mean()))
+    B = P.from_scipy(M + sps.diags(rng.uniform(0.0, 1.0, n) * M.diagonal().mean()))
+    return A, B
+
+
+def test_generalized_adjoint_matches_dense_reference(lib):
+    """Gradients with respect to A's and B's stored values for a generalised pencil
+    (6^3 Q1 stiffness and mass with random diagonals, k = 8) against the oracle's
+    dense generalised reference (its own full eigendecomposition)."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    Acsr, Bcsr = _random_fem_pencil(6, 7)
+    k = 8
+    s = B.Solver(Acsr, k, B=Bcsr, precond="jacobi", tau_ortho=1e-15)
+    info = s.solve(1e-13, P.initial_block(0, Acsr.n, P.block_size(k)))
+    assert info["converged"], info
+    lam_t, X_t, _ = s.eigpairs(k)
+    X = X_t.cpu().numpy()
+    rng = np.random.default_rng(2003)
+    wts = rng.uniform(0, 1, k)
+    m = rng.uniform(0, 1, Acsr.n)
+    xb_fn = lambda Xd: 2.0 * Xd * (m ** 2)[:, None]
+    gA, iters, gB = s.adjoint(k, wts, torch.from_numpy(xb_fn(X)).cuda(), cg_tol=1e-13,
+                              want_B=True)
+    rA, rB, _, _ = ADJ.dense_gradient_generalized(Acsr.to_scipy(), Bcsr.to_scipy(), k, wts, xb_fn)
+    eA = np.linalg.norm(gA.cpu().numpy() - rA) / np.linalg.norm(rA)
+    eB = np.linalg.norm(gB.cpu().numpy() - rB) / np.linalg.norm(rB)
+    print(f"generalised adjoint vs dense: A rel {eA:.2e}, B rel {eB:.2e}, CG iterations {iters}")
+    assert eA <= 1e-9 and eB <= 1e-9
+    # the standard-problem handle has no B gradient
+    w = P.workload(4, small=True)
+    s2, _ = _gpu_solve(w, maxit=2)
+    with pytest.raises(ValueError):
+        s2.adjoint(1, np.ones(1), None, want_B=True)
+
+
+def test_autograd_function_generalized_pencil(lib):
+    """LobpcgFunction on the generalised pencil: torch.autograd.grad with respect to
+    both value tensors equals the dense generalised reference."""
+    torch = _torch()
+    from paper_1704_07458_amd import autograd as AG
+
+    Acsr, Bcsr = _random_fem_pencil(6, 7)
+    k = 8
+    pa = AG.CsrPattern.from_host(Acsr.rowptr, Acsr.colind)
+    pb = AG.CsrPattern.from_host(Bcsr.rowptr, Bcsr.colind)
+    Av = torch.from_numpy(Acsr.values).cuda().requires_grad_(True)
+    Bv = torch.from_numpy(Bcsr.values).cuda().requires_grad_(True)
+    rng = np.random.default_rng(2003)
+    wts = rng.uniform(0, 1, k)
+    m = rng.uniform(0, 1, Acsr.n)
+    lam, X = AG.eigsh(Av, pa, k, Bv, pb, tol=1e-13, cg_tol=1e-13, precond="jacobi",
+                      tau_ortho=1e-15)
+    loss = (torch.from_numpy(wts).cuda() * lam).sum() + \
+        ((X * torch.from_numpy(m).cuda()[:, None]) ** 2).sum()
+    gA, gB = torch.autograd.grad(loss, [Av, Bv])
+    rA, rB, _, _ = ADJ.dense_gradient_generalized(Acsr.to_scipy(), Bcsr.to_scipy(), k, wts,
+                                                   lambda Xd: 2.0 * Xd * (m ** 2)[:, None])
+    assert np.linalg.norm(gA.cpu().numpy() - rA) <= 1e-9 * np.linalg.norm(rA)
+    assert np.linalg.norm(gB.cpu().numpy() - rB) <= 1e-9 * np.linalg.norm(rB)
+
+
+def test_autograd_function_8cubed_potential(lib):
+    """torch.autograd.grad of the 8^3 + U[0, 4] loss with respect to the potential V
+    (A = L + diag(V)) against the dense reference's diagonal entries."""
+    torch = _torch()
+    from paper_1704_07458_amd import autograd as AG
+
+    w = P.workload(4, small=True)
+    L8 = P.laplacian_3d(8)
+    A = w.A.to_scipy()
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    diag_p = np.flatnonzero(rows == A.indices)
+    pat = AG.CsrPattern.from_host(w.A.rowptr, w.A.colind)
+    V = torch.from_numpy(w.potential).cuda().requires_grad_(True)
+    Av = torch.from_numpy(L8.values).cuda().index_add(0, torch.from_numpy(diag_p).cuda(), V)
+    rng = np.random.default_rng(2000)
+    wts = rng.uniform(0, 1, w.k)
+    m = rng.uniform(0, 1, w.A.n)
+    lam, X = AG.eigsh(Av, pat, w.k, tol=1e-12, X0=w.X0, cg_tol=1e-13, precond="jacobi")
+    loss = (torch.from_numpy(wts).cuda() * lam).sum() + \
+        ((X * torch.from_numpy(m).cuda()[:, None]) ** 2).sum()
+    (gV,) = torch.autograd.grad(loss, [V])
+    g_ref, _, _ = ADJ.dense_gradient(A, w.k, wts, lambda Xd: 2.0 * Xd * (m ** 2)[:, None])
+    ref_V = g_ref[diag_p]
+    assert np.linalg.norm(gV.cpu().numpy() - ref_V) <= 1e-7 * np.linalg.norm(ref_V)
+
+
 def test_solve_is_bitwise_reproducible(lib):
     """Fresh solvers on the same input take the same iterations to the same bits."""
     torch = _torch()

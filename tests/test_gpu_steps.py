@@ -450,12 +450,15 @@ def test_rr_step_full_size_with_clustered_spectrum(lib, n_s, use_ortho):
     assert np.allclose(C.T @ GA @ C, T, atol=1e-10 * scale)
 
 
-@pytest.mark.parametrize("n_s", [2, 3, 17, 33, 64, 100, 330, 512])
+@pytest.mark.parametrize("n_s", [2, 3, 17, 33, 63, 64, 65, 80, 81, 97, 100, 129, 330, 511, 512])
 def test_projected_eigensolver_backward_error(lib, n_s):
     """Rayleigh-Ritz on an orthonormal basis (G_B = I) with n_x = n_s returns the
     full eigendecomposition of G_A: residual and orthogonality at the level of
     a backward-stable dense eigensolver, p(n) eps ||G_A|| and p(n) eps with
-    p(n) = 4 n, on a spectrum with exact 4-fold clusters and a graded tail."""
+    p(n) = 4 n, on a spectrum with exact 4-fold clusters and a graded tail.
+    The sizes cover the one-stage reduction (n_s < 64) and the two-stage one
+    (dense -> band of half-width 16 -> tridiagonal) around its panel and
+    window boundaries (64, 65, 80, 81, 97, 129, 511)."""
     torch = _torch()
     from paper_1704_07458_amd import binding as B
 
