@@ -55,23 +55,34 @@ def _log(msg):
 
 
 def timed_solves(torch, solver, X0, tol, steps, warmup, label):
+    """Warm-up, then `steps` timed solves with kernel events off (the headline), then
+    the same `steps` solves again with the per-kernel HIP events on (the roofline's
+    launch durations).  Returns (seconds per solve, infos, stats, seconds per solve
+    of the events pass)."""
     for i in range(warmup):
         info = solver.solve(tol, X0)
         _log(f"[bench] {label} warmup {i}: {info['status']} iters {info['iterations']} "
              f"{info['seconds_total']:.3f}s")
     torch.cuda.synchronize()
-    solver.kernel_stats(True)
     infos = []
     t0 = time.perf_counter()
     for i in range(steps):
         infos.append(solver.solve(tol, X0))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stats = solver.kernel_stats(False)
     for i, info in enumerate(infos):
         _log(f"[bench] {label} step {i}: {info['status']} iters {info['iterations']} "
              f"{info['seconds_total']:.3f}s")
-    return (t1 - t0) / steps, infos, stats
+    solver.kernel_stats(True)
+    t2 = time.perf_counter()
+    for i in range(steps):
+        solver.solve(tol, X0)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    stats = solver.kernel_stats(False)
+    _log(f"[bench] {label}: {(t1 - t0) / steps:.4f} s per solve, {(t3 - t2) / steps:.4f} s "
+         f"with kernel events")
+    return (t1 - t0) / steps, infos, stats, (t3 - t2) / steps
 
 
 def check_solution(w, lam, X, normA, exact):
@@ -84,32 +95,68 @@ def check_solution(w, lam, X, normA, exact):
     return float(rho.max()), err
 
 
-def cpu_baseline(w, iters, gpu_iters):
-    """The oracle, untuned, on the host: `iters` iterations of the same solve."""
-    from oracle import lobpcg as L
-
+def _oracle_threads():
     try:
         from threadpoolctl import threadpool_info
 
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] + [1]))
     except Exception:
-        cores = len(os.sched_getaffinity(0))
+        return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(w, iters, gpu_iters):
+    """The oracle, untuned, on the host: set-up plus `iters` iterations of the same
+    solve, each iteration timed on its own."""
+    from oracle import lobpcg as L
+
     A = w.A.to_scipy()
     pre = L.jacobi_precond(A)
     t0 = time.perf_counter()
     res = L.lobpcg(A, w.X0, w.k, w.tol, precond=pre, maxit=iters)
     dt = time.perf_counter() - t0
-    per_it = dt / res.iterations
+    its = [h.seconds for h in res.history]
+    setup = dt - sum(its)
+    # Iteration 1 has no P block (n_s = 2 n_x); the later ones are full width.
+    steady = its[1:] if len(its) > 1 else its
+    per_it = sum(steady) / len(steady)
     return {
-        "value": per_it * gpu_iters,
+        "value": setup + per_it * gpu_iters,
         "unit": "s",
-        "cores": int(cores),
+        "cores": _oracle_threads(),
         "kind": "oracle",
-        "sample": (f"{res.iterations} oracle iterations (incl. set-up) of the same 64^3 solve "
-                   f"from the same X0 took {dt:.1f} s = {per_it:.2f} s/iteration; value is that "
-                   f"rate times the GPU FP64 iteration count ({gpu_iters}): an estimate of the "
-                   "oracle's time to k eigenpairs"),
+        "sample": (f"set-up ({setup:.1f} s) and {res.iterations} oracle iterations of the same "
+                   f"64^3 solve from the same X0; iterations 2..{res.iterations} (full "
+                   f"n_s = 3 n_x) average {per_it:.2f} s; value = set-up + that rate times the "
+                   f"GPU FP64 iteration count ({gpu_iters}), an estimate from the start of the "
+                   "solve, where no pair is locked yet and every iteration is full width"),
     }
+
+
+def oracle_full_solve(w, label):
+    """One whole oracle solve, timed (progress every 10 iterations)."""
+    from oracle import lobpcg as L
+
+    A = w.A.to_scipy()
+    B = w.B.to_scipy() if w.B is not None else None
+    pre = L.jacobi_precond(A) if w.precond == "jacobi" else None
+    t_start = time.perf_counter()
+
+    def cb(h):
+        if h.it % 10 == 0:
+            _log(f"[bench] oracle {label}: iteration {h.it}, {h.n_c} pairs converged, "
+                 f"{time.perf_counter() - t_start:.1f} s")
+
+    t0 = time.perf_counter()
+    res = L.lobpcg(A, w.X0, w.k, w.tol, B=B, precond=pre, callback=cb)
+    dt = time.perf_counter() - t0
+    its = np.array([h.seconds for h in res.history])
+    return {"workload": label, "kind": "oracle, whole solve", "converged": bool(res.converged),
+            "iterations": int(res.iterations), "seconds": dt,
+            "setup_seconds": float(dt - its.sum()),
+            "iteration_seconds_mean": float(its.mean()),
+            "iteration_seconds_first5_after_1": float(its[1:6].mean()) if len(its) > 5 else None,
+            "iteration_seconds_last10": float(its[-10:].mean()),
+            "threads": _oracle_threads()}
 
 
 # Versions of section 6 (Fig. 2) that this solver can run: every X/P Gram block
@@ -203,10 +250,12 @@ def run_ksweep(torch, B, P):
 
 
 def _progress_printer(label, every=10):
+    t0 = time.perf_counter()
+
     def cb(it, nc, phase):
         if it % every == 0:
             _log(f"[bench] {label}: iteration {it} ({'fp32' if phase else 'fp64'}), "
-                 f"{nc} pairs converged")
+                 f"{nc} pairs converged, {time.perf_counter() - t0:.1f} s")
     return cb
 
 
@@ -289,14 +338,15 @@ def run_workloads(torch, B, P, which):
             print(json.dumps(line), flush=True)
             s.close()
         del X0
-    if which in ("periodic96", "all"):
+    if which.startswith("periodic96") or which == "all":
+        precisions = [which.split(":")[1]] if ":" in which else ["split", "fp64"]
         L3 = P.laplacian_3d(96, periodic=True)
         A = P.add_diagonal(L3, P.potential(0, L3.n, -8.0, 8.0))
         k = 1000
         As = A.to_scipy()
         normA_bound = float(np.max(np.asarray(abs(As).sum(axis=1)).ravel()))  # Gershgorin
         lams = {}
-        for prec in ("split", "fp64"):
+        for prec in precisions:
             s = B.Solver(A, k, precond="jacobi", precision=prec,
                          progress=_progress_printer(f"periodic96 {prec}"))
             s.kernel_stats(True)
@@ -330,6 +380,68 @@ def run_workloads(torch, B, P, which):
             print(json.dumps(line), flush=True)
             del X
             s.close()
+
+
+def run_small(torch, B, P, reps=10):
+    """Time to k eigenpairs on the 32^2 Laplacian (k = 10) and the 32^3 Laplacian
+    + U[0, 4] potential (k = 64), and the 32^3 adjoint's backward pass."""
+    e1 = 4.0 * np.sin(np.pi * np.arange(1, 33) / 66.0) ** 2
+    exact0 = np.sort((e1[:, None] + e1[None, :]).ravel())[:10]
+    w = P.workload(0)
+    X0 = torch.from_numpy(w.X0).cuda()
+    for prec in ("fp64", "split"):
+        s = B.Solver(w.A, w.k, precond="none", precision=prec)
+        s.solve(w.tol, X0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            info = s.solve(w.tol, X0)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        lam, X, _ = s.eigpairs(w.k)
+        rho, err = check_solution(w, lam.cpu().numpy(), X.cpu().numpy(), info["norm_A_est"],
+                                  exact0)
+        print(json.dumps({"workload": "2D 5-point Dirichlet Laplacian 32^2 (n=1024), k=10, "
+                                      "n_x=11, no preconditioner, tol 1e-8",
+                          "precision": prec, "status": info["status"],
+                          "iterations": info["iterations"],
+                          "iterations_fp32": info["fp32_iterations"],
+                          "seconds": sec, "ms_per_iteration": 1e3 * sec / info["iterations"],
+                          "max_rho": rho, "eig_rel_err_vs_closed_form": err,
+                          "timed": f"mean of {reps} solves after one warm-up"}), flush=True)
+        s.close()
+    w = P.workload(4)
+    X0 = torch.from_numpy(w.X0).cuda()
+    rng = np.random.default_rng(0 + 2000)
+    wts = rng.uniform(0.0, 1.0, w.k)
+    m = rng.uniform(0.0, 1.0, w.A.n)
+    s = B.Solver(w.A, w.k, precond="jacobi")
+    s.solve(w.tol, X0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        info = s.solve(w.tol, X0)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    lam, X, _ = s.eigpairs(w.k)
+    xb = 2.0 * X * torch.from_numpy(m ** 2).cuda()[:, None]
+    s.adjoint(w.k, wts, xb, cg_tol=1e-12)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, cg_iters = s.adjoint(w.k, wts, xb, cg_tol=1e-12)
+    torch.cuda.synchronize()
+    sec_adj = (time.perf_counter() - t0) / reps
+    print(json.dumps({"workload": "3D 7-point Dirichlet 32^3 + U[0,4] potential (n=32768), "
+                                  "k=64, n_x=71, Jacobi, tol 1e-8",
+                      "precision": "fp64", "status": info["status"],
+                      "iterations": info["iterations"], "seconds": sec,
+                      "ms_per_iteration": 1e3 * sec / info["iterations"],
+                      "adjoint_backward_seconds": sec_adj, "adjoint_cg_iterations": cg_iters,
+                      "adjoint": "loss sum_i w_i lambda_i + sum_i ||x_i o m||^2, cg_tol 1e-12",
+                      "timed": f"mean of {reps} solves / backward passes after one warm-up"}),
+          flush=True)
+    s.close()
 
 
 def _fem_smallest(N, k):
@@ -379,8 +491,14 @@ def main():
     ap.add_argument("--ksweep", action="store_true",
                     help="time to k eigenpairs for several k instead (one line each)")
     ap.add_argument("--workloads", nargs="?", const="all", default=None,
-                    choices=["all", "fem48", "periodic96"],
-                    help="time the FEM k=400 and/or periodic k=1000 pencils instead")
+                    choices=["all", "small", "fem48", "periodic96", "periodic96:split",
+                             "periodic96:fp64"],
+                    help="time the FEM k=400 and/or periodic k=1000 pencils instead "
+                         "(periodic96:<precision> runs one precision only)")
+    ap.add_argument("--oracle-full", type=int, default=None, metavar="CFG",
+                    help="only time one whole oracle solve on the host: 0 = 32^2 "
+                         "Laplacian k=10, 1 = 64^3 Laplacian k=100, 2 = FEM 48^3 k=400, "
+                         "4 = 32^3 + potential k=64")
     ap.add_argument("--phases", action="store_true",
                     help="one extra untimed FP64 solve with per-phase timing (stream syncs)")
     args = ap.parse_args()
@@ -388,6 +506,22 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path (a row "
               "partition across GPUs with halo exchange is designed, not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_full is not None:
+        from paper_1704_07458_amd import problems as P
+
+        if args.oracle_full not in (0, 1, 2, 4):
+            sys.exit("--oracle-full takes 0, 1, 2 or 4")
+        w = P.workload(args.oracle_full)
+        label = {0: "2D 5-point Dirichlet Laplacian 32^2 (n=1024), k=10, no preconditioner",
+                 1: "3D 7-point Dirichlet Laplacian 64^3 (n=262144), k=100, Jacobi",
+                 2: "Q1 FEM pencil (K, M) 48^3 (n=110592), k=400, Jacobi",
+                 4: "3D 7-point Dirichlet 32^3 + U[0,4] potential (n=32768), k=64, "
+                    "Jacobi"}[args.oracle_full]
+        line = oracle_full_solve(w, label)
+        line["tol"] = w.tol
+        print(json.dumps(line), flush=True)
+        return
 
     import torch
 
@@ -408,6 +542,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
     B.load()
+    if args.workloads == "small":
+        run_small(torch, B, P)
+        return
     if args.workloads:
         run_workloads(torch, B, P, args.workloads)
         return
@@ -422,7 +559,8 @@ def main():
         return
 
     s64 = B.Solver(w.A, w.k, precond="jacobi")
-    t64, infos64, st64 = timed_solves(torch, s64, X0, w.tol, args.steps, args.warmup, "fp64")
+    t64, infos64, st64, t64_ev = timed_solves(torch, s64, X0, w.tol, args.steps, args.warmup,
+                                              "fp64")
     lam64, X64, _ = s64.eigpairs(w.k)
     lam64_h, X64_h = lam64.cpu().numpy(), X64.cpu().numpy()
     rho64, err64 = check_solution(w, lam64_h, X64_h, infos64[-1]["norm_A_est"], exact)
@@ -439,7 +577,8 @@ def main():
     split = None
     if not args.no_split:
         s32 = B.Solver(w.A, w.k, precond="jacobi", precision="split")
-        t32, infos32, st32 = timed_solves(torch, s32, X0, w.tol, args.steps, args.warmup, "split")
+        t32, infos32, st32, t32_ev = timed_solves(torch, s32, X0, w.tol, args.steps,
+                                                  args.warmup, "split")
         lam32, X32, _ = s32.eigpairs(w.k)
         lam32_h = lam32.cpu().numpy()
         rho32, err32 = check_solution(w, lam32_h, X32.cpu().numpy(), infos32[-1]["norm_A_est"],
@@ -448,6 +587,7 @@ def main():
             "seconds": t32,
             "iterations_fp32": infos32[-1]["fp32_iterations"],
             "iterations_fp64": infos32[-1]["fp64_iterations"],
+            "seconds_with_kernel_events": t32_ev,
             "speedup_vs_fp64": t64 / t32,
             "max_rho": rho32,
             "eig_rel_err_vs_closed_form": err32,
@@ -480,6 +620,8 @@ def main():
     dom = max(per_kernel, key=lambda k: per_kernel[k]["seconds"])
     roof = dict(per_kernel[dom])
     roof["kernel"] = dom
+    roof["launch_durations"] = ("HIP events on the solver's stream around every launch, over a "
+                                "second pass of the same timed solves")
     roof["traffic"] = traffic_from_profiles(dom)
     roof.pop("seconds", None)
     total_kernel_s = sum(v["seconds"] for v in st64.values())
@@ -497,6 +639,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * t64,
+        "ms_per_step_with_kernel_events": 1e3 * t64_ev,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -522,7 +665,8 @@ def main():
         "roofline": roof,
         "kernels": per_kernel,
         "rayleigh_ritz_seconds": st64["rayleigh_ritz"]["seconds"],
-        "kernel_time_share": {k: v["seconds"] / (t64 * args.steps) for k, v in st64.items()},
+        "kernel_time_share": {k: v["seconds"] / (t64_ev * args.steps)
+                              for k, v in st64.items()},
         "cpu_baseline": cpu,
         "phases_fp64_s": phases,
     }

@@ -33,6 +33,7 @@ of the HIP path, with the same default):
 from __future__ import annotations
 
 import dataclasses
+import time
 from typing import Callable, List, Optional
 
 import numpy as np
@@ -382,6 +383,7 @@ class IterRecord:
     n_p: int
     cond_R: float
     max_rho_active: float
+    seconds: float = 0.0  # wall time of the iteration (instrumentation only)
 
 
 @dataclasses.dataclass
@@ -419,6 +421,7 @@ def lobpcg(
     ortho_kind: str = "drop",
     largest: bool = False,
     implicit_products: bool = False,
+    callback: Optional[Callable[["IterRecord"], None]] = None,
 ) -> LobpcgResult:
     """Algorithm 8: the robust and efficient LOBPCG of the paper, FP64.
 
@@ -438,6 +441,8 @@ def lobpcg(
     them in ascending order for -A, so the iteration runs on (-A, B) and the
     Ritz values are negated on return; precond must then approximate the
     inverse of (-A) shifted, as for any pencil.
+    callback: called with each iteration's record (timing and progress only;
+    it takes no part in the arithmetic).
     implicit_products: section 5.2's implicit updates A X = (A S) C_x and
     A P = (A S) C_p after the basis update instead of recomputing the products
     (B = I only: the paper restricts them to that case).
@@ -484,6 +489,7 @@ def lobpcg(
     converged = False
     while it < maxit:
         it += 1
+        t_it = time.perf_counter()
         # W (with reading R2): W0 = K^-1 R on the unconverged columns.
         W0 = Kinv(R[:, n_c:])
         V, MV = np.hstack([X, P]), np.hstack([BX, BP])
@@ -529,7 +535,10 @@ def lobpcg(
         ok = rho <= tol
         n_c = int(np.argmin(ok)) if not np.all(ok) else n_x
         history.append(IterRecord(it, n_c, use_ortho, W.shape[1], P.shape[1], rr.cond_R,
-                                  float(np.max(rho[n_c:])) if n_c < n_x else 0.0))
+                                  float(np.max(rho[n_c:])) if n_c < n_x else 0.0,
+                                  time.perf_counter() - t_it))
+        if callback is not None:
+            callback(history[-1])
         if n_c >= k:
             converged = True
             break

@@ -1,12 +1,14 @@
 """Pins of the oracle's counter-based Gaussian generator and the section 4.3 sketch.
 
 Section 4.3 only needs Omega to be Gaussian; the oracle's generator is pinned by
-that distribution (and by properties of the Philox construction), not against
-itself.  The sketch estimate is pinned by its expectation: for Gaussian columns
+the published known-answer vectors of Philox-4x32-10, by that distribution and by
+properties of the construction, not against itself.  The sketch estimate is pinned by its expectation: for Gaussian columns
 omega, E ||A omega||^2 = ||A||_F^2 and E ||omega||^2 = n, so ||A Omega^T||_F /
 ||Omega^T||_F concentrates at ||A||_F / sqrt(n), the root mean square eigenvalue,
 which the closed-form spectrum gives.
 """
+
+import os
 
 import numpy as np
 import scipy.stats as st
@@ -15,6 +17,18 @@ from oracle import closed_forms as cf
 from oracle import lobpcg as L
 from oracle import philox as PH
 from paper_1704_07458_amd import problems as P
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+
+
+def test_philox_matches_the_published_known_answer_vectors():
+    rows = [ln.split() for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        w = [int(x, 16) for x in r]
+        out = PH.philox4x32_10(*w[:4], *w[4:6])
+        assert [int(x) for x in out] == w[6:], r
 
 
 def test_gaussian_block_is_standard_normal():
