@@ -98,3 +98,27 @@ def norm2_laplacian_2d(N: int) -> float:
 
 def norm2_laplacian_3d(N: int) -> float:
     return float(3.0 * dirichlet_1d(N)[-1])
+
+
+def _ring_eigenvalues(N: int, d: float, off: float, phase: float) -> np.ndarray:
+    """The periodic ring with diagonal d and off * e^{+-i phase} on the cyclic
+    neighbours is diagonalised by the Fourier modes e^{i theta_j l},
+    theta_j = 2 pi j / N: eigenvalue d + 2 off cos(theta_j - phase), j = 0..N-1."""
+    theta = 2.0 * np.pi * np.arange(N) / N
+    return d + 2.0 * off * np.cos(theta - phase)
+
+
+def twisted_laplacian_3d(N: int, phases=(0.3, 0.7, 1.1)) -> np.ndarray:
+    """Spectrum of the complex Hermitian twisted periodic 7-point Laplacian
+    (bond phases phases[d] * 2 pi / N): sums of the three axes' ring values."""
+    e = [_ring_eigenvalues(N, 2.0, -1.0, f * 2.0 * np.pi / N) for f in phases]
+    return np.sort((e[2][:, None, None] + e[1][None, :, None] + e[0][None, None, :]).ravel())
+
+
+def twisted_pencil_3d(N: int, phases=(0.3, 0.7, 1.1), phase_b: float = 0.5) -> np.ndarray:
+    """Spectrum of the complex tensor-product pencil A = a_x (x) b (x) b + ...,
+    B = b (x) b (x) b: every factor is diagonalised by the same Fourier modes,
+    so lambda = a_x/b_x + a_y/b_y + a_z/b_z over all mode triples."""
+    b = _ring_eigenvalues(N, 4.0 / 6.0, 1.0 / 6.0, phase_b * 2.0 * np.pi / N)
+    r = [_ring_eigenvalues(N, 2.0, -1.0, f * 2.0 * np.pi / N) / b for f in phases]
+    return np.sort((r[2][:, None, None] + r[1][None, :, None] + r[0][None, None, :]).ravel())

@@ -45,6 +45,13 @@ from . import philox
 EPS64 = np.finfo(np.float64).eps
 
 
+def _H(M: np.ndarray) -> np.ndarray:
+    """Conjugate transpose (the transpose for real data): the paper states the
+    method for real pencils and notes that it carries over to complex Hermitian
+    ones with every transpose read as a conjugate transpose (section 1)."""
+    return M.conj().T
+
+
 # --------------------------------------------------------------------------
 # Operators
 # --------------------------------------------------------------------------
@@ -62,6 +69,14 @@ class Operator:
         if self.M is None:
             return U.copy()
         return np.asarray(self.M @ U)
+
+
+def _is_complex(mat) -> bool:
+    if mat is None:
+        return False
+    if hasattr(mat, "values_im"):
+        return mat.values_im is not None
+    return np.iscomplexobj(mat.data if sp.issparse(mat) else mat)
 
 
 def _csr(mat):
@@ -128,17 +143,17 @@ def criterion8(R, X, BX, theta):
 # Algorithm 2: Rayleigh-Ritz with diagonal scaling
 # --------------------------------------------------------------------------
 def rayleigh_ritz(GA: np.ndarray, GB: np.ndarray):
-    """C, theta with C^T GB C = I and C^T GA C = diag(theta), theta ascending.
+    """C, theta with C^H GB C = I and C^H GA C = diag(theta), theta ascending.
 
-    D = diag(GB)^-1/2; R^T R = D GB D; eigh(R^-T D GA D R^-1) = Z Theta;
+    D = diag(GB)^-1/2; R^H R = D GB D; eigh(R^-H D GA D R^-1) = Z Theta;
     C = D R^-1 Z.  Raises numpy.linalg.LinAlgError if Cholesky fails.
     """
-    d = 1.0 / np.sqrt(np.diag(GB))
+    d = 1.0 / np.sqrt(np.diag(GB).real)
     D = np.diag(d)
-    R = np.linalg.cholesky(D @ GB @ D).T  # upper triangular, R^T R = D GB D
+    R = _H(np.linalg.cholesky(D @ GB @ D))  # upper triangular, R^H R = D GB D
     Rinv = sla.solve_triangular(R, np.eye(R.shape[0]), lower=False)
-    H = Rinv.T @ (D @ GA @ D) @ Rinv
-    H = 0.5 * (H + H.T)
+    H = _H(Rinv) @ (D @ GA @ D) @ Rinv
+    H = 0.5 * (H + _H(H))
     theta, Z = np.linalg.eigh(H)
     C = D @ Rinv @ Z
     return C, theta
@@ -149,7 +164,7 @@ def rayleigh_ritz(GA: np.ndarray, GB: np.ndarray):
 # --------------------------------------------------------------------------
 def _drop_zero_columns(U: np.ndarray, MU: np.ndarray):
     """Reading R8: remove columns with exactly zero M-norm before scaling."""
-    g = np.einsum("ij,ij->j", U, MU)
+    g = np.einsum("ij,ij->j", U.conj(), MU).real
     keep = g > 0.0
     return U[:, keep], MU[:, keep]
 
@@ -163,9 +178,9 @@ def svqb(Mop: Operator, U: np.ndarray, tau_replace: float) -> np.ndarray:
     U, MU = _drop_zero_columns(U, Mop(U))
     if U.shape[1] == 0:
         return U
-    G = U.T @ MU
-    G = 0.5 * (G + G.T)
-    d = 1.0 / np.sqrt(np.diag(G))
+    G = _H(U) @ MU
+    G = 0.5 * (G + _H(G))
+    d = 1.0 / np.sqrt(np.diag(G).real)
     theta, Z = np.linalg.eigh(d[:, None] * G * d[None, :])
     floor = tau_replace * np.max(np.abs(theta))
     theta = np.where(theta < floor, floor, theta)
@@ -177,9 +192,9 @@ def svqb_drop(Mop: Operator, U: np.ndarray, tau_drop: float) -> np.ndarray:
     U, MU = _drop_zero_columns(U, Mop(U))
     if U.shape[1] == 0:
         return U
-    G = U.T @ MU
-    G = 0.5 * (G + G.T)
-    d = 1.0 / np.sqrt(np.diag(G))
+    G = _H(U) @ MU
+    G = 0.5 * (G + _H(G))
+    d = 1.0 / np.sqrt(np.diag(G).real)
     theta, Z = np.linalg.eigh(d[:, None] * G * d[None, :])
     J = theta > tau_drop * np.max(np.abs(theta))
     return U @ (d[:, None] * Z[:, J] * (theta[J] ** -0.5)[None, :])
@@ -189,7 +204,7 @@ def _rel_orth_error(U, MU):
     """||U^T M U - I||_F / (||MU||_F ||U||_F)  (Algorithm 5, inner test)."""
     if U.shape[1] == 0:
         return 0.0
-    G = U.T @ MU
+    G = _H(U) @ MU
     return np.linalg.norm(G - np.eye(U.shape[1])) / (np.linalg.norm(MU) * np.linalg.norm(U))
 
 
@@ -197,7 +212,7 @@ def _rel_ext_error(V, MV, U):
     """||V^T M U||_F / (||MV||_F ||U||_F)  (Algorithm 5, outer test); MU = M U."""
     if U.shape[1] == 0 or V.shape[1] == 0:
         return 0.0
-    return np.linalg.norm(MV.T @ U) / (np.linalg.norm(MV) * np.linalg.norm(U))
+    return np.linalg.norm(_H(MV) @ U) / (np.linalg.norm(MV) * np.linalg.norm(U))
 
 
 @dataclasses.dataclass
@@ -225,7 +240,7 @@ def ortho_drop(
     for _i in range(3):
         stats.outer += 1
         if V.shape[1] > 0:
-            U = U - V @ (MV.T @ U)
+            U = U - V @ (_H(MV) @ U)
         for j in range(3):
             n_u = U.shape[1]
             if j == 0:
@@ -253,7 +268,7 @@ def ortho(Mop: Operator, U: np.ndarray, V: np.ndarray, MV: np.ndarray, tol: Tole
     for _i in range(itmax1):
         stats.outer += 1
         if V.shape[1] > 0:
-            U = U - V @ (MV.T @ U)
+            U = U - V @ (_H(MV) @ U)
         for _j in range(itmax2):
             U = svqb(Mop, U, tol.tau_replace(U.shape[1]))
             stats.svqb_calls += 1
@@ -286,7 +301,7 @@ def _lq_rows(M: np.ndarray) -> np.ndarray:
     orthonormal to working precision even if M is rank deficient.  Returns Q^T
     (columns orthonormal), of width min(M.shape).
     """
-    q, _r = np.linalg.qr(M.T, mode="reduced")
+    q, _r = np.linalg.qr(_H(M), mode="reduced")
     return q
 
 
@@ -314,10 +329,10 @@ def rayleigh_ritz_modified(
     n_s = GA.shape[0]
     cond_R = 1.0
     if use_ortho:
-        theta, Z = np.linalg.eigh(0.5 * (GA + GA.T))
+        theta, Z = np.linalg.eigh(0.5 * (GA + _H(GA)))
         T = np.eye(n_s)
     else:
-        g = np.diag(GB)
+        g = np.diag(GB).real
         if not np.all(g > 0.0):
             # a column of S with zero B-norm (an exactly converged residual):
             # S^T B S is singular and has no Cholesky factor (reading R8)
@@ -325,15 +340,15 @@ def rayleigh_ritz_modified(
         d = 1.0 / np.sqrt(g)
         D = np.diag(d)
         try:
-            R = np.linalg.cholesky(D @ GB @ D).T
+            R = _H(np.linalg.cholesky(D @ GB @ D))
         except np.linalg.LinAlgError:
             return RRResult(None, None, None, None, None, True, True, np.inf)
         Rinv = sla.solve_triangular(R, np.eye(n_s), lower=False)
         cond_R = np.linalg.norm(R, 1) * np.linalg.norm(Rinv, 1)
         if cond_R ** 3 * tol.tau_skip > 1.0:
             return RRResult(None, None, None, None, None, True, True, cond_R)
-        H = Rinv.T @ (D @ GA @ D) @ Rinv
-        theta, Z = np.linalg.eigh(0.5 * (H + H.T))
+        H = _H(Rinv) @ (D @ GA @ D) @ Rinv
+        theta, Z = np.linalg.eigh(0.5 * (H + _H(H)))
         T = D @ Rinv
     Z1 = Z[:n_x, :n_x]
     Z1p = Z[:n_x, n_x:]
@@ -342,12 +357,12 @@ def rayleigh_ritz_modified(
         if literal_lq:
             q = _lq_rows(Z1p)[:, : n_x - n_c]
         else:
-            q = _lq_rows(Z1[:, n_c:].T @ Z1p)
+            q = _lq_rows(_H(Z1[:, n_c:]) @ Z1p)
     else:
         q = np.zeros((0, 0))
     Cx = T @ Z[:, :n_x]
     Cp = T @ Zp @ q if q.size else np.zeros((n_s, 0))
-    theta_p = q.T @ np.diag(theta[n_x:]) @ q if q.size else np.zeros((0, 0))
+    theta_p = _H(q) @ np.diag(theta[n_x:]) @ q if q.size else np.zeros((0, 0))
     return RRResult(Cx, Cp, theta[:n_x].copy(), theta_p, theta, use_ortho, False, cond_R)
 
 
@@ -362,7 +377,7 @@ def jacobi_diagonal(A) -> np.ndarray:
     bound = max_i sum_j |a_ij|, which makes the diagonal positive.
     """
     A = _csr(A)
-    d = A.diagonal().astype(np.float64)
+    d = A.diagonal().real.astype(np.float64)
     if np.all(d > 0):
         return d
     absrow = np.asarray(abs(A).sum(axis=1)).ravel()
@@ -457,7 +472,9 @@ def lobpcg(
         A = -_csr(A)
     Aop, Bop = Operator(_csr(A)), Operator(_csr(B))
     Kinv = precond if precond is not None else (lambda R: R.copy())
-    X0 = np.asarray(X0, dtype=np.float64)
+    X0 = np.asarray(X0)
+    cplx = np.iscomplexobj(X0) or _is_complex(A) or _is_complex(B)
+    X0 = X0.astype(np.complex128 if cplx else np.float64)
     n, n_x = X0.shape
     if not (1 <= k <= n_x) or 3 * n_x > n:
         raise ValueError("need 1 <= k <= n_x and 3 n_x <= n")
@@ -466,20 +483,28 @@ def lobpcg(
     if exact_norms is not None:
         normA, normB = exact_norms
     else:
-        Om = philox.sketch(sketch_seed, n, n_x) if Omega_T is None else Omega_T
+        if Omega_T is not None:
+            Om = Omega_T
+        elif cplx:
+            # reading R17: the complex Gaussian n x 2 n_x block whose real and
+            # imaginary parts are the two halves of the real 2n x 2n_x sketch
+            Om2 = philox.sketch(sketch_seed, 2 * n, 2 * n_x)
+            Om = Om2[:n] + 1j * Om2[n:]
+        else:
+            Om = philox.sketch(sketch_seed, n, n_x)
         normA = sketch_norm(Aop, Om)
         normB = 1.0 if Bop.is_identity else sketch_norm(Bop, Om)
 
     # Start: initial Rayleigh-Ritz on X0.
     AX0, BX0 = Aop(X0), Bop(X0)
-    C, theta = rayleigh_ritz(X0.T @ AX0, X0.T @ BX0)
+    C, theta = rayleigh_ritz(_H(X0) @ AX0, _H(X0) @ BX0)
     X = X0 @ C
     AX, BX = Aop(X), Bop(X)
     theta_x = theta
     R = AX - BX * theta_x[None, :]
     n_c, use_ortho = 0, bool(force_ortho)
-    P = np.zeros((n, 0))
-    AP, BP = np.zeros((n, 0)), np.zeros((n, 0))
+    P = np.zeros((n, 0), dtype=X0.dtype)
+    AP, BP = np.zeros((n, 0), dtype=X0.dtype), np.zeros((n, 0), dtype=X0.dtype)
     history: List[IterRecord] = []
     switch_iter = -1
     ostats = OrthoStats()
@@ -502,8 +527,8 @@ def lobpcg(
         S = np.hstack([X, P, W])
         AS = np.hstack([AX, AP, AW])
         BS = np.hstack([BX, BP, BW])
-        GA, GB = S.T @ AS, S.T @ BS
-        GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+        GA, GB = _H(S) @ AS, _H(S) @ BS
+        GA, GB = 0.5 * (GA + _H(GA)), 0.5 * (GB + _H(GB))
         # RayleighRitzModified (Algorithm 7).
         rr = rayleigh_ritz_modified(GA, GB, n_x, n_c, use_ortho, tols, literal_lq)
         if rr.flipped:
@@ -515,8 +540,8 @@ def lobpcg(
             S = np.hstack([X, P, W])
             AS = np.hstack([AX, AP, AW])
             BS = np.hstack([BX, BP, BW])
-            GA, GB = S.T @ AS, S.T @ BS
-            GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+            GA, GB = _H(S) @ AS, _H(S) @ BS
+            GA, GB = 0.5 * (GA + _H(GA)), 0.5 * (GB + _H(GB))
             rr = rayleigh_ritz_modified(GA, GB, n_x, n_c, use_ortho, tols, literal_lq)
         # Basis update [X, P] = S [C_x, C_p]; products recomputed explicitly, or
         # updated implicitly from A S (section 5.2).

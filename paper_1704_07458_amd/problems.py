@@ -114,6 +114,87 @@ def fem_q1_pencil(N: int):
     return from_scipy(K), from_scipy(M)
 
 
+@dataclasses.dataclass
+class ZCSR:
+    """A square complex sparse matrix in CSR form with sorted, unique column
+    indices; the real and imaginary parts of the values are separate float64
+    arrays (the library's complex Hermitian input layout)."""
+
+    n: int
+    rowptr: np.ndarray  # int64, n + 1
+    colind: np.ndarray  # int32, nnz
+    values_re: np.ndarray  # float64, nnz
+    values_im: np.ndarray  # float64, nnz
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix(
+            (self.values_re + 1j * self.values_im, self.colind.astype(np.int64), self.rowptr),
+            shape=(self.n, self.n),
+        )
+
+
+def zfrom_scipy(M) -> ZCSR:
+    M = sp.csr_matrix(M, dtype=np.complex128)
+    M.sum_duplicates()
+    M.sort_indices()
+    return ZCSR(
+        n=M.shape[0],
+        rowptr=np.ascontiguousarray(M.indptr, dtype=np.int64),
+        colind=np.ascontiguousarray(M.indices, dtype=np.int32),
+        values_re=np.ascontiguousarray(M.data.real, dtype=np.float64),
+        values_im=np.ascontiguousarray(M.data.imag, dtype=np.float64),
+    )
+
+
+def _ring(N: int, d: float, off: float, phase: float):
+    """Periodic 1D ring: d on the diagonal, off * e^{i phase} at (l, l-1) and
+    off * e^{-i phase} at (l, l+1), cyclically (Hermitian)."""
+    rows, cols, vals = [], [], []
+    for l in range(N):
+        rows += [l, l, l]
+        cols += [(l - 1) % N, l, (l + 1) % N]
+        vals += [off * np.exp(1j * phase), d, off * np.exp(-1j * phase)]
+    M = sp.coo_matrix((np.array(vals), (rows, cols)), shape=(N, N)).tocsr()
+    M.sum_duplicates()
+    return M
+
+
+def twisted_laplacian_3d(N: int, phases=(0.3, 0.7, 1.1)) -> ZCSR:
+    """Complex Hermitian 7-point Laplacian on a periodic N^3 grid whose bonds
+    along axis d carry the phase e^{i phases[d] 2 pi / N} (a uniform magnetic
+    twist): diagonal 6, neighbours -e^{+-i phi_d}.  N >= 3."""
+    I = sp.identity(N, format="csr")
+    T = [_ring(N, 2.0, -1.0, f * 2.0 * np.pi / N) for f in phases]
+    A = sp.kron(sp.kron(I, I), T[0]) + sp.kron(sp.kron(I, T[1]), I) + sp.kron(sp.kron(T[2], I), I)
+    return zfrom_scipy(A)
+
+
+def twisted_pencil_3d(N: int, phases=(0.3, 0.7, 1.1), phase_b: float = 0.5):
+    """Complex Hermitian-definite pencil (A, B) on a periodic N^3 grid, built
+    like the Q1 pencil from 1D rings: a_d = ring(2, -1, phi_d), b = ring(4, 1,
+    psi) / 6 (positive definite), A = a_x (x) b (x) b + b (x) a_y (x) b + b (x) b (x) a_z
+    in the x-fastest ordering, B = b (x) b (x) b; 27-point.  N >= 3."""
+    a = [_ring(N, 2.0, -1.0, f * 2.0 * np.pi / N) for f in phases]
+    b = _ring(N, 4.0 / 6.0, 1.0 / 6.0, phase_b * 2.0 * np.pi / N)
+    kron3 = lambda z, y, x: sp.kron(sp.kron(z, y), x, format="csr")
+    A = kron3(b, b, a[0]) + kron3(b, a[1], b) + kron3(a[2], b, b)
+    B = kron3(b, b, b)
+    return zfrom_scipy(A), zfrom_scipy(B)
+
+
+def complex_initial_block(seed: int, n: int, ncols: int) -> np.ndarray:
+    """Complex Gaussian initial block: real and imaginary parts N(0, 1) from
+    default_rng(seed), real part drawn first; n x ncols, row-major."""
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal((n, ncols))
+    im = rng.standard_normal((n, ncols))
+    return np.ascontiguousarray(re + 1j * im)
+
+
 def tridiag_1d(N: int, lo: float, d: float, hi: float) -> CSR:
     return from_scipy(_tridiag(N, lo, d, hi))
 
