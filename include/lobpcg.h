@@ -233,6 +233,60 @@ int lobpcg_adjoint(lobpcg_t h, int32_t count, const double* lambda_bar, const do
                    int64_t ld_xbar, double* grad, double* grad_B, double cg_tol,
                    int32_t cg_maxit, int32_t* cg_iters);
 
+/* Complex Hermitian pencils (section 1: the method carries over to A = A^H,
+ * B = B^H positive definite, with every transpose read as a conjugate
+ * transpose).  CSR as lobpcg_csr, with the real and imaginary parts of the
+ * stored values in two arrays of nnz doubles.  Symmetry (a_cr = conj(a_rc)) is
+ * the caller's responsibility. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const double* values_re;
+  const double* values_im;
+  int32_t on_device;
+} lobpcg_zcsr;
+
+/* Create a solver for the k smallest (opt.largest: largest) eigenpairs of the
+ * complex Hermitian pencil (A, B), B = NULL for B = I.  The handle runs
+ * Algorithm 8 on the real embedding Ahat = [Re A, -Im A; Im A, Re A] (order 2n,
+ * 4 nnz(A) stored values; likewise Bhat) for 2k pairs with block width 2 n_x:
+ * a complex eigenvalue is a double eigenvalue of the embedding, and the
+ * stacked vectors of x and i x span its eigenspace.  The Jacobi preconditioner
+ * is the embedding's (diag(Re A) twice); a preconditioner callback receives the
+ * embedding's 2n-row real blocks.  lobpcg_kernel_stats, lobpcg_set_profiling
+ * and lobpcg_dims (which reports n, k and n_x of the complex problem) accept
+ * the handle; lobpcg_solve, lobpcg_eigpairs and lobpcg_adjoint reject it
+ * (LOBPCG_ERR_ARG).  Requires 3 n_x <= n.  Errors as lobpcg_create. */
+int lobpcg_create_hermitian(lobpcg_t* out, const lobpcg_zcsr* A, const lobpcg_zcsr* B, int32_t k,
+                            const lobpcg_options* opt);
+
+/* Run Algorithm 8 on the embedding from the paired block [X0, i X0].
+ * X0_re, X0_im: row-major n x n_x real and imaginary parts of the complex
+ * initial block (host memory when x0_on_device = 0, device when 1), both NULL
+ * for the library's block: real parts from the first n rows and imaginary
+ * parts from the last n rows of the seeded 2n x n_x Gaussian block (Philox
+ * stream 0 of opt.seed).  The section 4.3 sketch is the embedding's (stream 1,
+ * 2n x 2n_x), i.e. the complex Gaussian block with those halves.  info
+ * reports the embedding's iteration (its n_converged counts real pairs).
+ * Returns as lobpcg_solve. */
+int lobpcg_solve_hermitian(lobpcg_t h, double tol, const double* X0_re, const double* X0_im,
+                           int32_t x0_on_device, lobpcg_precond_fn K, void* K_user,
+                           lobpcg_info* info);
+
+/* The leading `count` (<= k) complex eigenpairs of the last solve: lambda
+ * (ascending; descending with opt.largest), X_re / X_im (row-major n x count,
+ * leading dimension ldx >= count, B-orthonormal columns: X^H B X = I) and
+ * rel_resid (criterion (9) of each complex pair with the sketch norms).  The
+ * pairs come from the 2k leading real Ritz vectors z_j = x(1:n) + i x(n+1:2n):
+ * Q = the B-orthonormal basis of the k-dimensional range of Z^H B Z, then the
+ * eigenpairs of Q^H A Q (complex Rayleigh-Ritz).  k must not split a cluster
+ * of equal complex eigenvalues.  on_device = 0: host buffers; 1: device.
+ * Errors: LOBPCG_ERR_STATE before a solve, LOBPCG_ERR_ARG. */
+int lobpcg_eigpairs_hermitian(lobpcg_t h, int32_t count, double* lambda, double* X_re,
+                              double* X_im, int64_t ldx, double* rel_resid, int32_t on_device);
+
 /* Problem dimensions of a handle (any pointer may be NULL). */
 int lobpcg_dims(lobpcg_t h, int64_t* n, int32_t* k, int32_t* n_x);
 

@@ -54,6 +54,18 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32)
 
 
+class lobpcg_zcsr(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("nnz", C.c_int64),
+        ("rowptr", C.c_void_p),
+        ("colind", C.c_void_p),
+        ("values_re", C.c_void_p),
+        ("values_im", C.c_void_p),
+        ("on_device", C.c_int32),
+    ]
+
+
 class lobpcg_options(C.Structure):
     _fields_ = [
         ("block_size", C.c_int32),
@@ -131,6 +143,14 @@ SIGNATURES = {
     "lobpcg_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                  C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                  C.POINTER(C.c_int32)]),
+    "lobpcg_create_hermitian": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(lobpcg_zcsr),
+                                          C.POINTER(lobpcg_zcsr), C.c_int32,
+                                          C.POINTER(lobpcg_options)]),
+    "lobpcg_solve_hermitian": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                         C.c_int32, PRECOND_FN, C.c_void_p,
+                                         C.POINTER(lobpcg_info)]),
+    "lobpcg_eigpairs_hermitian": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]),
     "lobpcg_dims": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32)]),
     "lobpcg_destroy": (None, [C.c_void_p]),
@@ -246,6 +266,29 @@ def _csr_struct(M, keep: list):
     return s
 
 
+def _zcsr_struct(M, keep: list):
+    """lobpcg_zcsr for a problems.ZCSR (host numpy) or a dict of device tensors
+    (rowptr, colind, values_re, values_im)."""
+    s = lobpcg_zcsr()
+    if isinstance(M, dict):
+        rp, ci, vr, vi = M["rowptr"], M["colind"], M["values_re"], M["values_im"]
+        s.n, s.nnz = int(rp.numel() - 1), int(ci.numel())
+        s.rowptr, s.colind = _ptr(rp), _ptr(ci)
+        s.values_re, s.values_im = _ptr(vr), _ptr(vi)
+        s.on_device = 1
+        keep.extend([rp, ci, vr, vi])
+    else:
+        arrs = [np.ascontiguousarray(M.rowptr, dtype=np.int64),
+                np.ascontiguousarray(M.colind, dtype=np.int32),
+                np.ascontiguousarray(M.values_re, dtype=np.float64),
+                np.ascontiguousarray(M.values_im, dtype=np.float64)]
+        keep.extend(arrs)
+        s.n, s.nnz = int(M.n), int(arrs[1].size)
+        s.rowptr, s.colind, s.values_re, s.values_im = [a.ctypes.data for a in arrs]
+        s.on_device = 0
+    return s
+
+
 class TorchAllocator:
     """dev_alloc / dev_free hooks that take the handle's device memory from torch's
     caching allocator on the given stream (lobpcg_options.dev_alloc)."""
@@ -291,6 +334,28 @@ class Solver:
                  block_size: int = 0, maxit: int = 2000, allocator: str = "torch",
                  progress=None, **opts):
         lib = load()
+        o = self._options(precond, precision, block_size, maxit, allocator, progress, opts)
+        keep: list = []
+        a = _csr_struct(A, keep)
+        b = _csr_struct(B, keep) if B is not None else None
+        h = C.c_void_p()
+        check(lib.lobpcg_create(C.byref(h), C.byref(a), C.byref(b) if b is not None else None,
+                                int(k), C.byref(o)))
+        self._finish(h, k, a, b)
+
+    def _finish(self, h, k, a, b):
+        lib = load()
+        self._h = h
+        self.k = int(k)
+        n = C.c_int64()
+        kk = C.c_int32()
+        nx = C.c_int32()
+        check(lib.lobpcg_dims(h, C.byref(n), C.byref(kk), C.byref(nx)))
+        self.n, self.n_x = int(n.value), int(nx.value)
+        self.nnz_A = int(a.nnz)
+        self.nnz_B = int(b.nnz) if b is not None else None
+
+    def _options(self, precond, precision, block_size, maxit, allocator, progress, opts):
         o = default_options()
         # progress(iteration, n_converged, phase) after every iteration (phase 1 = FP32)
         self._progress = None
@@ -316,21 +381,7 @@ class Solver:
             o.dev_free = self._alloc.free_fn
         elif allocator != "hip":
             raise ValueError("allocator must be 'torch' or 'hip'")
-        keep: list = []
-        a = _csr_struct(A, keep)
-        b = _csr_struct(B, keep) if B is not None else None
-        h = C.c_void_p()
-        check(lib.lobpcg_create(C.byref(h), C.byref(a), C.byref(b) if b is not None else None,
-                                int(k), C.byref(o)))
-        self._h = h
-        self.k = int(k)
-        n = C.c_int64()
-        kk = C.c_int32()
-        nx = C.c_int32()
-        check(lib.lobpcg_dims(h, C.byref(n), C.byref(kk), C.byref(nx)))
-        self.n, self.n_x = int(n.value), int(nx.value)
-        self.nnz_A = int(a.nnz)
-        self.nnz_B = int(b.nnz) if b is not None else None
+        return o
 
     def close(self):
         if getattr(self, "_h", None):
@@ -431,6 +482,71 @@ class Solver:
 
 
 # ---------------------------------------------------------------- step calls
+class HermitianSolver(Solver):
+    """Handle around lobpcg_create_hermitian / solve_hermitian / eigpairs_hermitian:
+    the k smallest (or largest) eigenpairs of a complex Hermitian pencil, run by
+    the library on the real embedding [Re A, -Im A; Im A, Re A]."""
+
+    def __init__(self, A, k: int, B=None, precond: str = "none", precision: str = "fp64",
+                 block_size: int = 0, maxit: int = 2000, allocator: str = "torch",
+                 progress=None, **opts):
+        lib = load()
+        o = self._options(precond, precision, block_size, maxit, allocator, progress, opts)
+        keep: list = []
+        a = _zcsr_struct(A, keep)
+        b = _zcsr_struct(B, keep) if B is not None else None
+        h = C.c_void_p()
+        check(lib.lobpcg_create_hermitian(C.byref(h), C.byref(a),
+                                          C.byref(b) if b is not None else None, int(k),
+                                          C.byref(o)))
+        self._finish(h, k, a, b)
+
+    def solve(self, tol: float, X0=None) -> dict:
+        """X0: None, a complex host numpy array or a complex device tensor (n x n_x)."""
+        import torch
+
+        lib = load()
+        info = lobpcg_info()
+        keep = []
+        if X0 is None:
+            pre = pim = None
+            dev = 0
+        elif isinstance(X0, np.ndarray):
+            assert X0.shape == (self.n, self.n_x)
+            keep = [np.ascontiguousarray(X0.real, dtype=np.float64),
+                    np.ascontiguousarray(X0.imag, dtype=np.float64)]
+            pre, pim, dev = keep[0].ctypes.data, keep[1].ctypes.data, 0
+        else:
+            assert tuple(X0.shape) == (self.n, self.n_x)
+            keep = [X0.real.to(torch.float64).contiguous(),
+                    X0.imag.to(torch.float64).contiguous()]
+            pre, pim, dev = _ptr(keep[0]), _ptr(keep[1]), 1
+        cb = PRECOND_FN(self._precond_trampoline) if self._callback else PRECOND_FN()
+        self._cb_ref = cb
+        code = check(lib.lobpcg_solve_hermitian(self._h, float(tol), pre, pim, dev, cb, None,
+                                                C.byref(info)))
+        d = info.as_dict()
+        d["status"] = STATUS_NAMES[code]
+        d["converged"] = code == LOBPCG_OK
+        return d
+
+    def eigpairs(self, count: Optional[int] = None):
+        """(lambda, X, rho) as device tensors: count values, complex n x count, count values."""
+        import torch
+
+        count = self.k if count is None else int(count)
+        lam = torch.empty(count, dtype=torch.float64, device="cuda")
+        Xr = torch.empty((self.n, count), dtype=torch.float64, device="cuda")
+        Xi = torch.empty((self.n, count), dtype=torch.float64, device="cuda")
+        rho = torch.empty(count, dtype=torch.float64, device="cuda")
+        check(load().lobpcg_eigpairs_hermitian(self._h, count, _ptr(lam), _ptr(Xr), _ptr(Xi),
+                                               count, _ptr(rho), 1))
+        return lam, torch.complex(Xr, Xi), rho
+
+    def adjoint(self, *args, **kwargs):
+        raise NotImplementedError("the adjoint is for real pencils")
+
+
 def _dtype_code(t) -> int:
     import torch
 

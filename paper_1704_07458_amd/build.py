@@ -20,7 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblobpcg_mi355x.so")
-SOURCES = ["kernels.hip", "cholinv.hip", "small_gemm.hip", "tridiag_dc.hip", "dense.hip", "solver.hip", "adjoint.hip", "capi.cpp"]
+SOURCES = ["kernels.hip", "cholinv.hip", "small_gemm.hip", "tridiag_dc.hip", "dense.hip", "solver.hip",
+           "adjoint.hip", "hermitian.hip", "capi.cpp"]
 
 ARCH = os.environ.get("LOBPCG_OFFLOAD_ARCH", "gfx950")
 

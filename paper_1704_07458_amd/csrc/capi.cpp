@@ -15,10 +15,15 @@
 #include "kernels.hpp"
 #include "lobpcg.h"
 #include "lobpcg_steps.h"
+#include "hermitian.hpp"
 #include "solver.hpp"
 
+// A handle owns a real solver, or a complex Hermitian driver with its real
+// solver inside; `solver` points at the real solver either way.
 struct lobpcg_ctx {
-  std::unique_ptr<lobpcg::Solver> solver;
+  std::unique_ptr<lobpcg::Solver> own;
+  std::unique_ptr<lobpcg::Hermitian> herm;
+  lobpcg::Solver* solver = nullptr;
 };
 
 namespace {
@@ -81,9 +86,43 @@ int lobpcg_create(lobpcg_t* out, const lobpcg_csr* A, const lobpcg_csr* B, int32
     if (opt) o = *opt;
     else lobpcg_default_options(&o);
     std::unique_ptr<lobpcg_ctx> h(new lobpcg_ctx);
-    h->solver.reset(new lobpcg::Solver(A, B, k, o));
+    h->own.reset(new lobpcg::Solver(A, B, k, o));
+    h->solver = h->own.get();
     *out = h.release();
     return LOBPCG_OK;
+  });
+}
+
+int lobpcg_create_hermitian(lobpcg_t* out, const lobpcg_zcsr* A, const lobpcg_zcsr* B, int32_t k,
+                            const lobpcg_options* opt) {
+  return guarded([&]() {
+    LOBPCG_CHECK(out != nullptr, LOBPCG_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    lobpcg_options o;
+    if (opt) o = *opt;
+    else lobpcg_default_options(&o);
+    std::unique_ptr<lobpcg_ctx> h(new lobpcg_ctx);
+    h->herm.reset(new lobpcg::Hermitian(A, B, k, o));
+    h->solver = &h->herm->real();
+    *out = h.release();
+    return LOBPCG_OK;
+  });
+}
+
+int lobpcg_solve_hermitian(lobpcg_t h, double tol, const double* X0_re, const double* X0_im,
+                           int32_t x0_on_device, lobpcg_precond_fn K, void* K_user,
+                           lobpcg_info* info) {
+  return guarded([&]() {
+    LOBPCG_CHECK(h && h->herm, LOBPCG_ERR_ARG, "not a complex Hermitian handle");
+    return h->herm->solve(tol, X0_re, X0_im, x0_on_device != 0, K, K_user, info);
+  });
+}
+
+int lobpcg_eigpairs_hermitian(lobpcg_t h, int32_t count, double* lambda, double* X_re,
+                              double* X_im, int64_t ldx, double* rel_resid, int32_t on_device) {
+  return guarded([&]() {
+    LOBPCG_CHECK(h && h->herm, LOBPCG_ERR_ARG, "not a complex Hermitian handle");
+    return h->herm->eigpairs(count, lambda, X_re, X_im, ldx, rel_resid, on_device != 0);
   });
 }
 
@@ -91,6 +130,7 @@ int lobpcg_solve(lobpcg_t h, double tol, const double* X0, int32_t x0_on_device,
                  lobpcg_precond_fn K, void* K_user, lobpcg_info* info) {
   return guarded([&]() {
     LOBPCG_CHECK(h && h->solver, LOBPCG_ERR_ARG, "NULL handle");
+    LOBPCG_CHECK(!h->herm, LOBPCG_ERR_ARG, "complex Hermitian handle: use the _hermitian calls");
     return h->solver->solve(tol, X0, x0_on_device != 0, K, K_user, info);
   });
 }
@@ -99,6 +139,7 @@ int lobpcg_eigpairs(lobpcg_t h, int32_t count, double* lambda, double* X, int64_
                     double* rel_resid, int32_t on_device) {
   return guarded([&]() {
     LOBPCG_CHECK(h && h->solver, LOBPCG_ERR_ARG, "NULL handle");
+    LOBPCG_CHECK(!h->herm, LOBPCG_ERR_ARG, "complex Hermitian handle: use the _hermitian calls");
     return h->solver->eigpairs(count, lambda, X, ldx, rel_resid, on_device != 0);
   });
 }
@@ -108,6 +149,7 @@ int lobpcg_adjoint(lobpcg_t h, int32_t count, const double* lambda_bar, const do
                    int32_t cg_maxit, int32_t* cg_iters) {
   return guarded([&]() {
     LOBPCG_CHECK(h && h->solver, LOBPCG_ERR_ARG, "NULL handle");
+    LOBPCG_CHECK(!h->herm, LOBPCG_ERR_ARG, "complex Hermitian handle: use the _hermitian calls");
     return h->solver->adjoint(count, lambda_bar, X_bar, ld_xbar, grad, grad_B, cg_tol, cg_maxit,
                               cg_iters);
   });
@@ -116,6 +158,12 @@ int lobpcg_adjoint(lobpcg_t h, int32_t count, const double* lambda_bar, const do
 int lobpcg_dims(lobpcg_t h, int64_t* n, int32_t* k, int32_t* n_x) {
   return guarded([&]() {
     LOBPCG_CHECK(h && h->solver, LOBPCG_ERR_ARG, "NULL handle");
+    if (h->herm) {
+      if (n) *n = h->herm->n();
+      if (k) *k = h->herm->k();
+      if (n_x) *n_x = h->herm->nx();
+      return LOBPCG_OK;
+    }
     if (n) *n = h->solver->n();
     if (k) *k = h->solver->k();
     if (n_x) *n_x = h->solver->nx();

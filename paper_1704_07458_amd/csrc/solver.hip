@@ -316,6 +316,17 @@ void Solver::spmm(const DevCsr& M, const T* X, int64_t ldx, T* Y, int64_t ldy, i
   timer_.stop(tok, 0, (double)M.nnz * (sv + 4) + 8.0 * (M.n + 1) + 2.0 * M.n * ncols * sv, s_);
 }
 
+void Solver::apply(bool use_B, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                   int ncols) {
+  AllocatorScope scope(&alloc_);
+  if (use_B && !haveB_) {
+    LOBPCG_HIP(hipMemcpy2DAsync(Y, sizeof(double) * ldy, X, sizeof(double) * ldx,
+                                sizeof(double) * ncols, n_, hipMemcpyDeviceToDevice, s_));
+    return;
+  }
+  spmm<double>(use_B ? B_ : A_, X, ldx, Y, ldy, ncols);
+}
+
 template <typename T>
 void Solver::gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const T* R1,
                   int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,

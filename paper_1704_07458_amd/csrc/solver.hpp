@@ -46,6 +46,17 @@ class Solver {
   int64_t n() const { return n_; }
   int k() const { return k_; }
   int nx() const { return nx_; }
+  // For drivers built on this solver (the complex Hermitian embedding): the
+  // stream, the allocator, the sketch norms and the stored operators.
+  hipStream_t stream() const { return s_; }
+  const DevAllocator* allocator() const { return &alloc_; }
+  bool solved() const { return solved_; }
+  bool largest() const { return opt_.largest != 0; }
+  double norm_A_est() const { return normA_; }
+  double norm_B_est() const { return normB_; }
+  // Y = M X in FP64 on the solver's stream (M = A as stored, negated when
+  // largest, or B; B = I copies X); row-major blocks with ncols columns.
+  void apply(bool use_B, const double* X, int64_t ldx, double* Y, int64_t ldy, int ncols);
   void set_profiling(bool on) { profile_ = on; }
   KernelTimer& timer() { return timer_; }
 

@@ -142,7 +142,8 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = [B.lobpcg_csr, B.lobpcg_options, B.lobpcg_info, B.lobpcg_kernel_stat]
+    structs = [B.lobpcg_csr, B.lobpcg_zcsr, B.lobpcg_options, B.lobpcg_info,
+               B.lobpcg_kernel_stat]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lobpcg.h"', "int main(void) {"]
     for S in structs:
         n = S.__name__
@@ -162,3 +163,46 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(n, "sizeof")] == C.sizeof(S), n
         for f, _ in S._fields_:
             assert got[(n, f)] == getattr(S, f).offset, (n, f)
+
+
+def _create_hermitian(A, k, Bm=None, **opts):
+    lib = B.load()
+    o = B.default_options()
+    for key, val in opts.items():
+        setattr(o, key, val)
+    keep: list = []
+    a = B._zcsr_struct(A, keep)
+    b = B._zcsr_struct(Bm, keep) if Bm is not None else None
+    h = C.c_void_p()
+    code = lib.lobpcg_create_hermitian(C.byref(h), C.byref(a),
+                                       C.byref(b) if b is not None else None, k, C.byref(o))
+    if code == 0:
+        lib.lobpcg_destroy(h)
+    return code, lib.lobpcg_last_error().decode()
+
+
+def test_hermitian_create_rejects_bad_input_before_the_gpu():
+    A = P.twisted_laplacian_3d(4)  # n = 64
+    bad = P.ZCSR(A.n, A.rowptr.copy(), A.colind, A.values_re, A.values_im)
+    bad.rowptr[-1] += 1
+    code, msg = _create_hermitian(bad, 2)
+    assert code == -1 and "rowptr" in msg
+    uns = P.ZCSR(A.n, A.rowptr, A.colind.copy(), A.values_re, A.values_im)
+    s, e = A.rowptr[5], A.rowptr[6]
+    uns.colind[s:e] = uns.colind[s:e][::-1]
+    code, msg = _create_hermitian(uns, 2)
+    assert code == -1 and "sorted" in msg
+    code, _ = _create_hermitian(A, 0)
+    assert code == -1
+    code, msg = _create_hermitian(A, 20)  # n_x = 22, 3 n_x = 66 > 64
+    assert code == -1 and "3 * block_size" in msg
+    Bm, _ = P.twisted_pencil_3d(3)
+    code, msg = _create_hermitian(A, 2, Bm)
+    assert code == -1 and "order" in msg
+
+
+def test_hermitian_calls_reject_null_and_real_handles():
+    lib = B.load()
+    assert lib.lobpcg_solve_hermitian(None, 1e-8, None, None, 0, B.PRECOND_FN(), None,
+                                      None) == -1
+    assert lib.lobpcg_eigpairs_hermitian(None, 1, None, None, None, 1, None, 0) == -1
