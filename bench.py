@@ -317,6 +317,11 @@ def run_workloads(torch, B, P, which):
             s.kernel_stats(True)
             s.solve(w.tol, X0)
             st = s.kernel_stats(False)
+            # per-phase times (stream-synchronised, so a separate solve): the split
+            # solve switches to orthoDrop early, so this times Algorithm 5 in use
+            s.set_profiling(True)
+            pinfo = s.solve(w.tol, X0)
+            s.set_profiling(False)
             lam, X, _ = s.eigpairs(w.k)
             lam, X = lam.cpu().numpy(), X.cpu().numpy()
             lams[prec] = lam
@@ -331,6 +336,8 @@ def run_workloads(torch, B, P, which):
                     "ortho_switch_iter": info["ortho_switch_iter"],
                     "eig_rel_err_vs_closed_form": float(np.max(np.abs(lam - exact) / exact)),
                     "kernel_seconds": {k: v["seconds"] for k, v in st.items()},
+                    "phase_seconds_profiled_solve": pinfo["seconds_phase"],
+                    "ortho_calls": pinfo["ortho_calls"], "svqb_calls": pinfo["svqb_calls"],
                     **_pencil_checks(A, Bm, lam, X, info["norm_A_est"], info["norm_B_est"])}
             if prec == "split":
                 line["eig_rel_err_vs_fp64"] = float(np.max(np.abs(lam - lams["fp64"]) /

@@ -103,6 +103,13 @@ size_t Dense::library_workspace_bytes(rocblas_handle h) {
   return std::max<size_t>(bytes, 256);
 }
 
+void Dense::reserve_library_workspace(size_t bytes) {
+  if (bytes <= lib_ws_.size()) return;
+  LOBPCG_HIP(hipStreamSynchronize(s_));
+  lib_ws_.alloc(bytes);
+  LOBPCG_ROCBLAS(rocblas_set_workspace(h_, lib_ws_.get(), lib_ws_.size()));
+}
+
 Dense::~Dense() {
   if (s2_) (void)hipStreamSynchronize(s2_);
   for (hipEvent_t e : {ev_z_, ev_p_})

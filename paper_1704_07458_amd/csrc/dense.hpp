@@ -61,6 +61,9 @@ class Dense {
   int svqb_transform(double* G, int64_t ldg, int nu, double tau, bool drop, double* Tu);
 
   rocblas_handle handle() const { return h_; }
+  // Grow the main handle's library workspace to at least `bytes` (from the
+  // current allocator); callers size it with a device-memory size query.
+  void reserve_library_workspace(size_t bytes);
   hipStream_t stream() const { return s_; }
 
   // Device status word that the tridiagonal eigensolver sets to 1 when an

@@ -140,6 +140,130 @@ __global__ __launch_bounds__(256) void spmm_kernel(int64_t n,
   }
 }
 
+// A X fused with the residual and the convergence sums (B = I): the sparse
+// product of spmm_kernel over the n_x columns of X, and at the end of each row
+// r, for each column j: res = (A X)(r, j) - theta_j X(r, j), W(r, n_x-1-j) =
+// res * dinv[r] (res without dinv; the reversed W store of section 5.1),
+// optionally AX(r, j), and the FP64 sums of res^2 and X(r, j)^2 over the
+// workgroup's rows into part_r / part_x [block][n_x] (fixed order: each wave
+// its rows in order, then the four waves in order).  X(r, :) is the row the
+// diagonal entry gathered (loaded again for a row that stores no diagonal).
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void spmm_residual_kernel(
+    int64_t n, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const T* __restrict__ vals, const T* __restrict__ X, int64_t ldx, int nx,
+    const double* __restrict__ theta, const double* __restrict__ dinv, T* __restrict__ W,
+    int64_t ldw, T* __restrict__ AX, int64_t ldax, double* __restrict__ part_r,
+    double* __restrict__ part_x) {
+  __shared__ double sr[4][kWave * NC], sx[4][kWave * NC];
+  const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int wave = uniform(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int col0 = blockIdx.y * (kWave * NC) + lane;
+  const int64_t r0 = lb * kSpmmRowsPerBlock + (int64_t)wave * kSpmmRowsPerWave;
+  const int nr = r0 >= n ? 0 : (int)(n - r0 < kSpmmRowsPerWave ? n - r0 : kSpmmRowsPerWave);
+  bool cok[NC];
+  double th[NC], accr[NC], accx[NC];
+  T acc[NC], xd[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    cok[j] = col0 + kWave * j < nx;
+    th[j] = cok[j] ? theta[col0 + kWave * j] : 0.0;
+    accr[j] = 0.0;
+    accx[j] = 0.0;
+    acc[j] = T(0);
+    xd[j] = T(0);
+  }
+  bool diag = false;  // X(r, :) captured from the diagonal entry of the current row
+  // row r0 + cr is complete: residual, stores and sums
+  auto finish_row = [&](int cr) {
+    const int64_t r = r0 + cr;
+    const double dv = dinv ? dinv[r] : 1.0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (!cok[j]) continue;
+      const int c = col0 + kWave * j;
+      const double x = diag ? (double)xd[j] : (double)X[r * ldx + c];
+      const double res = (double)acc[j] - x * th[j];
+      accr[j] = fma(res, res, accr[j]);
+      accx[j] = fma(x, x, accx[j]);
+      W[r * ldw + (nx - 1 - c)] = (T)(res * dv);
+      if (AX) AX[r * ldax + c] = acc[j];
+    }
+  };
+  if (nr > 0) {
+    const int64_t rpl = lane <= nr ? rowptr[r0 + lane] : 0;
+    const int64_t pbeg = readlane64(rpl, 0), pend = readlane64(rpl, nr);
+    int cr = 0;
+    int64_t ce = readlane64(rpl, 1);
+    for (int64_t chunk = pbeg; chunk < pend; chunk += kWave) {
+      const int cnt = (int)(pend - chunk < kWave ? pend - chunk : kWave);
+      const int32_t cl = lane < cnt ? colind[chunk + lane] : 0;
+      const T al = lane < cnt ? vals[chunk + lane] : T(0);
+      for (int q = 0; q < cnt; q += kSpmmBatch) {
+        T xb[kSpmmBatch][NC];
+        T ab[kSpmmBatch];
+        int64_t cb[kSpmmBatch];
+#pragma unroll
+        for (int u = 0; u < kSpmmBatch; ++u) {
+          const bool ok = q + u < cnt;
+          const int li = ok ? q + u : 0;
+          const int64_t c = (int64_t)__builtin_amdgcn_readlane(cl, li);
+          cb[u] = c;
+          ab[u] = ok ? readlane_val(al, li) : T(0);
+#pragma unroll
+          for (int j = 0; j < NC; ++j)
+            xb[u][j] = (ok && cok[j]) ? X[c * ldx + col0 + kWave * j] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kSpmmBatch; ++u) {
+          if (q + u < cnt) {
+            const int64_t p = chunk + q + u;
+            while (cr + 1 < nr && p >= ce) {  // the current row is complete
+              finish_row(cr);
+#pragma unroll
+              for (int j = 0; j < NC; ++j) acc[j] = T(0);
+              diag = false;
+              ++cr;
+              ce = readlane64(rpl, cr + 1);
+            }
+            if (cb[u] == r0 + cr) {
+#pragma unroll
+              for (int j = 0; j < NC; ++j) xd[j] = xb[u][j];
+              diag = true;
+            }
+#pragma unroll
+            for (int j = 0; j < NC; ++j) acc[j] = fma(ab[u], xb[u][j], acc[j]);
+          }
+        }
+      }
+    }
+    for (; cr < nr; ++cr) {
+      finish_row(cr);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) acc[j] = T(0);
+      diag = false;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    sr[wave][lane + kWave * j] = accr[j];
+    sx[wave][lane + kWave * j] = accx[j];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (!cok[j]) continue;
+      const int t = lane + kWave * j;
+      const double a = ((sr[0][t] + sr[1][t]) + sr[2][t]) + sr[3][t];
+      const double b = ((sx[0][t] + sx[1][t]) + sx[2][t]) + sx[3][t];
+      part_r[lb * nx + col0 + kWave * j] = a;
+      part_x[lb * nx + col0 + kWave * j] = b;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ MFMA
 template <typename T>
 struct Mfma;
@@ -299,8 +423,9 @@ __global__ __launch_bounds__(kWave * WM * WP, 2) void gram_partial_kernel(
     }
 }
 
+template <typename P>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int p1, int nsplit,
-                                                          const double* __restrict__ part,
+                                                          const P* __restrict__ part,
                                                           double* __restrict__ G1, int c1,
                                                           double* __restrict__ G2, int c2,
                                                           int64_t ldg, int mirror_rows) {
@@ -312,12 +437,12 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int p1, 
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int t = 0;
   for (; t + 4 <= nsplit; t += 4) {
-    s0 += part[(int64_t)t * mp + idx];
-    s1 += part[(int64_t)(t + 1) * mp + idx];
-    s2 += part[(int64_t)(t + 2) * mp + idx];
-    s3 += part[(int64_t)(t + 3) * mp + idx];
+    s0 += (double)part[(int64_t)t * mp + idx];
+    s1 += (double)part[(int64_t)(t + 1) * mp + idx];
+    s2 += (double)part[(int64_t)(t + 2) * mp + idx];
+    s3 += (double)part[(int64_t)(t + 3) * mp + idx];
   }
-  for (; t < nsplit; ++t) s0 += part[(int64_t)t * mp + idx];
+  for (; t < nsplit; ++t) s0 += (double)part[(int64_t)t * mp + idx];
   const double s = (s0 + s1) + (s2 + s3);
   double* G = j < p1 ? G1 : G2;
   const int c = j < p1 ? c1 + j : c2 + (j - p1);
@@ -1524,8 +1649,8 @@ void launch_gram_plan(const GramPlan& g, int64_t n, int m, int p, int p1, const 
 #undef LOBPCG_GRAM_LAUNCH
     LOBPCG_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for((int64_t)m * p)), dim3(256), 0, s, m, p,
-                     p1, nsplit, part, G1, c1, G2 ? G2 : G1, c2, ldg, mirror_rows);
+  hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3(blocks_for((int64_t)m * p)), dim3(256), 0, s,
+                     m, p, p1, nsplit, part, G1, c1, G2 ? G2 : G1, c2, ldg, mirror_rows);
   LOBPCG_HIP(hipGetLastError());
 }
 }  // namespace
@@ -1646,6 +1771,54 @@ void launch_residual(int64_t n, int nx, const T* AX, int64_t ldax, const T* BX, 
   LOBPCG_HIP(hipGetLastError());
   hipLaunchKernelGGL(residual_rho_kernel, dim3((unsigned)nx), dim3(256), 0, s, nx, (int)nb, part_r,
                      part_x, theta, normA, normB, rho);
+  hipLaunchKernelGGL(residual_nc_kernel, dim3(1), dim3(256), 0, s, nx, rho, theta, tol, n_c);
+  LOBPCG_HIP(hipGetLastError());
+}
+
+template <typename P>
+void launch_gram_reduce(int m, int p, int p1, int nparts, const P* part, double* G1, int c1,
+                        double* G2, int c2, int64_t ldg, int mirror_rows, hipStream_t s) {
+  if (m == 0 || p == 0) return;
+  hipLaunchKernelGGL(gram_reduce_kernel<P>, dim3(blocks_for((int64_t)m * p)), dim3(256), 0, s, m,
+                     p, p1, nparts, part, G1, c1, G2 ? G2 : G1, c2, ldg, mirror_rows);
+  LOBPCG_HIP(hipGetLastError());
+}
+template void launch_gram_reduce<double>(int, int, int, int, const double*, double*, int, double*,
+                                         int, int64_t, int, hipStream_t);
+template void launch_gram_reduce<float>(int, int, int, int, const float*, double*, int, double*,
+                                        int, int64_t, int, hipStream_t);
+
+int64_t spmm_residual_workspace_bytes(int64_t n, int nx) {
+  const int64_t nb = std::max<int64_t>(1, (n + kSpmmRowsPerBlock - 1) / kSpmmRowsPerBlock);
+  return 2 * nb * (int64_t)std::max(nx, 1) * (int64_t)sizeof(double);
+}
+
+template <typename T>
+void launch_spmm_residual(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                          const T* vals, const T* X, int64_t ldx, int nx, const double* theta,
+                          const double* dinv, T* W, int64_t ldw, T* AX, int64_t ldax,
+                          double normA, double tol, double* rho, int32_t* n_c, void* work,
+                          hipStream_t s) {
+  if (nx == 0 || n == 0) return;
+  const int64_t nb = (n + kSpmmRowsPerBlock - 1) / kSpmmRowsPerBlock;
+  LOBPCG_CHECK(nb < (int64_t)1 << 31, LOBPCG_ERR_ARG, "fused residual grid too large");
+  double* part_r = static_cast<double*>(work);
+  double* part_x = part_r + nb * nx;
+  const unsigned gx = (unsigned)nb;
+  if (nx <= 64) {
+    hipLaunchKernelGGL((spmm_residual_kernel<T, 1>), dim3(gx, 1), dim3(256), 0, s, n, rowptr,
+                       colind, vals, X, ldx, nx, theta, dinv, W, ldw, AX, ldax, part_r, part_x);
+  } else if (nx <= 128) {
+    hipLaunchKernelGGL((spmm_residual_kernel<T, 2>), dim3(gx, 1), dim3(256), 0, s, n, rowptr,
+                       colind, vals, X, ldx, nx, theta, dinv, W, ldw, AX, ldax, part_r, part_x);
+  } else {
+    const unsigned gy = (unsigned)((nx + 255) / 256);
+    hipLaunchKernelGGL((spmm_residual_kernel<T, 4>), dim3(gx, gy), dim3(256), 0, s, n, rowptr,
+                       colind, vals, X, ldx, nx, theta, dinv, W, ldw, AX, ldax, part_r, part_x);
+  }
+  LOBPCG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(residual_rho_kernel, dim3((unsigned)nx), dim3(256), 0, s, nx, (int)nb, part_r,
+                     part_x, theta, normA, 1.0, rho);
   hipLaunchKernelGGL(residual_nc_kernel, dim3(1), dim3(256), 0, s, nx, rho, theta, tol, n_c);
   LOBPCG_HIP(hipGetLastError());
 }
@@ -1867,6 +2040,10 @@ void launch_sqrt_sum(int n, const double* v, double* out, hipStream_t s) {
                                    int64_t, double, double, double, double*, int32_t*, void*,   \
                                    hipStream_t);                                                \
   template void launch_colsq<T>(int64_t, int, const T*, int64_t, double*, void*, hipStream_t); \
+  template void launch_spmm_residual<T>(int64_t, const int64_t*, const int32_t*, const T*,     \
+                                        const T*, int64_t, int, const double*, const double*,  \
+                                        T*, int64_t, T*, int64_t, double, double, double*,     \
+                                        int32_t*, void*, hipStream_t);                          \
   template void launch_copy2d_reverse<T>(int64_t, int, const T*, int64_t, T*, int64_t,         \
                                          hipStream_t);
 LOBPCG_INST(double)

@@ -27,6 +27,14 @@ void launch_gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, const
                  int64_t ldr1, const T* R2, int64_t ldr2, double* G1, int c1, double* G2, int c2,
                  int64_t ldg, int mirror_rows, void* work, hipStream_t s);
 
+// The second stage of launch_gram on its own: G(i, c + j) = sum over the
+// nparts partial tiles part[t][i * p + j] (row-major m x p each, summed in
+// FP64 in a fixed order), columns j < p1 to G1 from c1, the rest to G2 from
+// c2; mirror_rows as launch_gram.
+template <typename P>
+void launch_gram_reduce(int m, int p, int p1, int nparts, const P* part, double* G1, int c1,
+                        double* G2, int c2, int64_t ldg, int mirror_rows, hipStream_t s);
+
 // launch_gram with the split-K partial tiles in a fixed device array of
 // kGramScratchBytes per GPU instead of a workspace (the split count is capped
 // to fit); m * p * 8 > kGramScratchBytes is LOBPCG_ERR_ARG.  Calls that overlap
@@ -56,6 +64,19 @@ void launch_residual(int64_t n, int nx, const T* AX, int64_t ldax, const T* BX, 
 
 // out[j] = sum_i Y[i, j]^2 for j < ncols (FP64 accumulation, deterministic).
 int64_t colsq_workspace_bytes(int64_t n, int ncols);
+// A X fused with the residual for B = I: the sparse product over the n_x
+// columns of X (row-major, ldx), then per row R = A X - X Theta written to W
+// with reversed columns and the Jacobi factor dinv (may be NULL), A X to AX
+// when AX != NULL, and criterion (9) with ||B|| = 1 as launch_residual.
+// work: spmm_residual_workspace_bytes(n, nx) bytes.
+int64_t spmm_residual_workspace_bytes(int64_t n, int nx);
+template <typename T>
+void launch_spmm_residual(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                          const T* vals, const T* X, int64_t ldx, int nx, const double* theta,
+                          const double* dinv, T* W, int64_t ldw, T* AX, int64_t ldax,
+                          double normA, double tol, double* rho, int32_t* n_c, void* work,
+                          hipStream_t s);
+
 template <typename T>
 void launch_colsq(int64_t n, int ncols, const T* Y, int64_t ldy, double* out, void* work,
                   hipStream_t s);

@@ -23,9 +23,26 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "kernels.hpp"
 
 namespace lobpcg {
+
+// Rows per chunk when the Gram blocks go through the library's batched GEMM
+// (0: gram_partial_kernel).  Measured on MI355X: for the 64^3 shapes (m x p up
+// to 330 x 220) the split-K kernel is faster (46 against 41 TFLOP/s FP64, 82
+// against 58 FP32); for the FEM k = 400 and periodic k = 1000 shapes the
+// batched GEMM over row chunks runs FP64 at 66-70 TFLOP/s against 43-45, and
+// FP32 at 134 against 90 (k = 1000; at k = 400 the two tie in FP32).  FP32
+// chunks keep the kernel's bound of 8192 rows per FP32 accumulation.
+static int64_t gram_library_rows(bool fp32, int64_t n, int m, int p) {
+  const int64_t mp = (int64_t)m * p;
+  if (fp32) return mp >= 2000000 ? std::min<int64_t>(n, 8192) : 0;
+  if (mp < 500000) return 0;
+  return std::min<int64_t>(n, std::max<int64_t>(4096, (n / 32 + 255) / 256 * 256));
+}
+
 
 namespace {
 constexpr double kEps64 = 2.220446049250313e-16;
@@ -182,6 +199,17 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   X0buf_.alloc(sizeof(double) * (size_t)n_ * nx_);
   int64_t ws = gram_workspace_bound(n_, nsmax_, 2 * nx_, split);
   ws = std::max(ws, residual_workspace_bytes(n_, nx_));
+  ws = std::max(ws, spmm_residual_workspace_bytes(n_, nx_));
+  {
+    // partial tiles of the library Gram path at its largest shape (m = n_s,
+    // p = 2 n_x); both precisions' chunkings
+    const int64_t mp = (int64_t)nsmax_ * 2 * nx_;
+    for (int f = 0; f < (split ? 2 : 1); ++f) {
+      const int64_t rows = gram_library_rows(f == 1, n_, nsmax_, 2 * nx_);
+      if (rows > 0)
+        ws = std::max(ws, ((n_ + rows - 1) / rows) * mp * (int64_t)(f == 1 ? 4 : 8));
+    }
+  }
   ws = std::max(ws, colsq_workspace_bytes(n_, 2 * nx_));
   ws = std::max(ws, jacobi_workspace_bytes(n_));
   work_.alloc(ws);
@@ -192,6 +220,47 @@ Solver::Solver(const lobpcg_csr* A, const lobpcg_csr* B, int k, const lobpcg_opt
   }
   dense_.reset(new Dense(nsmax_, nx_, s_));
   dense_->set_timer(&timer_);
+  {
+    // device workspace of the basis-update GEMMs at their largest shape
+    rocblas_handle h = dense_->handle();
+    size_t bytes = 0;
+    LOBPCG_CHECK(rocblas_start_device_memory_size_query(h) == rocblas_status_success,
+                 LOBPCG_ERR_HIP, "rocBLAS size query");
+    const double one = 1.0, zero = 0.0;
+    const float onef = 1.0f, zerof = 0.0f;
+    double* Cd = C_.as<double>();
+    (void)rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, 2 * nx_,
+                        (rocblas_int)n_, nsmax_, &one, Cd, nsmax_, b64_.S[0].as<double>(),
+                        (rocblas_int)ldS_, &zero, b64_.S[1].as<double>(), (rocblas_int)ldS_);
+    if (split) {
+      C32_.alloc(sizeof(float) * (size_t)nsmax_ * 2 * nx_);
+      (void)rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, 2 * nx_,
+                          (rocblas_int)n_, nsmax_, &onef, C32_.as<float>(), nsmax_,
+                          b32_.S[0].as<float>(), (rocblas_int)ldS_, &zerof,
+                          b32_.S[1].as<float>(), (rocblas_int)ldS_);
+    }
+    // and of the batched Gram GEMMs (R operand n x 2 n_x, L operand n x n_s)
+    for (int f = 0; f < (split ? 2 : 1); ++f) {
+      const int64_t rows = gram_library_rows(f == 1, n_, nsmax_, 2 * nx_);
+      if (rows == 0) continue;
+      const int64_t mp = (int64_t)nsmax_ * 2 * nx_;
+      if (f == 0)
+        (void)rocblas_dgemm_strided_batched(
+            h, rocblas_operation_none, rocblas_operation_transpose, 2 * nx_, nsmax_,
+            (rocblas_int)rows, &one, b64_.S[0].as<double>(), (rocblas_int)ldS_, rows * ldS_,
+            b64_.S[1].as<double>(), (rocblas_int)ldS_, rows * ldS_, &zero,
+            static_cast<double*>(work_.get()), 2 * nx_, mp, (rocblas_int)(n_ / rows));
+      else
+        (void)rocblas_sgemm_strided_batched(
+            h, rocblas_operation_none, rocblas_operation_transpose, 2 * nx_, nsmax_,
+            (rocblas_int)rows, &onef, b32_.S[0].as<float>(), (rocblas_int)ldS_, rows * ldS_,
+            b32_.S[1].as<float>(), (rocblas_int)ldS_, rows * ldS_, &zerof,
+            static_cast<float*>(work_.get()), 2 * nx_, mp, (rocblas_int)(n_ / rows));
+    }
+    LOBPCG_CHECK(rocblas_stop_device_memory_size_query(h, &bytes) == rocblas_status_success,
+                 LOBPCG_ERR_HIP, "rocBLAS size query");
+    dense_->reserve_library_workspace(bytes);
+  }
   // nc_[2]: set by the tridiagonal eigensolver when a QL leaf did not
   // converge; read with n_c once per iteration
   dense_->set_status_word(nc_.as<int32_t>() + 2);
@@ -333,9 +402,60 @@ void Solver::gram(int64_t n, int m, int p, int p1, const T* L, int64_t ldl, cons
                   int64_t ldg, int mirror_rows) {
   if (m == 0 || p == 0) return;
   const int tok = timer_.start(s_);
-  launch_gram<T>(n, m, p, p1, L, ldl, R1, ldr1, R2, ldr2, G1, c1, G2, c2, ldg, mirror_rows,
-                 work_.get(), s_);
+  const int64_t rows = gram_library_rows(sizeof(T) == 4, n, m, p);
+  if (rows > 0) {
+    // Split-K through the library: partial tiles (p x m column-major, i.e.
+    // row-major m x p) of equal row chunks by one strided-batched GEMM per R
+    // segment (G^T = R^T L in column-major terms), the remainder chunk by a
+    // plain GEMM, then the same fixed-order FP64 sum as gram_partial_kernel's.
+    rocblas_handle h = dense_->handle();
+    T* part = static_cast<T*>(work_.get());
+    const int64_t full = n / rows, rem = n - full * rows;
+    const int64_t mp = (int64_t)m * p;
+    const T one = 1, zero = 0;
+    auto gemm = [&](int pr, const T* R, int64_t ldr, int64_t r0, int64_t nr, int64_t batch,
+                    T* out) {
+      rocblas_status st;
+      if constexpr (sizeof(T) == 8)
+        st = rocblas_dgemm_strided_batched(
+            h, rocblas_operation_none, rocblas_operation_transpose, pr, m, (rocblas_int)nr, &one,
+            R + r0 * ldr, (rocblas_int)ldr, nr * ldr, L + r0 * ldl, (rocblas_int)ldl, nr * ldl,
+            &zero, out, p, mp, (rocblas_int)batch);
+      else
+        st = rocblas_sgemm_strided_batched(
+            h, rocblas_operation_none, rocblas_operation_transpose, pr, m, (rocblas_int)nr, &one,
+            R + r0 * ldr, (rocblas_int)ldr, nr * ldr, L + r0 * ldl, (rocblas_int)ldl, nr * ldl,
+            &zero, out, p, mp, (rocblas_int)batch);
+      LOBPCG_CHECK(st == rocblas_status_success, LOBPCG_ERR_HIP,
+                   "rocBLAS strided-batched GEMM (Gram blocks)");
+    };
+    const int p2 = p - p1;
+    if (full > 0) {
+      gemm(p1, R1, ldr1, 0, rows, full, part);
+      if (p2 > 0) gemm(p2, R2, ldr2, 0, rows, full, part + p1);
+    }
+    if (rem > 0) {
+      gemm(p1, R1, ldr1, full * rows, rem, 1, part + full * mp);
+      if (p2 > 0) gemm(p2, R2, ldr2, full * rows, rem, 1, part + full * mp + p1);
+    }
+    launch_gram_reduce<T>(m, p, p1, (int)(full + (rem > 0)), part, G1, c1, G2, c2, ldg,
+                          mirror_rows, s_);
+  } else {
+    launch_gram<T>(n, m, p, p1, L, ldl, R1, ldr1, R2, ldr2, G1, c1, G2, c2, ldg, mirror_rows,
+                   work_.get(), s_);
+  }
   timer_.stop(tok, 1, 2.0 * n * m * p, s_);
+}
+
+// The basis update Y = S C is a plain GEMM.  Measured on MI355X: rocBLAS's
+// GEMM runs the FP32 products at 67-144 TFLOP/s against 54-71 for
+// update_kernel (64^3 to 96^3 shapes, K = 330-3300, N = 110-1100), and the
+// FP64 ones at 61-72 against 55-59 once K * N reaches ~5e5, while
+// update_kernel is the faster one for the FP64 shapes of the 64^3 workload
+// (K = 330, N <= 220: 50-52 against 40-49).
+static bool update_uses_library(bool fp32, int K, int N) {
+  if (fp32) return true;
+  return (int64_t)K * N >= 250000;
 }
 
 template <typename T>
@@ -343,7 +463,27 @@ void Solver::update(int64_t n, int K, int N, const T* S, int64_t lds, const doub
                     int64_t ldc, double alpha, double beta, T* Y, int64_t ldy) {
   if (N == 0) return;
   const int tok = timer_.start(s_);
-  launch_update<T>(n, K, N, S, lds, C, ldc, alpha, beta, Y, ldy, s_);
+  if (update_uses_library(sizeof(T) == 4, K, N)) {
+    // Y^T (N x n) = C^T (N x K) S^T (K x n) in column-major terms: S, Y row-major
+    rocblas_handle h = dense_->handle();
+    if constexpr (sizeof(T) == 4) {
+      launch_copy2d<double, float>(N, K, C, ldc, C32_.as<float>(), ldc, s_);
+      const float a = (float)alpha, b = (float)beta;
+      LOBPCG_CHECK(rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, N,
+                                 (rocblas_int)n, K, &a, C32_.as<float>(), (rocblas_int)ldc, S,
+                                 (rocblas_int)lds, &b, Y, (rocblas_int)ldy) ==
+                       rocblas_status_success,
+                   LOBPCG_ERR_HIP, "rocblas_sgemm (basis update)");
+    } else {
+      LOBPCG_CHECK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, N,
+                                 (rocblas_int)n, K, &alpha, C, (rocblas_int)ldc, S,
+                                 (rocblas_int)lds, &beta, Y, (rocblas_int)ldy) ==
+                       rocblas_status_success,
+                   LOBPCG_ERR_HIP, "rocblas_dgemm (basis update)");
+    }
+  } else {
+    launch_update<T>(n, K, N, S, lds, C, ldc, alpha, beta, Y, ldy, s_);
+  }
   timer_.stop(tok, 2, 2.0 * n * K * N, s_);
 }
 
@@ -596,16 +736,35 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     cur ^= 1;
     // Residual R = AX - BX Theta with A X recomputed by the sparse product, or
     // updated implicitly as A X = (A S) C_x (section 5.2).
+    // With B = I and A X recomputed, the sparse product and the residual run
+    // as one kernel (A X is stored only when the next step forms its X/P Gram
+    // blocks explicitly, the one later use).
+    const bool fused = !impl && !B;
     if (impl) {
       AX = ASp(cur);
       update<T>(n, ns, nx, ASo, ldS, C, ldc, 1.0, 0.0, AX, ldS);
-    } else {
+    } else if (!fused) {
       phase_mark(0);
       spmm<T>(A, Sn, ldS, AX, ldX, nx);
     }
     if (B) spmm<T>(*B, Sn, ldS, BXP, ldBXP, nx);
     phase_mark(6);
-    {
+    if (fused) {
+      const bool keep_ax = !opt_.implicit_gram || basic || xp_explicit;
+      const T* av;
+      if constexpr (sizeof(T) == 8) av = A.v64.as<T>();
+      else av = A.v32.as<T>();
+      const double sv = sizeof(T);
+      const int tok = timer_.start(s_);
+      launch_spmm_residual<T>(n, A.rowptr.as<int64_t>(), A.colind.as<int32_t>(), av, Sn, ldS,
+                              nx, theta, dinv, use_cb ? Rb : Sn + nx + npn,
+                              use_cb ? ldX : ldS, keep_ax ? AX : nullptr, ldAX, normA_, tol,
+                              rho_.as<double>(), nc_.as<int32_t>(), work_.get(), s_);
+      timer_.stop(tok, 0,
+                  (double)A.nnz * (sv + 4) + 8.0 * (n + 1) + (double)n * nx * sv * (keep_ax ? 3 : 2) +
+                      (dinv ? 8.0 * n : 0.0),
+                  s_);
+    } else {
       const int tok = timer_.start(s_);
       launch_residual<T>(n, nx, AX, ldAX, B ? BXP : nullptr, ldBXP, Sn, ldS, theta, dinv,
                          use_cb ? Rb : Sn + nx + npn, use_cb ? ldX : ldS, normA_, normB_, tol,

@@ -98,6 +98,7 @@ class Solver {
   Blocks<double> b64_;
   Blocks<float> b32_;
   DevBuf GA_, GB_, C_, theta_, theta_p_, rho_, dinv_, nc_, work_, X0buf_, nrm_;
+  DevBuf C32_;  // FP32 copy of C for the library GEMM of the FP32 phase
   int32_t* hbuf_ = nullptr;   // pinned host words
   hipEvent_t ev_nc_ = nullptr;  // n_c copied to hbuf_ (the host waits for it alone)
   double* hdbl_ = nullptr;    // pinned host doubles
