@@ -104,9 +104,21 @@ def _oracle_threads():
         return len(os.sched_getaffinity(0))
 
 
+def _whole_solve_ratio():
+    """Mean iteration time of the committed whole oracle solve of this workload over
+    the mean of its iterations 2..6 (later iterations lock pairs and cost less), and
+    that solve's record; (None, None) when the profile is absent."""
+    path = os.path.join(ROOT, "profiles", "oracle_laplace64_k100_whole_solve.json.txt")
+    if not os.path.exists(path):
+        return None, None
+    rec = json.loads([ln for ln in open(path) if ln.startswith("{")][-1])
+    return rec["iteration_seconds_mean"] / rec["iteration_seconds_first5_after_1"], rec
+
+
 def cpu_baseline(w, iters, gpu_iters):
     """The oracle, untuned, on the host: set-up plus `iters` iterations of the same
-    solve, each iteration timed on its own."""
+    solve, each iteration timed on its own, scaled to the GPU's iteration count with
+    the per-iteration profile of a committed whole oracle solve of this workload."""
     from oracle import lobpcg as L
 
     A = w.A.to_scipy()
@@ -119,17 +131,28 @@ def cpu_baseline(w, iters, gpu_iters):
     # Iteration 1 has no P block (n_s = 2 n_x); the later ones are full width.
     steady = its[1:] if len(its) > 1 else its
     per_it = sum(steady) / len(steady)
-    return {
-        "value": setup + per_it * gpu_iters,
+    raw = setup + per_it * gpu_iters
+    ratio, rec = _whole_solve_ratio()
+    value = setup + per_it * (ratio or 1.0) * gpu_iters
+    out = {
+        "value": value,
         "unit": "s",
         "cores": _oracle_threads(),
         "kind": "oracle",
         "sample": (f"set-up ({setup:.1f} s) and {res.iterations} oracle iterations of the same "
                    f"64^3 solve from the same X0; iterations 2..{res.iterations} (full "
-                   f"n_s = 3 n_x) average {per_it:.2f} s; value = set-up + that rate times the "
-                   f"GPU FP64 iteration count ({gpu_iters}), an estimate from the start of the "
-                   "solve, where no pair is locked yet and every iteration is full width"),
+                   f"n_s = 3 n_x) average {per_it:.2f} s; value = set-up + that rate x "
+                   + (f"{ratio:.3f} (mean over early iteration time of the committed whole "
+                      "oracle solve, profiles/oracle_laplace64_k100_whole_solve.json.txt: "
+                      "locked pairs make later iterations cheaper) x "
+                      if ratio else "") +
+                   f"the GPU FP64 iteration count ({gpu_iters})"),
+        "start_of_solve_extrapolation": raw,
     }
+    if rec:
+        out["whole_solve_measured"] = {"seconds": rec["seconds"], "iterations": rec["iterations"],
+                                       "threads": rec["threads"]}
+    return out
 
 
 def oracle_full_solve(w, label):
