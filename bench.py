@@ -474,6 +474,69 @@ def run_small(torch, B, P, reps=10):
     s.close()
 
 
+def run_seeds(torch, B, P, nseeds):
+    """The headline workload from the initial blocks of seeds 0..nseeds-1 (one
+    warm-up solve each, then one timed solve per precision): per-seed times and
+    iterations, median and minimum."""
+    exact = dirichlet3d_smallest(64, 100)
+    w0 = P.workload(1)
+    rows = []
+    for prec in ("fp64", "split"):
+        s = B.Solver(w0.A, w0.k, precond="jacobi", precision=prec)
+        per = []
+        for seed in range(nseeds):
+            X0 = torch.from_numpy(P.initial_block(seed, w0.A.n, w0.n_x)).cuda()
+            s.solve(w0.tol, X0)  # warm-up
+            info, sec = _timed_solve(torch, s, w0.tol, X0)
+            lam, X, _ = s.eigpairs(w0.k)
+            rho, err = check_solution(w0, lam.cpu().numpy(), X.cpu().numpy(),
+                                      info["norm_A_est"], exact)
+            per.append({"seed": seed, "seconds": sec, "iterations": info["iterations"],
+                        "status": info["status"], "max_rho": rho,
+                        "eig_rel_err_vs_closed_form": err})
+            _log(f"[bench] seeds {prec} seed {seed}: {sec:.3f} s, {info['iterations']} iterations")
+            del X0
+        t = sorted(p["seconds"] for p in per)
+        rows.append({"workload": "3D 7-point Dirichlet Laplacian 64^3 (n=262144), k=100, "
+                                 "n_x=110, Jacobi, tol 1e-8, X0 from default_rng(seed)",
+                     "precision": prec, "seeds": per, "median_seconds": t[len(t) // 2],
+                     "min_seconds": t[0]})
+        s.close()
+    for r in rows:
+        print(json.dumps(r), flush=True)
+
+
+def oracle_estimate(cfg, iters, gpu_iters):
+    """The oracle for `iters` iterations of a workload too large for a whole host
+    solve, each iteration timed; estimate = set-up + mean of iterations 2.. (full
+    width) x the GPU's iteration count."""
+    from oracle import lobpcg as L
+    from paper_1704_07458_amd import problems as P
+
+    w = P.workload(cfg)
+    A = w.A.to_scipy()
+    pre = L.jacobi_precond(A) if w.precond == "jacobi" else None
+    t_start = time.perf_counter()
+
+    def cb(h):
+        _log(f"[bench] oracle estimate: iteration {h.it} took {h.seconds:.1f} s "
+             f"({time.perf_counter() - t_start:.1f} s so far)")
+
+    t0 = time.perf_counter()
+    res = L.lobpcg(A, w.X0, w.k, w.tol, precond=pre, maxit=iters, callback=cb)
+    dt = time.perf_counter() - t0
+    its = [h.seconds for h in res.history]
+    setup = dt - sum(its)
+    full = its[1:] if len(its) > 1 else its
+    per = sum(full) / len(full)
+    return {"workload": w.name, "kind": "oracle, estimate", "iterations_run": res.iterations,
+            "iteration_seconds": its, "setup_seconds": setup,
+            "gpu_iterations": gpu_iters, "estimate_seconds": setup + per * gpu_iters,
+            "threads": _oracle_threads(),
+            "note": "mean of the full-width iterations (2..) x the GPU FP64 iteration count: an "
+                    "estimate from the start of the solve, where no pair is locked yet"}
+
+
 def _fem_smallest(N, k):
     h = 1.0 / (N + 1)
     t = np.arange(1, N + 1) * np.pi / (N + 1)
@@ -529,6 +592,12 @@ def main():
                     help="only time one whole oracle solve on the host: 0 = 32^2 "
                          "Laplacian k=10, 1 = 64^3 Laplacian k=100, 2 = FEM 48^3 k=400, "
                          "4 = 32^3 + potential k=64")
+    ap.add_argument("--seeds", type=int, default=0, metavar="N",
+                    help="time the headline workload from the blocks of seeds 0..N-1 instead")
+    ap.add_argument("--oracle-estimate", type=int, nargs=3, default=None,
+                    metavar=("CFG", "ITERS", "GPU_ITERS"),
+                    help="only time ITERS oracle iterations of workload CFG on the host and "
+                         "scale to GPU_ITERS (for pencils too large for a whole host solve)")
     ap.add_argument("--phases", action="store_true",
                     help="one extra untimed FP64 solve with per-phase timing (stream syncs)")
     args = ap.parse_args()
@@ -536,6 +605,11 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path (a row "
               "partition across GPUs with halo exchange is designed, not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_estimate is not None:
+        cfg, iters, gits = args.oracle_estimate
+        print(json.dumps(oracle_estimate(cfg, iters, gits)), flush=True)
+        return
 
     if args.oracle_full is not None:
         from paper_1704_07458_amd import problems as P
@@ -572,6 +646,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
     B.load()
+    if args.seeds:
+        run_seeds(torch, B, P, args.seeds)
+        return
     if args.workloads == "small":
         run_small(torch, B, P)
         return
