@@ -87,6 +87,23 @@ int lobpcg_residual(int64_t n, int32_t nx, int32_t dtype, const void* AX, int64_
                     double normB, double tol, double* rho, int32_t* n_c_out, void* work,
                     void* stream);
 
+/* Bytes of workspace lobpcg_spmm_residual needs. */
+int64_t lobpcg_spmm_residual_workspace(int64_t n, int32_t nx);
+
+/* The sparse product A X fused with Algorithm 8's residual and converged count for
+ * B = I (eq. 9), the solver's path for recomputed A X: Y = A X formed row by row (CSR
+ * A as in lobpcg_spmm; X: n x nx, ldx), stored to AX (ldax) only when AX != NULL;
+ * R = Y - X diag(theta); W(:, nx-1-j) = dinv .* R(:, j) (reversed column order,
+ * section 5.1; dinv NULL = identity; W must not be NULL nor alias X);
+ * rho_j = ||r_j||_2 / ((normA + |theta_j|) ||x_j||_2) with FP64 sums; n_c_out as
+ * lobpcg_residual.  The product's summation order is lobpcg_spmm's.  work:
+ * lobpcg_spmm_residual_workspace(n, nx) bytes. */
+int lobpcg_spmm_residual(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                         const void* values, int32_t dtype, const void* X, int64_t ldx,
+                         int32_t nx, const double* theta, const double* dinv, void* W,
+                         int64_t ldw, void* AX, int64_t ldax, double normA, double tol,
+                         double* rho, int32_t* n_c_out, void* work, void* stream);
+
 /* One RayleighRitzModified step (Algorithm 7) on the device, FP64.
  * GA, GB: n_s x n_s symmetric (column-major, ldg); GB is ignored when
  * use_ortho != 0 (S^T B S = I).  Reads n_x, n_c.  Outputs (device):

@@ -178,6 +178,12 @@ SIGNATURES = {
                                   C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                   C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lobpcg_spmm_residual_workspace": (C.c_int64, [C.c_int64, C.c_int32]),
+    "lobpcg_spmm_residual": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                       C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_double,
+                                       C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
     "lobpcg_rr_step": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
                                  C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
@@ -642,6 +648,28 @@ def residual(AX, X, theta, BX=None, dinv=None, W=None, normA=1.0, normB=1.0, tol
                                  W.stride(0) if W is not None else 0, float(normA), float(normB),
                                  float(tol), _ptr(rho), _ptr(nc), _ptr(work), _stream()))
     return rho, nc
+
+
+def spmm_residual(rowptr, colind, values, X, theta, W, dinv=None, AX=None, normA=1.0,
+                  tol=1e-8):
+    """A X fused with the residual for B = I (lobpcg_spmm_residual); W (n x nx view)
+    receives the reversed, Jacobi-scaled residual; returns (rho, n_c) device tensors."""
+    import torch
+
+    lib = load()
+    n, nx = int(X.shape[0]), int(X.shape[1])
+    dt = _dtype_code(X)
+    work = torch.empty(max(int(lib.lobpcg_spmm_residual_workspace(n, nx)), 8),
+                       dtype=torch.uint8, device="cuda")
+    rho = torch.empty(max(nx, 1), dtype=torch.float64, device="cuda")
+    nc = torch.zeros(2, dtype=torch.int32, device="cuda")
+    check(lib.lobpcg_spmm_residual(n, _ptr(rowptr), _ptr(colind), _ptr(values), dt, _ptr(X),
+                                   int(X.stride(0)), nx, _ptr(theta),
+                                   _ptr(dinv) if dinv is not None else None, _ptr(W),
+                                   int(W.stride(0)), _ptr(AX) if AX is not None else None,
+                                   int(AX.stride(0)) if AX is not None else 0, float(normA),
+                                   float(tol), _ptr(rho), _ptr(nc), _ptr(work), _stream()))
+    return rho[:nx], nc
 
 
 def rr_step(GA, GB, n_x: int, n_c: int, use_ortho: bool, tau_skip: float, literal: bool = False,

@@ -318,6 +318,34 @@ int lobpcg_residual(int64_t n, int32_t nx, int32_t dtype, const void* AX, int64_
   });
 }
 
+int64_t lobpcg_spmm_residual_workspace(int64_t n, int32_t nx) {
+  if (n < 0 || nx < 0) return -1;
+  return lobpcg::spmm_residual_workspace_bytes(n, nx);
+}
+
+int lobpcg_spmm_residual(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                         const void* values, int32_t dtype, const void* X, int64_t ldx,
+                         int32_t nx, const double* theta, const double* dinv, void* W,
+                         int64_t ldw, void* AX, int64_t ldax, double normA, double tol,
+                         double* rho, int32_t* n_c_out, void* work, void* stream) {
+  return guarded([&]() {
+    LOBPCG_CHECK(n >= 0 && nx >= 0 && ldx >= nx && W && ldw >= nx && (!AX || ldax >= nx) &&
+                     (dtype == 0 || dtype == 1),
+                 LOBPCG_ERR_ARG, "lobpcg_spmm_residual: bad arguments");
+    if (dtype == 0)
+      lobpcg::launch_spmm_residual<double>(n, rowptr, colind, (const double*)values,
+                                           (const double*)X, ldx, nx, theta, dinv, (double*)W,
+                                           ldw, (double*)AX, ldax, normA, tol, rho, n_c_out,
+                                           work, as_stream(stream));
+    else
+      lobpcg::launch_spmm_residual<float>(n, rowptr, colind, (const float*)values,
+                                          (const float*)X, ldx, nx, theta, dinv, (float*)W, ldw,
+                                          (float*)AX, ldax, normA, tol, rho, n_c_out, work,
+                                          as_stream(stream));
+    return LOBPCG_OK;
+  });
+}
+
 int lobpcg_rr_step(int32_t n_s, int32_t n_x, int32_t n_c, int32_t use_ortho, int32_t lq_literal,
                    int32_t n_ident, const double* GA, const double* GB, int64_t ldg,
                    double tau_skip, double* C,

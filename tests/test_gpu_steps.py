@@ -245,6 +245,99 @@ def test_residual_and_criterion9(lib):
     assert nc2.cpu().numpy()[0] == expect
 
 
+@pytest.mark.parametrize("nx", [1, 13, 64, 65, 130, 300])
+def test_spmm_residual_fused_fp64(lib, nx):
+    """A X fused with the residual and criterion (9) for B = I: W, rho and n_c against a
+    host FP64 computation on a ragged pattern (empty rows, rows without a diagonal
+    entry, one long row), and the stored A X equal bit for bit to the plain product."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    A = _ragged_csr(3, 1111)
+    As = A.to_scipy()
+    rp, ci, va = _dev_csr(A)
+    rng = np.random.default_rng(nx)
+    n = A.n
+    ld = nx + 5
+    Xh = rng.standard_normal((n, ld))
+    X = torch.from_numpy(Xh).cuda()[:, :nx]
+    theta = np.sort(rng.uniform(-2, 5, nx))
+    dinv = rng.uniform(0.5, 2.0, n)
+    Wt = torch.full((n, nx + 2), np.nan, dtype=torch.float64, device="cuda")
+    AXt = torch.full((n, nx + 1), np.nan, dtype=torch.float64, device="cuda")
+    normA = 9.0
+    rho, nc = B.spmm_residual(rp, ci, va, X, torch.from_numpy(theta).cuda(), Wt[:, :nx],
+                              dinv=torch.from_numpy(dinv).cuda(), AX=AXt[:, :nx], normA=normA,
+                              tol=1e300)
+    x = Xh[:, :nx]
+    AX = As @ x
+    ax_bound = 2 * gamma(int(np.diff(A.rowptr).max()), U64) * (abs(As) @ np.abs(x))
+    got_ax = AXt.cpu().numpy()[:, :nx]
+    assert np.all(np.abs(got_ax - AX) <= ax_bound + 1e-300)
+    plain = B.spmm(rp, ci, va, X)
+    assert np.array_equal(got_ax, plain.cpu().numpy())
+    assert np.all(np.isnan(AXt.cpu().numpy()[:, nx:]))
+    R = AX - x * theta
+    # the residual carries the product's error plus one rounding of theta x and one
+    # of the difference; W adds the rounding of the scaling
+    r_bound = ax_bound + 2 * U64 * (np.abs(AX) + np.abs(x * theta)) + 1e-300
+    W = Wt.cpu().numpy()
+    assert np.all(np.isnan(W[:, nx:]))
+    refW = (R * dinv[:, None])[:, ::-1]
+    w_bound = (r_bound * dinv[:, None])[:, ::-1] * (1 + 2 * U64) + U64 * np.abs(refW)
+    assert np.all(np.abs(W[:, :nx] - refW) <= w_bound)
+    ref_rho = L.criterion9(R, x, theta, normA, 1.0)
+    got_rho = rho.cpu().numpy()
+    rel = np.linalg.norm(r_bound, axis=0) / ((normA + np.abs(theta)) *
+                                             np.linalg.norm(x, axis=0))
+    assert np.all(np.abs(got_rho - ref_rho) <= rel + 1e-13 * ref_rho)
+    n_c = nc.cpu().numpy()
+    assert n_c[0] == nx and n_c[1] == 0
+    # leading run below a threshold that accepts the first column only when it is
+    # not larger than the second
+    thr = float(ref_rho[0] * (1 + 1e-9))
+    _, nc2 = B.spmm_residual(rp, ci, va, X, torch.from_numpy(theta).cuda(), Wt[:, :nx],
+                             normA=normA, tol=thr)
+    ok = got_rho <= thr
+    expect = int(np.argmin(ok)) if not ok.all() else nx
+    assert nc2.cpu().numpy()[0] == expect >= 1
+    # without dinv the W store is the unscaled reversed residual
+    assert np.all(np.abs(Wt.cpu().numpy()[:, :nx] - R[:, ::-1]) <=
+                  r_bound[:, ::-1] + U64 * np.abs(R[:, ::-1]))
+
+
+def test_spmm_residual_fused_fp32(lib):
+    """FP32 product and stores with FP64 residual sums: W and A X within the FP32
+    product's bound of a host FP64 computation on the same FP32 data."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    A = P.add_diagonal(P.laplacian_3d(11), np.linspace(0, 3, 11 ** 3))
+    As = A.to_scipy().astype(np.float32).astype(np.float64)
+    rp, ci, va = _dev_csr(A, np.float32)
+    rng = np.random.default_rng(7)
+    nx = 70
+    X32 = rng.standard_normal((A.n, nx)).astype(np.float32)
+    theta = np.sort(rng.uniform(0.1, 4, nx))
+    Wt = torch.empty((A.n, nx), dtype=torch.float32, device="cuda")
+    AXt = torch.empty((A.n, nx), dtype=torch.float32, device="cuda")
+    rho, nc = B.spmm_residual(rp, ci, va, torch.from_numpy(X32).cuda(),
+                              torch.from_numpy(theta).cuda(), Wt, AX=AXt, normA=15.0, tol=1e300)
+    x = X32.astype(np.float64)
+    AX = As @ x
+    ax_bound = 2 * gamma(7, U32) * (abs(As) @ np.abs(x))
+    got_ax = AXt.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got_ax - AX) <= ax_bound)
+    R = AX - x * theta
+    r_bound = ax_bound + 2 * U64 * (np.abs(AX) + np.abs(x * theta))
+    W = Wt.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(W - R[:, ::-1]) <= r_bound[:, ::-1] + U32 * np.abs(R[:, ::-1]) + 1e-30)
+    ref_rho = L.criterion9(R, x, theta, 15.0, 1.0)
+    rel = np.linalg.norm(r_bound, axis=0) / ((15.0 + np.abs(theta)) * np.linalg.norm(x, axis=0))
+    assert np.all(np.abs(rho.cpu().numpy() - ref_rho) <= rel + 1e-12 * ref_rho)
+    assert nc.cpu().numpy()[0] == nx
+
+
 def _signs_match(a, b, tol):
     """Columns of a equal +-columns of b; returns the sign vector."""
     s = np.sign(np.sum(a * b, axis=0))
