@@ -134,6 +134,47 @@ def test_spmm_full_size_sampled_rows(lib, cfg1):
         assert np.all(np.abs(Y[rows] - ref) <= bound)
 
 
+def test_spmm_residual_full_size_sampled_rows(lib, cfg1):
+    """A X fused with the residual and criterion (9) (the B = I product the solver
+    runs) at the bench's shape, 262144 x 110: the stored A X and the reversed,
+    Jacobi-scaled residual on sampled rows within the product's rounding bound of
+    host FP64 products, and rho (a sum over every row) against the host's norms."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    A = cfg1.A
+    As = A.to_scipy()
+    n, nx = A.n, cfg1.n_x
+    rp = torch.from_numpy(A.rowptr).cuda()
+    ci = torch.from_numpy(A.colind).cuda()
+    va = torch.from_numpy(A.values).cuda()
+    rng = np.random.default_rng(3)
+    Xh = rng.standard_normal((n, nx))
+    theta = np.sort(rng.uniform(0.01, 0.5, nx))
+    dinv = 1.0 / L.jacobi_diagonal(As)
+    X = torch.from_numpy(Xh).cuda()
+    W = torch.empty((n, nx), dtype=torch.float64, device="cuda")
+    AXt = torch.empty((n, nx), dtype=torch.float64, device="cuda")
+    rho, nc = B.spmm_residual(rp, ci, va, X, torch.from_numpy(theta).cuda(), W,
+                              dinv=torch.from_numpy(dinv).cuda(), AX=AXt, normA=12.0,
+                              tol=1e300)
+    rows = rng.choice(n, 3000, replace=False)
+    AXs = As[rows] @ Xh
+    ax_bound = 2 * gamma(7, U64) * (abs(As[rows]) @ np.abs(Xh))
+    got_ax = AXt.cpu().numpy()[rows]
+    assert np.all(np.abs(got_ax - AXs) <= ax_bound)
+    R = AXs - Xh[rows] * theta
+    r_bound = ax_bound + 2 * U64 * (np.abs(AXs) + np.abs(Xh[rows] * theta))
+    refW = (R * dinv[rows, None])[:, ::-1]
+    w_bound = (r_bound * dinv[rows, None])[:, ::-1] * (1 + 2 * U64) + U64 * np.abs(refW)
+    assert np.all(np.abs(W.cpu().numpy()[rows] - refW) <= w_bound)
+    # rho over all rows: the host's FP64 residual norms of the full product
+    Rall = As @ Xh - Xh * theta
+    ref_rho = L.criterion9(Rall, Xh, theta, 12.0, 1.0)
+    assert np.allclose(rho.cpu().numpy(), ref_rho, rtol=1e-12, atol=0)
+    assert nc.cpu().numpy()[0] == nx
+
+
 def test_gram_and_update_full_size(lib, cfg1):
     """Gram S^T [AW | W] and update S C at the bench's shapes (n = 262144, n_s = 330)."""
     torch = _torch()
