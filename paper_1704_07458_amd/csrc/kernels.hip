@@ -32,6 +32,11 @@ constexpr int kXcds = 8;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+// Config word of a raw buffer resource on gfx9-family chips (32-bit data,
+// no swizzle): buffer loads take one per-lane offset and a scalar offset.
+constexpr int kBufferConfig = 0x00020000;
 
 // Workgroups are handed to the 8 XCDs round-robin.  Map the dispatch index so
 // that each XCD works on one contiguous range of logical blocks: neighbouring
@@ -1217,7 +1222,7 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
       const int groups = kTrdThreads / q_pass;  // 2..16 column groups
       const int rows_pass = kR * q_pass;
       {
-        const int g = t / q_pass, qq = t % q_pass;
+        const int g = uniform(t / q_pass), qq = t % q_pass;  // q_pass: whole waves
         // column i + 1 is not modified again within the panel: keep its raw
         // entry for the next step (thread t owns row i + 1 + t there)
         have_pre = j + 1 < nbp && i + 1 + t < n;
@@ -1231,18 +1236,31 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
             const double* ap = A + (int64_t)(i + 1 + g) * lda + r0;
             int c = i + 1 + g;
             if (kPairs && r0 + 1 < n) {
+              // buffer loads: the lane's byte offset in one register, the
+              // batch's column offsets scalar (the launcher keeps lda n 8 < 2^31)
+              const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                  A, (short)0, (int)(lda * n * (int64_t)sizeof(double)), kBufferConfig);
+              int voff = (int)(((int64_t)c * lda + r0) * (int64_t)sizeof(double));
+              const int cstep = (int)(step * (int64_t)sizeof(double));
               for (; c + 7 * groups < n; c += 8 * groups) {
-                double2 av[8];
+                // the batch's v entries first, all in flight together with the
+                // matrix loads (one LDS latency per batch, not one per column)
+                double vc[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) av[u] = *reinterpret_cast<const double2*>(ap + u * step);
-                ap += 8 * step;
+                for (int u = 0; u < 8; ++u) vc[u] = vj[c + u * groups];
+                v4i raw[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                  raw[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, u * cstep, 0);
+                voff += 8 * cstep;
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                  const double vc = vj[c + u * groups];
-                  acc0 = fma(av[u].x, vc, acc0);
-                  acc1 = fma(av[u].y, vc, acc1);
+                  const v2d av = __builtin_bit_cast(v2d, raw[u]);
+                  acc0 = fma(av.x, vc[u], acc0);
+                  acc1 = fma(av.y, vc[u], acc1);
                 }
               }
+              ap = A + (int64_t)c * lda + r0;
               for (; c < n; c += groups) {
                 const double2 av = *reinterpret_cast<const double2*>(ap);
                 acc0 = fma(av.x, vj[c], acc0);
@@ -1989,7 +2007,8 @@ void launch_sytrd_lower(int n, double* A, int64_t lda, double* d, double* e, dou
     LOBPCG_HIP(hipMemcpyAsync(d, A, sizeof(double), hipMemcpyDeviceToDevice, s));
     return;
   }
-  if (lda % 2 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0)
+  if (lda % 2 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+      lda * n * (int64_t)sizeof(double) <= INT32_MAX)
     hipLaunchKernelGGL(sytrd_lower_kernel<true>, dim3(1), dim3(kTrdThreads), 0, s, n, A, lda, d, e,
                        tau);
   else
