@@ -1207,7 +1207,19 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
       for (int q = wave; q < 2 * j; q += nwaves) {
         const double* M = q < j ? W + q * kTrdMaxN : V + (q - j) * kTrdMaxN;
         double acc = 0.0;
-        for (int r = i + 1 + lane; r < n; r += kWave) acc = fma(M[r], vj[r], acc);
+        int r = i + 1 + lane;
+        // four rows' reads in flight at a time, summed in row order
+        for (; r + 3 * kWave < n; r += 4 * kWave) {
+          double mv[4], vv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            mv[u] = M[r + u * kWave];
+            vv[u] = vj[r + u * kWave];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc = fma(mv[u], vv[u], acc);
+        }
+        for (; r < n; r += kWave) acc = fma(M[r], vj[r], acc);
         acc = wave_sum(acc);
         if (lane == 0) yv[q] = acc;
       }
@@ -1235,7 +1247,10 @@ __global__ __launch_bounds__(kTrdThreads) void sytrd_lower_kernel(int n, double*
             const int64_t step = (int64_t)groups * lda;
             const double* ap = A + (int64_t)(i + 1 + g) * lda + r0;
             int c = i + 1 + g;
-            if (kPairs && r0 + 1 < n) {
+            // An odd last row takes the pair path too: its partner row n lies in
+            // the column's padding (lda even, so lda > n), and that partner's sum
+            // goes to a slot that is never read.
+            if (kPairs) {
               // buffer loads: the lane's byte offset in one register, the
               // batch's column offsets scalar (the launcher keeps lda n 8 < 2^31)
               const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
