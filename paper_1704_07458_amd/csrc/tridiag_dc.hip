@@ -377,14 +377,32 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
   __syncthreads();
   const int K = K_s;
   for (int i = t; i < m; i += kDcThreads) {
+    // kept: the kept entries before it in (value, index) order; deflated: K
+    // plus the deflated entries before it.  Eight entries' reads in flight per
+    // step and branch-free counts (one LDS round trip per eight entries).
+    const double di = ds[i];
+    const bool dfi = defl[i] != 0;
     int rank = 0;
-    if (!defl[i]) {
-      for (int j = 0; j < m; ++j)
-        if (!defl[j] && (ds[j] < ds[i] || (ds[j] == ds[i] && j < i))) ++rank;
-    } else {
-      rank = K;
-      for (int j = 0; j < i; ++j) rank += defl[j] ? 1 : 0;
+    int j = 0;
+    for (; j + 8 <= m; j += 8) {
+      double dj[8];
+      int fj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        dj[u] = ds[j + u];
+        fj[u] = defl[j + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {  // bitwise logic: no short-circuit branches
+        const int before = (int)(j + u < i), f = (int)(fj[u] != 0);
+        const int lt = (int)(dj[u] < di), eq = (int)(dj[u] == di);
+        rank += dfi ? (f & before) : ((1 - f) & (lt | (eq & before)));
+      }
     }
+    for (; j < m; ++j)
+      rank += dfi ? ((defl[j] && j < i) ? 1 : 0)
+                  : ((!defl[j] && (ds[j] < di || (ds[j] == di && j < i))) ? 1 : 0);
+    if (dfi) rank += K;
     iw[kOrd + lo + rank] = i;
     dsort[lo + rank] = ds[i];
     if (rank < K) zsort[lo + rank] = zs[i] / znorm_s;
@@ -608,10 +626,21 @@ __global__ __launch_bounds__(kDcThreads) void dc_order_kernel(int n, int level,
   for (int i = t; i < m; i += kDcThreads) w[i] = i < K ? lamk[lo + i] : dsort[lo + i];
   __syncthreads();
   for (int i = t; i < m; i += kDcThreads) {
+    // rank in (value, index) order, eight entries' reads in flight per step
+    const double wi = w[i];
     int rank = 0;
-    for (int j = 0; j < m; ++j) rank += (w[j] < w[i] || (w[j] == w[i] && j < i)) ? 1 : 0;
+    int j = 0;
+    for (; j + 8 <= m; j += 8) {
+      double wj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) wj[u] = w[j + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        rank += (int)(wj[u] < wi) | ((int)(wj[u] == wi) & (int)(j + u < i));
+    }
+    for (; j < m; ++j) rank += (w[j] < wi || (w[j] == wi && j < i)) ? 1 : 0;
     iw[kPerm + lo + rank] = i;
-    lam[lo + rank] = w[i];
+    lam[lo + rank] = wi;
   }
 }
 
