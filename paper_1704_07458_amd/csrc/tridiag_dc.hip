@@ -304,42 +304,50 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
   if (t == 0) {
     // close pairs, in order over the survivors: |dt c s| <= tol (c^2 + s^2) is
     // |dt c s| / (c^2 + s^2) <= tol without the square root and divisions (a
-    // close pair is rare, the rotation is formed only then); the next entry is
-    // loaded before the current one is tested
+    // close pair is rare, the rotation is formed only then)
     int nrot = 0, prev = -1;
     double pd = 0.0, pz = 0.0;
-    double nd = ds[0], nz = zs[0];
-    int ndf = defl[0];
-    for (int i = 0; i < m; ++i) {
-      const double di = nd, zi = nz;
-      const int dfi = ndf;
-      if (i + 1 < m) {
-        nd = ds[i + 1];
-        nz = zs[i + 1];
-        ndf = defl[i + 1];
+    // entries are read eight at a time (one LDS round trip per eight): handling
+    // entry i writes only entries i and prev < i, never a later one
+    for (int i8 = 0; i8 < m; i8 += 8) {
+      double dch[8], zch[8];
+      int fch[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = min(i8 + u, m - 1);
+        dch[u] = ds[q];
+        zch[u] = zs[q];
+        fch[u] = defl[q];
       }
-      if (dfi) continue;
-      if (prev >= 0 && fabs((di - pd) * zi * pz) <= tol * fma(zi, zi, pz * pz)) {
-        const double tau = hypot(zi, pz);
-        const double cc = zi / tau, ss = -pz / tau;
-        const double dnew = pd * ss * ss + di * cc * cc;
-        zs[i] = tau;
-        zs[prev] = 0.0;
-        ds[prev] = pd * cc * cc + di * ss * ss;
-        ds[i] = dnew;
-        defl[prev] = 1;
-        iw[kRp + lo + nrot] = prev;
-        iw[kRi + lo + nrot] = i;
-        rw[lo + nrot] = cc;
-        rw[kDcMaxN + lo + nrot] = ss;
-        ++nrot;
-        pd = dnew;
-        pz = tau;
-      } else {
-        pd = di;
-        pz = zi;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i8 + u;
+        if (i >= m) break;
+        const double di = dch[u], zi = zch[u];
+        const int dfi = fch[u];
+        if (dfi) continue;
+        if (prev >= 0 && fabs((di - pd) * zi * pz) <= tol * fma(zi, zi, pz * pz)) {
+          const double tau = hypot(zi, pz);
+          const double cc = zi / tau, ss = -pz / tau;
+          const double dnew = pd * ss * ss + di * cc * cc;
+          zs[i] = tau;
+          zs[prev] = 0.0;
+          ds[prev] = pd * cc * cc + di * ss * ss;
+          ds[i] = dnew;
+          defl[prev] = 1;
+          iw[kRp + lo + nrot] = prev;
+          iw[kRi + lo + nrot] = i;
+          rw[lo + nrot] = cc;
+          rw[kDcMaxN + lo + nrot] = ss;
+          ++nrot;
+          pd = dnew;
+          pz = tau;
+        } else {
+          pd = di;
+          pz = zi;
+        }
+        prev = i;
       }
-      prev = i;
     }
     iw[kNrot + node] = nrot;
   }
