@@ -619,6 +619,128 @@ __global__ __launch_bounds__(256, 2) void update_kernel(int64_t n, int K, int N,
     }
 }
 
+// The FP64 update with S fed by LDS DMA (global_load_lds_dwordx4): the S tile
+// of a stage (128 rows x kKB) is 16 chunks of 8 rows, one 1 KB DMA each, and
+// goes into one of three LDS buffers two stages ahead, with no staging
+// registers and no LDS store instructions; C is loaded through registers one
+// stage ahead as in update_kernel.  In a chunk, lane L holds row 8j + L/8 and
+// the stage's k pair (L & 7) ^ (row & 7) (the XOR keeps the MFMA operand reads
+// spread over the LDS banks); pairs past K read the last pair instead (C is
+// zero there).  Needs K even and >= 2, lds even and S 16-byte aligned (the
+// launcher checks).  Per iteration the C loads of stage st + 1 are issued
+// before the DMA of stage st + 2, so the wait the compiler places for those C
+// registers leaves only the newer DMA outstanding: stage st + 1's S, issued a
+// stage earlier, has landed before the barrier.  Same products, same order
+// of accumulation as update_kernel: the results are identical.
+template <int TN, int WR>
+__global__ __launch_bounds__(256, 2) void update_dma_kernel(int64_t n, int K, int N,
+                                                            const double* __restrict__ S,
+                                                            int64_t lds,
+                                                            const double* __restrict__ C,
+                                                            int64_t ldc, double alpha, int beta1,
+                                                            double* __restrict__ Y, int64_t ldy,
+                                                            int tiles_n) {
+  using acc_t = v4d;
+  typedef __attribute__((address_space(3))) void lds_void;
+  __shared__ __align__(16) double Sd[3][kUpdTM * kKB];
+  constexpr int WC = 4 / WR, RW = kUpdTM / WR, CW = TN / WC;
+  constexpr int FA = RW / 16, FB = CW / 16;
+  static_assert(FA * 16 == RW && FB * 16 == CW, "16-row/column blocks");
+  static_assert(kKB == 16 && kUpdTM == 128, "8-row chunks of 16 doubles, four per wave");
+  __shared__ double Cs[2][TN][kKB + kUpdPad];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t tr = lb / tiles_n;
+  const int tc = lb % tiles_n;
+  const int tid = threadIdx.x;
+  const int wave = uniform(tid / kWave);
+  const int lane = tid % kWave;
+  const int wr = wave / WC, wc = wave % WC;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rows_valid = (int)(n - tr * kUpdTM < kUpdTM ? n - tr * kUpdTM : kUpdTM);
+  const int cols_valid = N - tc * TN < TN ? N - tc * TN : TN;
+  auto dma_s = [&](int buf, int kb) {
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = wave + 4 * jj;
+      const int row = 8 * j + (lane >> 3);
+      const int p = (lane & 7) ^ (row & 7);
+      const int r = row < rows_valid ? row : rows_valid - 1;
+      const int k0 = kb + 2 * p + 1 < K ? kb + 2 * p : K - 2;
+      __builtin_amdgcn_global_load_lds(S + (tr * kUpdTM + r) * lds + k0,
+                                       (lds_void*)&Sd[buf][j * 8 * kKB], 16, 0, 0);
+    }
+  };
+  const int kk = tid % kKB, q0 = tid / kKB;
+  constexpr int kPerC = TN / 16;
+  const double* cbase = C + (int64_t)(tc * TN + q0) * ldc + kk;
+  const int64_t cstep = 16 * ldc;
+  double gc[kPerC];
+  auto gload_c = [&](int kb) {
+    const bool kok = kb + kk < K;
+#pragma unroll
+    for (int i = 0; i < kPerC; ++i) {
+      const int q = q0 + 16 * i;
+      gc[i] = (kok && q < cols_valid) ? cbase[i * cstep + kb] : 0.0;
+    }
+  };
+  auto sstore_c = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < kPerC; ++i) Cs[buf][q0 + 16 * i][kk] = gc[i];
+  };
+  acc_t acc[FA][FB];
+#pragma unroll
+  for (int a = 0; a < FA; ++a)
+#pragma unroll
+    for (int b = 0; b < FB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  const int nst = (K + kKB - 1) / kKB;
+  dma_s(0, 0);
+  gload_c(0);
+  if (nst > 1) dma_s(1, kKB);
+  sstore_c(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const bool more = st + 1 < nst;
+    if (more) gload_c((st + 1) * kKB);
+    if (st + 2 < nst) dma_s((st + 2) % 3, (st + 2) * kKB);
+    const double* Sb = Sd[st % 3];
+    const int cb = st & 1;
+#pragma unroll
+    for (int s4 = 0; s4 < kKB / 4; ++s4) {
+      const int k = 4 * s4 + lk;
+      double a[FA], b[FB];
+#pragma unroll
+      for (int f = 0; f < FA; ++f) {
+        const int row = wr * RW + f * 16 + li;
+        a[f] = Sb[row * kKB + 2 * ((k >> 1) ^ (row & 7)) + (k & 1)];
+      }
+#pragma unroll
+      for (int f = 0; f < FB; ++f) b[f] = Cs[cb][wc * CW + f * 16 + li][k];
+#pragma unroll
+      for (int fa = 0; fa < FA; ++fa)
+#pragma unroll
+        for (int fb = 0; fb < FB; ++fb) acc[fa][fb] = Mfma<double>::mma(a[fa], b[fb], acc[fa][fb]);
+    }
+    if (more) sstore_c(cb ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int fa = 0; fa < FA; ++fa)
+#pragma unroll
+    for (int fb = 0; fb < FB; ++fb) {
+      const int j = tc * TN + wc * CW + fb * 16 + li;
+      if (j >= N) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = tr * kUpdTM + wr * RW + fa * 16 + Mfma<double>::row(lk, q);
+        if (r < n) {
+          double v = alpha * acc[fa][fb][q];
+          if (beta1) v += Y[r * ldy + j];
+          Y[r * ldy + j] = v;
+        }
+      }
+    }
+}
+
 // ------------------------------------------------------------------ residual
 // Grid: x = row blocks (kResRows rows each), y = column chunks of 64.
 // Each thread owns one column; 4 waves stride over the block's rows.
@@ -1771,7 +1893,24 @@ void launch_update(int64_t n, int K, int N, const T* S, int64_t lds, const doubl
   const int64_t tiles_r = (n + kUpdTM - 1) / kUpdTM;
   const int64_t grid = tiles_r * tiles_n;
   LOBPCG_CHECK(grid < (int64_t)1 << 31, LOBPCG_ERR_ARG, "update grid too large");
-  // 2 x 2 waves for 128- and 64-wide tiles; 4 x 1 (32 rows x 112 columns each) for 112
+  // 2 x 2 waves for 128- and 64-wide tiles; 4 x 1 (32 rows x 112 columns each) for 112.
+  // FP64 with 112- or 64-wide tiles takes the LDS-DMA kernel where its layout holds.
+  if constexpr (sizeof(T) == 8) {
+    const bool dma = (tn == 112 || tn == 64) && K >= 2 && K % 2 == 0 && lds % 2 == 0 &&
+                     reinterpret_cast<uintptr_t>(S) % 16 == 0;
+    if (dma) {
+      if (tn == 112)
+        hipLaunchKernelGGL((update_dma_kernel<112, 4>), dim3((unsigned)grid), dim3(256), 0, s, n,
+                           K, N, (const double*)S, lds, C, ldc, alpha, beta != 0.0 ? 1 : 0,
+                           (double*)Y, ldy, tiles_n);
+      else
+        hipLaunchKernelGGL((update_dma_kernel<64, 2>), dim3((unsigned)grid), dim3(256), 0, s, n,
+                           K, N, (const double*)S, lds, C, ldc, alpha, beta != 0.0 ? 1 : 0,
+                           (double*)Y, ldy, tiles_n);
+      LOBPCG_HIP(hipGetLastError());
+      return;
+    }
+  }
   if (tn == 64)
     hipLaunchKernelGGL((update_kernel<T, 64, 2>), dim3((unsigned)grid), dim3(256), 0, s, n, K, N,
                        S, lds, C, ldc, (T)alpha, beta != 0.0 ? 1 : 0, Y, ldy, tiles_n);

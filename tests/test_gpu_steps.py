@@ -148,9 +148,10 @@ def test_gram_fp32_accumulation(lib, n, m, p):
     assert np.all(np.abs(G - ref) <= bound)
 
 
-# column tiles: 64 (22, 3), 112 (220, 65, and 110 = n_x of the bench), 128 (128)
+# column tiles: 64 (22, 3, 40, 5), 112 (220, 65, and 110 = n_x of the bench), 128 (128); even K
+# with 64- and 112-wide tiles takes the LDS-DMA kernel (K = 2 its smallest), odd K the other
 @pytest.mark.parametrize("n,K,N", [(1000, 33, 22), (4097, 330, 220), (70, 5, 3), (2000, 130, 65),
-                                   (5001, 330, 110), (3000, 200, 128)])
+                                   (5001, 330, 110), (3000, 200, 128), (1500, 64, 40), (300, 2, 5)])
 def test_update_fp64(lib, n, K, N):
     torch = _torch()
     from paper_1704_07458_amd import binding as B
