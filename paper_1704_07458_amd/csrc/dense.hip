@@ -191,6 +191,10 @@ void Dense::join_p() {
   p_pending_ = false;
 }
 
+void Dense::extend_p() {
+  if (p_pending_) LOBPCG_HIP(hipEventRecord(ev_p_, s2_));
+}
+
 // Mt = (Z_1(:, nc:nx)^T Z_1perp)^T = Z_1perp^T Z_1(:, nc:nx)   (m x na), or its
 // literal reading (the first n_x - n_c rows of Z_1perp, transposed).
 static void p_operand(const double* Z, int64_t ld, int ns, int nx, int nc, bool literal_lq,

@@ -52,6 +52,11 @@ class Dense {
 
   // Orders the main stream after the deferred P block (no-op when none).
   void join_p();
+  // The deferred P block's stream, while one is pending (else nullptr): work
+  // queued there follows the P block, and extend_p() makes join_p() wait for
+  // it too.
+  hipStream_t p_stream() const { return p_pending_ ? s2_ : nullptr; }
+  void extend_p();
 
   // SVQB transform of Algorithms 4 / 6 from the Gram matrix G = U^T M U (nu x nu,
   // column-major, ldg; overwritten): Tu = D Z(:, J) Theta(J)^-1/2 written to Tu

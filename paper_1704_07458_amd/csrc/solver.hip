@@ -460,9 +460,15 @@ static bool update_uses_library(bool fp32, int K, int N) {
 
 template <typename T>
 void Solver::update(int64_t n, int K, int N, const T* S, int64_t lds, const double* C,
-                    int64_t ldc, double alpha, double beta, T* Y, int64_t ldy) {
+                    int64_t ldc, double alpha, double beta, T* Y, int64_t ldy,
+                    hipStream_t stream) {
   if (N == 0) return;
-  const int tok = timer_.start(s_);
+  // another stream takes the hand-written kernel only (the library route's
+  // handle and FP32 copy of C belong to the main stream)
+  LOBPCG_CHECK(!stream || !update_uses_library(sizeof(T) == 4, K, N), LOBPCG_ERR_ARG,
+               "update: the library route runs on the main stream");
+  const hipStream_t us = stream ? stream : s_;
+  const int tok = timer_.start(us);
   if (update_uses_library(sizeof(T) == 4, K, N)) {
     // Y^T (N x n) = C^T (N x K) S^T (K x n) in column-major terms: S, Y row-major
     rocblas_handle h = dense_->handle();
@@ -482,9 +488,9 @@ void Solver::update(int64_t n, int K, int N, const T* S, int64_t lds, const doub
                    LOBPCG_ERR_HIP, "rocblas_dgemm (basis update)");
     }
   } else {
-    launch_update<T>(n, K, N, S, lds, C, ldc, alpha, beta, Y, ldy, s_);
+    launch_update<T>(n, K, N, S, lds, C, ldc, alpha, beta, Y, ldy, us);
   }
-  timer_.stop(tok, 2, 2.0 * n * K * N, s_);
+  timer_.stop(tok, 2, 2.0 * n * K * N, us);
 }
 
 // Algorithm 5 (orthoDrop) with Algorithms 4 (svqb) and 6 (svqbDrop), metric
@@ -668,6 +674,8 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     const T* MV = B ? BXP : Sc;
     const int64_t ldmv = B ? ldBXP : ldS;
     if (use_ortho) {
+      phase_mark(5);
+      dense_->join_p();  // P, updated on the second stream, is read from here on
       phase_mark(2);
       nw = ortho_drop<T>(b, B, W, ldS, nw, Sc, ldS, MV, ldmv, nv, tau_ortho, eps, info);
     }
@@ -678,6 +686,8 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
       phase_mark(0);
       spmm<T>(A, W, ldS, AWc, ldAW, nw);
       if (B) spmm<T>(*B, W, ldS, BW, ldX, nw);
+      phase_mark(5);
+      dense_->join_p();  // the Gram reads P, updated on the second stream
       // Gram columns of W in S^T A S and S^T B S; the rest from eqs. (12)-(14).
       phase_mark(3);
       gram<T>(n, ns, use_ortho ? nw : 2 * nw, nw, Sc, ldS, AWc, ldAW, B ? BW : W,
@@ -775,14 +785,26 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     // host waits for this copy only, the P update runs on meanwhile.
     LOBPCG_HIP(hipMemcpyAsync(hbuf_, nc_.get(), sizeof(int32_t) * 3, hipMemcpyDeviceToHost, s_));
     LOBPCG_HIP(hipEventRecord(ev_nc_, s_));
-    // the wait for Algorithm 7's P block (second stream) is Rayleigh-Ritz time
-    phase_mark(4);
-    dense_->join_p();
-    phase_mark(5);
-    if (npn > 0) {
-      update<T>(n, ns, npn, Sc, ldS, C + (int64_t)nx * ldc, ldc, 1.0, 0.0, Sn + nx, ldS);
-      if (impl) update<T>(n, ns, npn, ASo, ldS, C + (int64_t)nx * ldc, ldc, 1.0, 0.0, AX + nx, ldS);
-      if (B) spmm<T>(*B, Sn + nx, ldS, BXP + nx, ldBXP, npn);
+    // P = S C_p.  FP64 with the hand-written kernel, B = I and A P not updated:
+    // queued behind Algorithm 7's P block on the second stream, so that it runs
+    // beside the next step's A W; that step joins before its first read of P
+    // (orthoDrop or the Gram).  Otherwise the main stream waits for the P block
+    // (Rayleigh-Ritz time) and updates.
+    const hipStream_t ps = dense_->p_stream();
+    if (npn > 0 && ps && sizeof(T) == 8 && !impl && !B &&
+        !update_uses_library(false, ns, npn)) {
+      update<T>(n, ns, npn, Sc, ldS, C + (int64_t)nx * ldc, ldc, 1.0, 0.0, Sn + nx, ldS, ps);
+      dense_->extend_p();
+    } else {
+      phase_mark(4);
+      dense_->join_p();
+      phase_mark(5);
+      if (npn > 0) {
+        update<T>(n, ns, npn, Sc, ldS, C + (int64_t)nx * ldc, ldc, 1.0, 0.0, Sn + nx, ldS);
+        if (impl)
+          update<T>(n, ns, npn, ASo, ldS, C + (int64_t)nx * ldc, ldc, 1.0, 0.0, AX + nx, ldS);
+        if (B) spmm<T>(*B, Sn + nx, ldS, BXP + nx, ldBXP, npn);
+      }
     }
     np = npn;
     LOBPCG_HIP(hipEventSynchronize(ev_nc_));
@@ -817,6 +839,7 @@ int Solver::run(Blocks<T>& b, const DevCsr& A, const DevCsr* B, double tol, int 
     }
     if (nx - nc == 0 && np == 0) throw Error(LOBPCG_ERR_BREAKDOWN, "search space collapsed");
   }
+  dense_->join_p();  // a P update still queued on the second stream
   } catch (const Error& e) {
     // A breakdown or a non-finite value in the FP32 phase of the precision
     // split does not end the solve: the FP64 phase takes over, from the last

@@ -80,7 +80,7 @@ class Solver {
             int mirror_rows);
   template <typename T>
   void update(int64_t n, int K, int N, const T* S, int64_t lds, const double* C, int64_t ldc,
-              double alpha, double beta, T* Y, int64_t ldy);
+              double alpha, double beta, T* Y, int64_t ldy, hipStream_t stream = nullptr);
   void phase_mark(int phase);
   void sync();
   // ||A||^(Omega), ||B||^(Omega) of section 4.3 from the seeded sketch.
