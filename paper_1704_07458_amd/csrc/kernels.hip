@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(int64_t n,
 // r, for each column j: res = (A X)(r, j) - theta_j X(r, j), W(r, n_x-1-j) =
 // res * dinv[r] (res without dinv; the reversed W store of section 5.1),
 // optionally AX(r, j), and the FP64 sums of res^2 and X(r, j)^2 over the
-// workgroup's rows into part_r / part_x [block][n_x] (fixed order: each wave
+// workgroup's rows into part_r / part_x [n_x][block] (fixed order: each wave
 // its rows in order, then the four waves in order).  X(r, :) is the row the
 // diagonal entry gathered (loaded again for a row that stores no diagonal).
 template <typename T, int NC>
@@ -263,8 +263,8 @@ __global__ __launch_bounds__(256) void spmm_residual_kernel(
       const int t = lane + kWave * j;
       const double a = ((sr[0][t] + sr[1][t]) + sr[2][t]) + sr[3][t];
       const double b = ((sx[0][t] + sx[1][t]) + sx[2][t]) + sx[3][t];
-      part_r[lb * nx + col0 + kWave * j] = a;
-      part_x[lb * nx + col0 + kWave * j] = b;
+      part_r[(int64_t)(col0 + kWave * j) * gridDim.x + lb] = a;
+      part_x[(int64_t)(col0 + kWave * j) * gridDim.x + lb] = b;
     }
   }
 }
@@ -778,17 +778,21 @@ __global__ __launch_bounds__(256) void residual_kernel(
   if (wave == 0 && ok) {
     const double a = ((sr[0][lane] + sr[1][lane]) + sr[2][lane]) + sr[3][lane];
     const double b = ((sx[0][lane] + sx[1][lane]) + sx[2][lane]) + sx[3][lane];
-    part_r[(int64_t)lb * nx + j] = a;
-    part_x[(int64_t)lb * nx + j] = b;
+    part_r[(int64_t)j * gridDim.x + lb] = a;
+    part_x[(int64_t)j * gridDim.x + lb] = b;
   }
 }
 
-// Deterministic sum of column j's nblocks partials: one workgroup per column,
-// each thread sums a fixed strided subset, then a fixed-order tree in LDS.
+// Deterministic sum of column j's nblocks partials (stored column after
+// column: part[j * nblocks + block], so a column's partials are contiguous):
+// one workgroup per column, each thread sums a fixed strided subset, then a
+// fixed-order tree in LDS.
 __device__ __forceinline__ double block_sum_column(const double* __restrict__ part, int ncols,
                                                    int nblocks, int j, double* sbuf) {
+  (void)ncols;
   double a = 0.0;
-  for (int t = threadIdx.x; t < nblocks; t += blockDim.x) a += part[(int64_t)t * ncols + j];
+  const double* col = part + (int64_t)j * nblocks;
+  for (int t = threadIdx.x; t < nblocks; t += blockDim.x) a += col[t];
   sbuf[threadIdx.x] = a;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -859,7 +863,7 @@ __global__ __launch_bounds__(256) void colsq_kernel(int64_t n, int ncols, const 
   sq[wave][lane] = acc;
   __syncthreads();
   if (wave == 0 && j < ncols)
-    part[(int64_t)lb * ncols + j] = ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane];
+    part[(int64_t)j * gridDim.x + lb] = ((sq[0][lane] + sq[1][lane]) + sq[2][lane]) + sq[3][lane];
 }
 
 // Grid: one workgroup per column.
