@@ -172,6 +172,30 @@ def test_update_fp64(lib, n, K, N):
     assert np.all(np.abs(Y0.cpu().numpy() - ref2) <= bound + 2 * U64 * np.abs(Y0h))
 
 
+# the FP64 update takes the LDS-DMA kernel for even K, an even row stride and a
+# 16-byte-aligned S, and the register-staged kernel otherwise: each route, same bound
+@pytest.mark.parametrize("route", ["dma", "odd_stride", "misaligned", "odd_k"])
+def test_update_fp64_routes(lib, route):
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    n, N = 2049, 110
+    K = 97 if route == "odd_k" else 96
+    width = {"dma": K + 2, "odd_stride": K + 1, "misaligned": K + 2, "odd_k": K + 1}[route]
+    off = 1 if route == "misaligned" else 0
+    rng = np.random.default_rng(11)
+    Sh = rng.standard_normal((n, width))
+    Ch = rng.standard_normal((K, N))
+    S = torch.from_numpy(Sh).cuda()[:, off:off + K]
+    takes_dma = K % 2 == 0 and S.stride(0) % 2 == 0 and S.data_ptr() % 16 == 0
+    assert takes_dma == (route == "dma")
+    Y = B.update(S, torch.from_numpy(Ch).cuda()).cpu().numpy()
+    Sk = Sh[:, off:off + K]
+    ref = Sk @ Ch
+    bound = 2 * gamma(K, U64) * (np.abs(Sk) @ np.abs(Ch))
+    assert np.all(np.abs(Y - ref) <= bound)
+
+
 @pytest.mark.parametrize("n,K,N", [(3000, 96, 70), (4001, 330, 110)])
 def test_update_fp32(lib, n, K, N):
     torch = _torch()
