@@ -783,36 +783,66 @@ __global__ __launch_bounds__(256) void residual_kernel(
   }
 }
 
-// Deterministic sum of column j's nblocks partials (stored column after
-// column: part[j * nblocks + block], so a column's partials are contiguous):
-// one workgroup per column, each thread sums a fixed strided subset, then a
-// fixed-order tree in LDS.
-__device__ __forceinline__ double block_sum_column(const double* __restrict__ part, int ncols,
-                                                   int nblocks, int j, double* sbuf) {
-  (void)ncols;
-  double a = 0.0;
-  const double* col = part + (int64_t)j * nblocks;
-  for (int t = threadIdx.x; t < nblocks; t += blockDim.x) a += col[t];
-  sbuf[threadIdx.x] = a;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sbuf[threadIdx.x] += sbuf[threadIdx.x + s];
+// Deterministic sums of column j's nblocks partials in one or two arrays
+// (stored column after column: part[j * nblocks + block], so a column's
+// partials are contiguous): one workgroup per column, each thread sums its
+// fixed strided subset in order, then a fixed-order tree in LDS.  The loads
+// go out in batches of kSumBatch per array before their adds (in the same
+// order as one at a time, so the sums are the same bits): the partials of a
+// 262144-row fused residual are 8192 per column, 32 per thread, and one round
+// trip per add would make the kernel a chain of dependent loads.
+constexpr int kSumBatch = 16;
+
+template <int NA>
+__device__ __forceinline__ void block_sum_columns(const double* const (&part)[NA], int nblocks,
+                                                  int j, double* sbuf, double (&out)[NA]) {
+  const int nt = blockDim.x;
+  const double* col[NA];
+  double a[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    col[q] = part[q] + (int64_t)j * nblocks;
+    a[q] = 0.0;
+  }
+  int t = threadIdx.x;
+  for (; t + (kSumBatch - 1) * nt < nblocks; t += kSumBatch * nt) {
+    double v[NA][kSumBatch];
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+#pragma unroll
+      for (int u = 0; u < kSumBatch; ++u) v[q][u] = col[q][t + u * nt];
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+#pragma unroll
+      for (int u = 0; u < kSumBatch; ++u) a[q] += v[q][u];
+  }
+  for (; t < nblocks; t += nt)
+#pragma unroll
+    for (int q = 0; q < NA; ++q) a[q] += col[q][t];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    sbuf[threadIdx.x] = a[q];
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) sbuf[threadIdx.x] += sbuf[threadIdx.x + s];
+      __syncthreads();
+    }
+    out[q] = sbuf[0];
     __syncthreads();
   }
-  const double r = sbuf[0];
-  __syncthreads();
-  return r;
 }
 
 // Grid: one workgroup per column.  rho_j of eq. (9).
 __global__ __launch_bounds__(256) void residual_rho_kernel(
     int nx, int nblocks, const double* __restrict__ part_r, const double* __restrict__ part_x,
     const double* __restrict__ theta, double normA, double normB, double* __restrict__ rho) {
+  (void)nx;
   __shared__ double sbuf[256];
   const int j = blockIdx.x;
-  const double a = block_sum_column(part_r, nx, nblocks, j, sbuf);
-  const double b = block_sum_column(part_x, nx, nblocks, j, sbuf);
-  if (threadIdx.x == 0) rho[j] = sqrt(a) / ((normA + fabs(theta[j]) * normB) * sqrt(b));
+  const double* const parts[2] = {part_r, part_x};
+  double ab[2];
+  block_sum_columns<2>(parts, nblocks, j, sbuf, ab);
+  if (threadIdx.x == 0) rho[j] = sqrt(ab[0]) / ((normA + fabs(theta[j]) * normB) * sqrt(ab[1]));
 }
 
 // One workgroup: the leading run n_c[0] of rho_j <= tol and a non-finite flag n_c[1].
@@ -870,10 +900,13 @@ __global__ __launch_bounds__(256) void colsq_kernel(int64_t n, int ncols, const 
 __global__ __launch_bounds__(256) void colsq_finish_kernel(int ncols, int nblocks,
                                                            const double* __restrict__ part,
                                                            double* __restrict__ out) {
+  (void)ncols;
   __shared__ double sbuf[256];
   const int j = blockIdx.x;
-  const double a = block_sum_column(part, ncols, nblocks, j, sbuf);
-  if (threadIdx.x == 0) out[j] = a;
+  const double* const parts[1] = {part};
+  double a[1];
+  block_sum_columns<1>(parts, nblocks, j, sbuf, a);
+  if (threadIdx.x == 0) out[j] = a[0];
 }
 
 // ------------------------------------------------------------------ Jacobi
