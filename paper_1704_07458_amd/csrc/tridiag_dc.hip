@@ -52,52 +52,16 @@ __device__ __forceinline__ void dc_range(int n, int level, int idx, int& lo, int
 
 __device__ __forceinline__ double dc_wave_sum(double v) { return wave64_sum(v); }
 
-// ---------------------------------------------------------------- input check
-// One workgroup.  A non-finite d or e (a non-finite projected matrix) would
-// make the merges' rank computations and orderings undefined; such an input is
-// replaced by the zero tridiagonal (every later kernel then sees finite values)
-// and reported through *fail = 2.
-__global__ __launch_bounds__(256) void dc_sanitize_kernel(int n, double* d, double* e, int* fail) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  int mine = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    if (!isfinite(d[i])) mine = 1;
-    if (i < n - 1 && !isfinite(e[i])) mine = 1;
-  }
-  if (mine) atomicOr(&bad, 1);
-  __syncthreads();
-  if (!bad) return;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    d[i] = 0.0;
-    if (i < n - 1) e[i] = 0.0;
-  }
-  if (threadIdx.x == 0) atomicMax(fail, 2);
-}
-
-// ---------------------------------------------------------------- tear
-// d[mid - 1] and d[mid] lose |e[mid - 1]| for every internal node (distinct
-// indices: children are at least kDcLeaf / 2 rows apart from their parent's mid).
-__global__ void dc_tear_kernel(int n, int depth, const double* __restrict__ e, double* d) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int level = 0, base = 0;
-  while (level < depth && t >= base + (1 << level)) {
-    base += 1 << level;
-    ++level;
-  }
-  if (level >= depth) return;
-  int lo, hi;
-  dc_range(n, level, t - base, lo, hi);
-  const int mid = (lo + hi) / 2;
-  const double b = fabs(e[mid - 1]);
-  d[mid - 1] -= b;
-  d[mid] -= b;
-}
-
 // ---------------------------------------------------------------- leaves
 // One wave per leaf: the implicit QL algorithm with Wilkinson's shift on the
 // leaf's tridiagonal block (the Bowdler-Martin-Reinsch-Wilkinson scheme).
+// The leaf first takes the tears of the merges above it: every leaf boundary
+// inside [0, n) is the split point mid of one merge, which removes |e[mid - 1]|
+// from d[mid - 1] and d[mid] (so each d entry loses at most one such term).
+// A leaf whose entries (d, its e and the two e at its boundaries) are not all
+// finite is solved as the zero block instead, writes zeros over its own e and
+// over a non-finite boundary e, and raises *fail to 2: every value the merges
+// read is then finite (their ranks and orderings stay defined).
 // Every lane runs the scalar recurrence on (d, e) in LDS with identical
 // values; lane k applies each plane rotation to row k of the eigenvector
 // block.  An off-diagonal e_i is negligible once |e_i| <= eps (|d_i| +
@@ -113,9 +77,8 @@ __device__ __forceinline__ double dc_lane_get(double v, int i) {
   return __hiloint2double(hi32, lo32);
 }
 
-__global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const double* __restrict__ d,
-                                                         const double* __restrict__ e,
-                                                         double* __restrict__ lam,
+__global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const double* d,
+                                                         double* e, double* lam,
                                                          double* __restrict__ Z, int64_t ldz,
                                                          int* __restrict__ fail) {
   __shared__ double V[kDcLeaf][kDcLeaf + 1];  // V[row][col]
@@ -127,8 +90,26 @@ __global__ __launch_bounds__(kWave) void dc_leaf_kernel(int n, int depth, const 
   dc_range(n, depth, blockIdx.x, lo, hi);
   const int m = hi - lo;
   for (int q = lane; q < kDcLeaf * kDcLeaf; q += kWave) V[q / kDcLeaf][q % kDcLeaf] = (q / kDcLeaf == q % kDcLeaf) ? 1.0 : 0.0;
-  double dv = lane < m ? d[lo + lane] : 0.0;
-  double ev = lane < m - 1 ? e[lo + lane] : 0.0;
+  const double din = lane < m ? d[lo + lane] : 0.0;
+  const double ein = lane < m - 1 ? e[lo + lane] : 0.0;
+  const double el = lo > 0 ? e[lo - 1] : 0.0;
+  const double er = hi < n ? e[hi - 1] : 0.0;
+  const bool bad = __ballot(!isfinite(din) || !isfinite(ein)) != 0 || !isfinite(el) ||
+                   !isfinite(er);
+  double dv = 0.0, ev = 0.0;
+  if (!bad) {
+    dv = din;
+    ev = ein;
+    if (lane == 0 && lo > 0) dv -= fabs(el);
+    if (lane == m - 1 && hi < n) dv -= fabs(er);
+  } else {
+    if (lane < m - 1) e[lo + lane] = 0.0;
+    if (lane == 0) {
+      if (!isfinite(el)) e[lo - 1] = 0.0;
+      if (!isfinite(er)) e[hi - 1] = 0.0;
+      atomicMax(fail, 2);
+    }
+  }
   // scale by a power of two (exact) so that every entry is below 1 in magnitude
   double amax = fmax(fabs(dv), fabs(ev));
   for (int off = kWave / 2; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, kWave));
@@ -421,12 +402,10 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
 // ---------------------------------------------------------------- merge: stage
 // One workgroup per (node, position k): Qs[lo:hi, lo + k] = column src[k] of
 // diag(Q1, Q2) (the other child's rows zero).
-__global__ __launch_bounds__(kDcThreads) void dc_stage_kernel(int n, int level, int mmax,
-                                                              const int* __restrict__ iw,
-                                                              const double* __restrict__ Z,
-                                                              double* __restrict__ Qs,
-                                                              int64_t ldz) {
-  const int node = blockIdx.x / mmax, k = blockIdx.x % mmax;
+__device__ __forceinline__ void dc_stage(int bid, int n, int level, int mmax,
+                                         const int* __restrict__ iw, const double* __restrict__ Z,
+                                         double* __restrict__ Qs, int64_t ldz) {
+  const int node = bid / mmax, k = bid % mmax;
   int lo, hi;
   dc_range(n, level, node, lo, hi);
   const int m = hi - lo, n1 = (lo + hi) / 2 - lo;
@@ -443,13 +422,12 @@ __global__ __launch_bounds__(kDcThreads) void dc_stage_kernel(int n, int level, 
 
 // ---------------------------------------------------------------- merge: rotate
 // One thread per (node, row): the deflation rotations, in order, on the row.
-__global__ __launch_bounds__(kDcThreads) void dc_rotate_kernel(int n, int level, int rblocks,
-                                                               const int* __restrict__ iw,
-                                                               const double* __restrict__ rw,
-                                                               double* __restrict__ Qs,
-                                                               int64_t ldz) {
-  const int node = blockIdx.x / rblocks;
-  const int r = (blockIdx.x % rblocks) * kDcThreads + threadIdx.x;
+__device__ __forceinline__ void dc_rotate(int bid, int n, int level, int rblocks,
+                                          const int* __restrict__ iw,
+                                          const double* __restrict__ rw, double* __restrict__ Qs,
+                                          int64_t ldz) {
+  const int node = bid / rblocks;
+  const int r = (bid % rblocks) * kDcThreads + threadIdx.x;
   int lo, hi;
   dc_range(n, level, node, lo, hi);
   if (r >= hi - lo) return;
@@ -471,14 +449,16 @@ __global__ __launch_bounds__(kDcThreads) void dc_rotate_kernel(int n, int level,
 // The root is located in the variable tau shifted to the nearer pole, by Newton
 // steps on -tau f(tau) safeguarded by the bracketing interval.
 // lamk[lo + j] = root j;  Dl[lo + i, lo + j] = d_i - root_j.
-__global__ __launch_bounds__(kDcThreads) void dc_secular_kernel(
-    int n, int level, int rblocks, const double* __restrict__ dsort,
-    const double* __restrict__ zsort, const int* __restrict__ iw,
-    const double* __restrict__ rhoK, double* __restrict__ lamk, double* __restrict__ Dl,
-    int64_t ldz) {
-  const int node = blockIdx.x / rblocks;
+__device__ __forceinline__ void dc_secular(int bid, int n, int level, int rblocks,
+                                           const double* __restrict__ dsort,
+                                           const double* __restrict__ zsort,
+                                           const int* __restrict__ iw,
+                                           const double* __restrict__ rhoK,
+                                           double* __restrict__ lamk, double* __restrict__ Dl,
+                                           int64_t ldz) {
+  const int node = bid / rblocks;
   const int lane = threadIdx.x % kWave;
-  const int j = (blockIdx.x % rblocks) * (kDcThreads / kWave) + threadIdx.x / kWave;
+  const int j = (bid % rblocks) * (kDcThreads / kWave) + threadIdx.x / kWave;
   int lo, hi;
   dc_range(n, level, node, lo, hi);
   const int K = iw[node];
@@ -546,16 +526,15 @@ __global__ __launch_bounds__(kDcThreads) void dc_secular_kernel(
 // ---------------------------------------------------------------- merge: zhat
 // One thread per (node, i < K): z recomputed from the roots (Gu-Eisenstat),
 // zhat_i^2 = (root_i - d_i) / rho  prod_{j != i} (root_j - d_i) / (d_j - d_i).
-__global__ __launch_bounds__(kDcThreads) void dc_zhat_kernel(int n, int level, int rblocks,
-                                                             const double* __restrict__ dsort,
-                                                             const double* __restrict__ zsort,
-                                                             const int* __restrict__ iw,
-                                                             const double* __restrict__ rhoK,
-                                                             const double* __restrict__ Dl,
-                                                             double* __restrict__ zh,
-                                                             int64_t ldz) {
-  const int node = blockIdx.x / rblocks;
-  const int i = (blockIdx.x % rblocks) * kDcThreads + threadIdx.x;
+__device__ __forceinline__ void dc_zhat(int bid, int n, int level, int rblocks,
+                                        const double* __restrict__ dsort,
+                                        const double* __restrict__ zsort,
+                                        const int* __restrict__ iw,
+                                        const double* __restrict__ rhoK,
+                                        const double* __restrict__ Dl, double* __restrict__ zh,
+                                        int64_t ldz) {
+  const int node = bid / rblocks;
+  const int i = (bid % rblocks) * kDcThreads + threadIdx.x;
   int lo, hi;
   dc_range(n, level, node, lo, hi);
   const int K = iw[node];
@@ -619,14 +598,13 @@ __global__ __launch_bounds__(kWave) void dc_vectors_kernel(int n, int level, int
 // ---------------------------------------------------------------- merge: order
 // One workgroup per node: ascending order of the node's eigenvalues (kept
 // roots, then deflated d), lam[lo:hi) and the slot of each.
-__global__ __launch_bounds__(kDcThreads) void dc_order_kernel(int n, int level,
-                                                              int* __restrict__ iw,
-                                                              const double* __restrict__ lamk,
-                                                              const double* __restrict__ dsort,
-                                                              double* __restrict__ lam) {
+__device__ __forceinline__ void dc_order(int bid, int n, int level, int* __restrict__ iw,
+                                         const double* __restrict__ lamk,
+                                         const double* __restrict__ dsort,
+                                         double* __restrict__ lam) {
   __shared__ double w[kDcMaxN];
   const int t = threadIdx.x;
-  const int node = blockIdx.x;
+  const int node = bid;
   int lo, hi;
   dc_range(n, level, node, lo, hi);
   const int m = hi - lo;
@@ -650,6 +628,41 @@ __global__ __launch_bounds__(kDcThreads) void dc_order_kernel(int n, int level,
     iw[kPerm + lo + rank] = i;
     lam[lo + rank] = wi;
   }
+}
+
+// ---------------------------------------------------------------- merge: fused launches
+// Steps of a merge level that depend only on earlier launches share one
+// launch (each workgroup takes one step's block; the branch is uniform over
+// the workgroup).  After prepare: the secular roots (blocks [0, nodes sblocks))
+// and the staging of the child columns.  After those: the order of the node's
+// eigenvalues (one block per node), zhat, and the deflation rotations of the
+// staged columns.  The steps of one launch read nothing another writes.
+__global__ __launch_bounds__(kDcThreads) void dc_secular_stage_kernel(
+    int n, int level, int sblocks, int mmax, const double* __restrict__ dsort,
+    const double* __restrict__ zsort, const int* __restrict__ iw,
+    const double* __restrict__ rhoK, double* __restrict__ lamk, double* __restrict__ Dl,
+    const double* __restrict__ Z, double* __restrict__ Qs, int64_t ldz) {
+  const int nsec = (1 << level) * sblocks;
+  const int bid = (int)blockIdx.x;
+  if (bid < nsec)
+    dc_secular(bid, n, level, sblocks, dsort, zsort, iw, rhoK, lamk, Dl, ldz);
+  else
+    dc_stage(bid - nsec, n, level, mmax, iw, Z, Qs, ldz);
+}
+
+__global__ __launch_bounds__(kDcThreads) void dc_order_zhat_rotate_kernel(
+    int n, int level, int rblocks, int* __restrict__ iw, const double* __restrict__ lamk,
+    const double* __restrict__ dsort, double* __restrict__ lam, const double* __restrict__ zsort,
+    const double* __restrict__ rhoK, const double* __restrict__ Dl, double* __restrict__ zh,
+    const double* __restrict__ rw, double* __restrict__ Qs, int64_t ldz) {
+  const int nodes = 1 << level;
+  const int bid = (int)blockIdx.x;
+  if (bid < nodes)
+    dc_order(bid, n, level, iw, lamk, dsort, lam);
+  else if (bid < nodes + nodes * rblocks)
+    dc_zhat(bid - nodes, n, level, rblocks, dsort, zsort, iw, rhoK, Dl, zh, ldz);
+  else
+    dc_rotate(bid - nodes - nodes * rblocks, n, level, rblocks, iw, rw, Qs, ldz);
 }
 
 // ---------------------------------------------------------------- merge: scatter
@@ -696,15 +709,8 @@ void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64
   double* zsort = vec4 + n;
   double* lamk = vec4 + 2 * n;
   double* zh = vec4 + 3 * n;
-  hipLaunchKernelGGL(dc_sanitize_kernel, dim3(1), dim3(256), 0, s, n, d, const_cast<double*>(e),
-                     fail);
-  if (depth > 0) {
-    const int internal = (1 << depth) - 1;
-    hipLaunchKernelGGL(dc_tear_kernel, dim3(dc_blocks(internal, 64)), dim3(64), 0, s, n, depth, e,
-                       d);
-  }
-  hipLaunchKernelGGL(dc_leaf_kernel, dim3(1u << depth), dim3(kWave), 0, s, n, depth, d, e, lam, Z,
-                     ldz, fail);
+  hipLaunchKernelGGL(dc_leaf_kernel, dim3(1u << depth), dim3(kWave), 0, s, n, depth, d,
+                     const_cast<double*>(e), lam, Z, ldz, fail);
   LOBPCG_HIP(hipGetLastError());
   for (int level = depth - 1; level >= 0; --level) {
     const int nodes = 1 << level;
@@ -713,14 +719,10 @@ void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64
     const int sb = (int)dc_blocks(mmax, kDcThreads / kWave);
     hipLaunchKernelGGL(dc_prepare_kernel, dim3(nodes), dim3(kDcThreads), 0, s, n, level, e, lam,
                        Z, ldz, dsort, zsort, iw, rw, rhoK);
-    hipLaunchKernelGGL(dc_stage_kernel, dim3(nodes * mmax), dim3(kDcThreads), 0, s, n, level, mmax,
-                       iw, Z, Qs, ldz);
-    hipLaunchKernelGGL(dc_rotate_kernel, dim3(nodes * rb), dim3(kDcThreads), 0, s, n, level, rb, iw,
-                       rw, Qs, ldz);
-    hipLaunchKernelGGL(dc_secular_kernel, dim3(nodes * sb), dim3(kDcThreads), 0, s, n, level, sb,
-                       dsort, zsort, iw, rhoK, lamk, Dl, ldz);
-    hipLaunchKernelGGL(dc_zhat_kernel, dim3(nodes * rb), dim3(kDcThreads), 0, s, n, level, rb,
-                       dsort, zsort, iw, rhoK, Dl, zh, ldz);
+    hipLaunchKernelGGL(dc_secular_stage_kernel, dim3(nodes * (sb + mmax)), dim3(kDcThreads), 0, s,
+                       n, level, sb, mmax, dsort, zsort, iw, rhoK, lamk, Dl, Z, Qs, ldz);
+    hipLaunchKernelGGL(dc_order_zhat_rotate_kernel, dim3(nodes * (1 + 2 * rb)), dim3(kDcThreads), 0,
+                       s, n, level, rb, iw, lamk, dsort, lam, zsort, rhoK, Dl, zh, rw, Qs, ldz);
     hipLaunchKernelGGL(dc_vectors_kernel, dim3(nodes * mmax), dim3(kWave), 0, s, n, level, mmax,
                        iw, zh, Qs, Dl, G, ldz);
     LOBPCG_HIP(hipGetLastError());
@@ -738,8 +740,6 @@ void tridiag_dc(int n, double* d, const double* e, double* lam, double* Z, int64
       dims[node] = hi - lo;
     }
     small_dgemm_diag_batch(nodes, offs, dims, G, ldz, Dl, ldz, Y, ldz, s);
-    hipLaunchKernelGGL(dc_order_kernel, dim3(nodes), dim3(kDcThreads), 0, s, n, level, iw, lamk,
-                       dsort, lam);
     hipLaunchKernelGGL(dc_scatter_kernel, dim3(nodes * mmax), dim3(kDcThreads), 0, s, n, level,
                        mmax, iw, Y, Qs, Z, ldz);
     LOBPCG_HIP(hipGetLastError());

@@ -9,6 +9,7 @@ gamma_K = K u / (1 - K u), taken with a factor 2 of slack.
 
 import numpy as np
 import pytest
+import scipy.linalg
 import scipy.sparse as sp
 
 from oracle import lobpcg as L
@@ -416,6 +417,34 @@ def test_rr_step_flags_ill_conditioned(lib):
     got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), 3, 0, False,
                     L.Tolerances().tau_skip)
     assert got["flipped"] and got["cond"] > 1e5
+
+
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_rr_step_reports_a_nonfinite_projected_matrix(lib, where):
+    """A NaN in S^T A S reaches the tridiagonal eigensolver, which reports it
+    (the leaves holding one are solved as zero blocks, so the merges only see
+    finite values); the call fails with ERR_NONFINITE, and the next call on a
+    finite pencil is unaffected."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    rng = np.random.default_rng(9)
+    n, n_s, n_x = 400, 100, 30
+    A = P.laplacian_2d_dirichlet(20).to_scipy()
+    S = rng.standard_normal((n, n_s))
+    GA, GB = S.T @ (A @ S), S.T @ S
+    GA, GB = 0.5 * (GA + GA.T), 0.5 * (GB + GB.T)
+    bad = GA.copy()
+    i = {"first": 0, "middle": n_s // 2, "last": n_s - 1}[where]
+    bad[i, i] = np.nan
+    with pytest.raises(B.LobpcgError, match="non-finite"):
+        B.rr_step(torch.from_numpy(bad).cuda(), torch.from_numpy(GB).cuda(), n_x, 0, False,
+                  L.Tolerances().tau_skip)
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), n_x, 0, False,
+                    L.Tolerances().tau_skip)
+    lam = np.sort(scipy.linalg.eigh(GA, GB, eigvals_only=True))
+    th = got["theta"].cpu().numpy()[:n_s]
+    assert np.allclose(th, lam, rtol=1e-9, atol=1e-9 * np.abs(lam).max())
 
 
 @pytest.mark.parametrize("n_s", [1, 2, 31, 32, 33, 65, 100, 330, 512])
