@@ -203,9 +203,50 @@ constexpr int kNrot = 64, kOrd = 128, kSrc = kOrd + kDcMaxN, kRp = kSrc + kDcMax
               kRi = kRp + kDcMaxN, kPerm = kRi + kDcMaxN, kDcInts = kPerm + kDcMaxN;
 static_assert(kDcInts <= 4096, "int workspace");
 
+// Bit sets over a node's positions, 64 per word: the highest set position
+// below i (or -1), the lowest at or above from (or -1), the count below i.
+__device__ __forceinline__ int dc_prev_set(const unsigned long long* w, int i) {
+  int q = i >> 6;
+  unsigned long long b = w[q] & ((1ull << (i & 63)) - 1);
+  while (b == 0) {
+    if (--q < 0) return -1;
+    b = w[q];
+  }
+  return (q << 6) + 63 - __builtin_clzll(b);
+}
+
+__device__ __forceinline__ int dc_next_set(const unsigned long long* w, int nw, int from) {
+  int q = from >> 6;
+  if (q >= nw) return -1;
+  unsigned long long b = w[q] & (~0ull << (from & 63));
+  while (b == 0) {
+    if (++q >= nw) return -1;
+    b = w[q];
+  }
+  return (q << 6) + __builtin_ctzll(b);
+}
+
+__device__ __forceinline__ int dc_count_below(const unsigned long long* w, int i) {
+  int c = 0;
+  const int q = i >> 6;
+  for (int k = 0; k < q; ++k) c += __popcll(w[k]);
+  return c + __popcll(w[q] & ((1ull << (i & 63)) - 1));
+}
+
 // ---------------------------------------------------------------- merge: prepare
-// One workgroup per node: sorted d and z, deflation (sequential scan), the
-// order [kept ascending | deflated], the rotation list, rho of the kept set.
+// One workgroup per node: sorted d and z, deflation, the order [kept ascending
+// | deflated], the rotation list, rho of the kept set.
+// Close pairs are a scan over the survivors of the small-z test, each against
+// the previous survivor as the earlier steps of the scan left it.  A survivor
+// whose predecessor is unchanged is tested against the predecessor's own
+// values, so those tests run in parallel first (bit set cw); the sequential
+// pass then starts at each flagged survivor and follows the chain of rotations
+// from it while the next survivor is close to the rotated value: the same
+// tests on the same values, in the same order, as a scan over every survivor.
+// The order: when the kept values ascend in position order (checked), a kept
+// entry's rank is the number of kept entries before it and a deflated one's K
+// plus the deflated entries before it (counts of bits); otherwise the ranks
+// come from comparisons with every entry.
 __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
     int n, int level, const double* __restrict__ e, const double* __restrict__ lam,
     const double* __restrict__ Z, int64_t ldz, double* __restrict__ dsort,
@@ -216,7 +257,10 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
   __shared__ int K_s;
   __shared__ double rho_s, znorm_s;
   __shared__ double wmax[2][kDcThreads / kWave];
+  __shared__ unsigned long long sw[kDcMaxN / 64], cw[kDcMaxN / 64], kw[kDcMaxN / 64];
+  __shared__ int unsorted;
   const int t = threadIdx.x;
+  const int lane = t % kWave, wv = t / kWave;
   const int node = blockIdx.x;
   int lo, hi;
   dc_range(n, level, node, lo, hi);
@@ -282,53 +326,59 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
   // deflation of tiny rho |z_i|, in parallel
   for (int i = t; i < m; i += kDcThreads) defl[i] = (rho * fabs(zs[i]) <= tol) ? 1 : 0;
   __syncthreads();
+  const int nw = (m + 63) / 64;
+  for (int w = wv; w < nw; w += kDcThreads / kWave) {
+    const int i = 64 * w + lane;
+    const unsigned long long b = __ballot(i < m && !defl[i]);
+    if (lane == 0) sw[w] = b;
+  }
+  __syncthreads();
+  // |dt c s| <= tol (c^2 + s^2) is |dt c s| / (c^2 + s^2) <= tol without the
+  // square root and divisions (the rotation is formed only for a close pair)
+  for (int w = wv; w < nw; w += kDcThreads / kWave) {
+    const int i = 64 * w + lane;
+    bool close = false;
+    if (i < m && !defl[i]) {
+      const int p = dc_prev_set(sw, i);
+      if (p >= 0) {
+        const double di = ds[i], zi = zs[i], pd = ds[p], pz = zs[p];
+        close = fabs((di - pd) * zi * pz) <= tol * fma(zi, zi, pz * pz);
+      }
+    }
+    const unsigned long long b = __ballot(close);
+    if (lane == 0) cw[w] = b;
+  }
+  __syncthreads();
   if (t == 0) {
-    // close pairs, in order over the survivors: |dt c s| <= tol (c^2 + s^2) is
-    // |dt c s| / (c^2 + s^2) <= tol without the square root and divisions (a
-    // close pair is rare, the rotation is formed only then)
-    int nrot = 0, prev = -1;
-    double pd = 0.0, pz = 0.0;
-    // entries are read eight at a time (one LDS round trip per eight): handling
-    // entry i writes only entries i and prev < i, never a later one
-    for (int i8 = 0; i8 < m; i8 += 8) {
-      double dch[8], zch[8];
-      int fch[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = min(i8 + u, m - 1);
-        dch[u] = ds[q];
-        zch[u] = zs[q];
-        fch[u] = defl[q];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i8 + u;
-        if (i >= m) break;
-        const double di = dch[u], zi = zch[u];
-        const int dfi = fch[u];
-        if (dfi) continue;
-        if (prev >= 0 && fabs((di - pd) * zi * pz) <= tol * fma(zi, zi, pz * pz)) {
-          const double tau = hypot(zi, pz);
-          const double cc = zi / tau, ss = -pz / tau;
-          const double dnew = pd * ss * ss + di * cc * cc;
-          zs[i] = tau;
-          zs[prev] = 0.0;
-          ds[prev] = pd * cc * cc + di * ss * ss;
-          ds[i] = dnew;
-          defl[prev] = 1;
-          iw[kRp + lo + nrot] = prev;
-          iw[kRi + lo + nrot] = i;
-          rw[lo + nrot] = cc;
-          rw[kDcMaxN + lo + nrot] = ss;
-          ++nrot;
-          pd = dnew;
-          pz = tau;
-        } else {
-          pd = di;
-          pz = zi;
-        }
+    int nrot = 0;
+    int i = dc_next_set(cw, nw, 0);
+    while (i >= 0) {
+      int prev = dc_prev_set(sw, i);
+      double pd = ds[prev], pz = zs[prev];
+      for (;;) {
+        const double di = ds[i], zi = zs[i];
+        if (!(fabs((di - pd) * zi * pz) <= tol * fma(zi, zi, pz * pz))) break;
+        const double tau = hypot(zi, pz);
+        const double cc = zi / tau, ss = -pz / tau;
+        const double dnew = pd * ss * ss + di * cc * cc;
+        zs[i] = tau;
+        zs[prev] = 0.0;
+        ds[prev] = pd * cc * cc + di * ss * ss;
+        ds[i] = dnew;
+        defl[prev] = 1;
+        iw[kRp + lo + nrot] = prev;
+        iw[kRi + lo + nrot] = i;
+        rw[lo + nrot] = cc;
+        rw[kDcMaxN + lo + nrot] = ss;
+        ++nrot;
+        pd = dnew;
+        pz = tau;
         prev = i;
+        i = dc_next_set(sw, nw, i + 1);
+        if (i < 0) break;
       }
+      if (i < 0) break;
+      i = dc_next_set(cw, nw, i + 1);
     }
     iw[kNrot + node] = nrot;
   }
@@ -365,14 +415,34 @@ __global__ __launch_bounds__(kDcThreads) void dc_prepare_kernel(
   }
   __syncthreads();
   const int K = K_s;
+  for (int w = wv; w < nw; w += kDcThreads / kWave) {
+    const int i = 64 * w + lane;
+    const unsigned long long b = __ballot(i < m && !defl[i]);
+    if (lane == 0) kw[w] = b;
+  }
+  if (t == 0) unsorted = 0;
+  __syncthreads();
+  for (int i = t; i < m; i += kDcThreads)
+    if (!defl[i]) {
+      const int p = dc_prev_set(kw, i);
+      if (p >= 0 && ds[p] > ds[i]) unsorted = 1;
+    }
+  __syncthreads();
+  const bool ascending = unsorted == 0;
   for (int i = t; i < m; i += kDcThreads) {
     // kept: the kept entries before it in (value, index) order; deflated: K
-    // plus the deflated entries before it.  Eight entries' reads in flight per
-    // step and branch-free counts (one LDS round trip per eight entries).
+    // plus the deflated entries before it.  Without ascending kept values:
+    // eight entries' reads in flight per step and branch-free counts (one LDS
+    // round trip per eight entries).
     const double di = ds[i];
     const bool dfi = defl[i] != 0;
     int rank = 0;
     int j = 0;
+    if (ascending) {
+      const int kb = dc_count_below(kw, i);
+      rank = dfi ? i - kb : kb;
+      j = m;
+    }
     for (; j + 8 <= m; j += 8) {
       double dj[8];
       int fj[8];
