@@ -517,7 +517,9 @@ __device__ __forceinline__ void dc_rotate(int bid, int n, int level, int rblocks
 // ---------------------------------------------------------------- merge: secular roots
 // One wave per (node, root j < K), lanes sharing the sums over the kept set.
 // The root is located in the variable tau shifted to the nearer pole, by Newton
-// steps on -tau f(tau) safeguarded by the bracketing interval.
+// steps on -tau f(tau) safeguarded by the bracketing interval.  Each lane keeps
+// its share of d and z (entries lane, lane + 64, ...) in registers for the
+// whole iteration, so a step is arithmetic and wave sums only.
 // lamk[lo + j] = root j;  Dl[lo + i, lo + j] = d_i - root_j.
 __device__ __forceinline__ void dc_secular(int bid, int n, int level, int rblocks,
                                            const double* __restrict__ dsort,
@@ -536,12 +538,23 @@ __device__ __forceinline__ void dc_secular(int bid, int n, int level, int rblock
   const double rho = rhoK[node];
   const double* dd = dsort + lo;
   const double* zz = zsort + lo;
+  constexpr int kPer = kDcMaxN / kWave;
+  double dr[kPer], zr[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = lane + u * kWave;
+    dr[u] = i < K ? dd[i] : 0.0;
+    zr[u] = i < K ? zz[i] : 0.0;
+  }
   int o;
   double a, c;
   if (j < K - 1) {
     const double half = 0.5 * (dd[j + 1] - dd[j]);
+    const double dj = dd[j];
     double f = 0.0;
-    for (int i = lane; i < K; i += kWave) f += zz[i] * zz[i] / ((dd[i] - dd[j]) - half);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (lane + u * kWave < K) f += zr[u] * zr[u] / ((dr[u] - dj) - half);
     f = 1.0 + rho * dc_wave_sum(f);
     if (f >= 0.0) {
       o = j;
@@ -561,11 +574,13 @@ __device__ __forceinline__ void dc_secular(int bid, int n, int level, int rblock
   double tau = 0.5 * (a + c);
   for (int it = 0; it < kDcBisect; ++it) {
     double f = 0.0, fp = 0.0, fa = 0.0;
-    for (int i = lane; i < K; i += kWave) {
-      const double q = zz[i] / ((dd[i] - dor) - tau);
-      f = fma(zz[i], q, f);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (lane + u * kWave >= K) continue;
+      const double q = zr[u] / ((dr[u] - dor) - tau);
+      f = fma(zr[u], q, f);
       fp = fma(q, q, fp);
-      fa += fabs(zz[i] * q);
+      fa += fabs(zr[u] * q);
     }
     f = 1.0 + rho * dc_wave_sum(f);
     fp = rho * dc_wave_sum(fp);
@@ -590,7 +605,11 @@ __device__ __forceinline__ void dc_secular(int bid, int n, int level, int rblock
     tau = nt;
   }
   if (lane == 0) lamk[lo + j] = dor + tau;
-  for (int i = lane; i < K; i += kWave) Dl[(int64_t)(lo + j) * ldz + lo + i] = (dd[i] - dor) - tau;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = lane + u * kWave;
+    if (i < K) Dl[(int64_t)(lo + j) * ldz + lo + i] = (dr[u] - dor) - tau;
+  }
 }
 
 // ---------------------------------------------------------------- merge: zhat
