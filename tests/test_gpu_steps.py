@@ -597,6 +597,44 @@ def test_rr_step_full_size_with_clustered_spectrum(lib, n_s, use_ortho):
     assert np.allclose(C.T @ GA @ C, T, atol=1e-10 * scale)
 
 
+@pytest.mark.parametrize("n_s", [330, 512])
+def test_rr_step_near_degenerate_clusters(lib, n_s):
+    """The spectrum of a late projected matrix: the smallest 3D Laplacian
+    eigenvalues with their multiplicities (permutations of the 1D indices),
+    split at 1e-10 relative, beside spread values, in a random orthonormal
+    basis.  The divide and conquer then sees clusters of nearly equal poles
+    with tiny weights just above its deflation threshold (close-pair rotation
+    chains, roots hugging a pole).  The Ritz values must match the spectrum to
+    the eigensolver's backward error, and C must satisfy the output contract."""
+    torch = _torch()
+    from paper_1704_07458_amd import binding as B
+
+    N = 64
+    l1 = 4.0 * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2
+    L3 = np.sort((l1[:, None, None] + l1[None, :, None] + l1[None, None, :]).ravel())
+    rng = np.random.default_rng(n_s)
+    n_x = n_s // 3
+    lam = np.concatenate([L3[:n_x] * (1 + 1e-10 * rng.standard_normal(n_x)),
+                          rng.uniform(L3[n_x], 6.0, n_s - n_x)])
+    Q, _ = np.linalg.qr(rng.standard_normal((n_s, n_s)))
+    GA = (Q * lam) @ Q.T
+    GA = 0.5 * (GA + GA.T)
+    GB = np.eye(n_s)
+    tol = L.Tolerances()
+    got = B.rr_step(torch.from_numpy(GA).cuda(), torch.from_numpy(GB).cuda(), n_x, 0, True,
+                    tol.tau_skip)
+    th = got["theta"].cpu().numpy()[:n_s]
+    scale = np.abs(lam).max()
+    assert np.allclose(th, np.sort(lam), rtol=0, atol=1e-12 * scale)
+    Cx, Cp = got["Cx"].cpu().numpy(), got["Cp"].cpu().numpy()
+    C = np.hstack([Cx, Cp])
+    assert np.allclose(C.T @ C, np.eye(C.shape[1]), atol=1e-10)
+    T = np.zeros((C.shape[1],) * 2)
+    T[:n_x, :n_x] = np.diag(th[:n_x])
+    T[n_x:, n_x:] = got["theta_p"].cpu().numpy()
+    assert np.allclose(C.T @ GA @ C, T, atol=1e-10 * scale)
+
+
 @pytest.mark.parametrize("n_s", [2, 3, 17, 33, 63, 64, 65, 80, 81, 97, 100, 129, 330, 511, 512])
 def test_projected_eigensolver_backward_error(lib, n_s):
     """Rayleigh-Ritz on an orthonormal basis (G_B = I) with n_x = n_s returns the
